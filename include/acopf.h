@@ -1,0 +1,228 @@
+/*
+ * acopf.h -- C ABI of the MI355X (gfx950) ACOPF model-evaluation library.
+ *
+ * The library evaluates the polar power-balance ACOPF model at an
+ * interior-point iterate, the work an interior-point solver repeats every
+ * iteration (paper: OPFLOW section, compact statement min f(x) s.t. g(x) = 0,
+ * h- <= h(x) <= h+, x- <= x <= x+, evaluated on the GPU with the data kept
+ * resident there).  It computes, in FP64:
+ *   f       quadratic generator cost on MW:  sum_k c2 (B Pg)^2 + c1 B Pg + c0
+ *   grad_f  dense, length n (zeros outside the Pg block)
+ *   c       constraints [g^P (nb); g^Q (nb); h^f (nl); h^t (nl)]
+ *           g = bus injection - generation + load; h = squared apparent flow
+ *   J       values of dc/dx on the fixed CSR pattern of acopf_pattern
+ *   H       values of the lower triangle of sigma grad^2 f + sum lambda_r grad^2 c_r
+ *   u       vector-Jacobian product  w_f grad f + J' w_c
+ * Variables x = [theta (nb); v (nb); Pg (ng); Qg (ng)], n = 2 nb + 2 ng;
+ * constraints and multipliers in the order of c, m = 2 nb + 2 nl.
+ * Branch model: pi model, series admittance 1/(r + j x), charging b/2 at both
+ * ends, ideal transformer tap*exp(j shift) on the from side.  Per unit on
+ * base_mva; angles in radians.
+ *
+ * Pattern rule (structural, explicit zeros kept, parallel branches share one
+ * slot, columns strictly ascending in each row):
+ *   J row g^P_i: theta_j, v_j for j in {i} u N(i), then Pg_k of gens at bus i
+ *   J row g^Q_i: the same with Qg
+ *   J rows h^f_l, h^t_l: theta_a, theta_b, v_a, v_b with a < b its endpoints
+ *   H row theta_i: theta_j for j <= i in {i} u N(i)
+ *   H row v_i: theta_j for j in {i} u N(i), then v_j for j <= i
+ *   H row Pg_k: Pg_k;  H rows Qg_k: empty.
+ *
+ * Conventions for every call:
+ *   - returns 0 (ACOPF_OK) or a negative ACOPF_E* code; acopf_last_error()
+ *     returns a thread-local message for the last failure on this thread;
+ *   - no C++ exception crosses the ABI;
+ *   - "device" pointers are hipMalloc'd memory of the device the handle was
+ *     created on (e.g. torch tensor data pointers); "host" pointers are
+ *     ordinary CPU memory;
+ *   - evaluation calls are asynchronous: they enqueue work on `stream` and
+ *     return; results are valid once the stream is synchronised;
+ *   - NaN or Inf in x or the multipliers is not checked; it propagates;
+ *   - a handle may be used by one stream at a time (evaluations keep a small
+ *     per-handle scratch for the deterministic reduction of f).
+ * All results are deterministic: repeated calls, and the same instance
+ * evaluated alone or inside any batch, give bitwise identical values.
+ */
+#ifndef ACOPF_ABI_H_
+#define ACOPF_ABI_H_
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ACOPF_OK = 0,
+  ACOPF_EINVAL = -1,  /* bad argument, size or network data                */
+  ACOPF_ENOMEM = -2,  /* device or host allocation failed                   */
+  ACOPF_EHIP = -3,    /* HIP runtime error (message carries the HIP string) */
+  ACOPF_EBUDGET = -4, /* request exceeds a memory budget                    */
+  ACOPF_ESTATE = -5   /* handle in the wrong state (e.g. still referenced)   */
+};
+
+/* `what` bits for the fused and batched evaluations. */
+enum {
+  ACOPF_F = 1u,      /* objective value           */
+  ACOPF_GRADF = 2u,  /* objective gradient (n)    */
+  ACOPF_C = 4u,      /* constraint values (m)     */
+  ACOPF_J = 8u,      /* Jacobian values           */
+  ACOPF_H = 16u,     /* Lagrangian Hessian values */
+  ACOPF_ALL = 31u
+};
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* acopf_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int acopf_version(void);
+
+typedef struct acopf_net_s* acopf_net;
+typedef struct acopf_batch_s* acopf_batch;
+
+/* Network description.  HOST pointers, read during acopf_net_create and not
+ * kept; the caller keeps ownership.  Bus ids are 0-based.  Validation:
+ * nbus >= 1, nbranch >= 0, ngen >= 0, base_mva > 0, endpoints in range and
+ * distinct, not both r and x zero, tap > 0, generator buses in range,
+ * every value finite.  Parallel branches are allowed. */
+typedef struct {
+  int32_t nbus, nbranch, ngen;
+  double base_mva;                  /* the cost is on MW = base_mva * Pg   */
+  const int32_t* br_from;           /* [nbranch]                           */
+  const int32_t* br_to;             /* [nbranch]                           */
+  const double* br_r;               /* [nbranch] series resistance, pu     */
+  const double* br_x;               /* [nbranch] series reactance, pu      */
+  const double* br_b;               /* [nbranch] total charging, pu        */
+  const double* br_tap;             /* [nbranch] tap ratio (1 for lines)   */
+  const double* br_shift;           /* [nbranch] phase shift, rad          */
+  const double* bus_pd;             /* [nbus] active load, pu              */
+  const double* bus_qd;             /* [nbus] reactive load, pu            */
+  const double* bus_gs;             /* [nbus] shunt conductance at v = 1   */
+  const double* bus_bs;             /* [nbus] shunt susceptance at v = 1   */
+  const int32_t* gen_bus;           /* [ngen]                              */
+  const double* gen_c2;             /* [ngen] $/MW^2h                      */
+  const double* gen_c1;             /* [ngen] $/MWh                        */
+  const double* gen_c0;             /* [ngen] $/h                          */
+} acopf_net_desc;
+
+typedef struct {
+  int64_t n;         /* variables: 2 nbus + 2 ngen                         */
+  int64_t m;         /* constraints: 2 nbus + 2 (live branches)            */
+  int64_t nnz_jac;   /* Jacobian pattern entries                           */
+  int64_t nnz_hess;  /* lower-Hessian pattern entries                      */
+  int32_t nbus, nbranch, ngen;
+  int32_t outage;    /* removed branch of an N-1 net, -1 for a base net    */
+} acopf_dims;
+
+/* Create a network on the current HIP device: validates `desc`, derives the
+ * branch admittances, the bus adjacency and the CSR patterns on the host and
+ * uploads them.  Errors: EINVAL (validation, with the offending index in the
+ * message, or a bus whose rows exceed the per-tile capacity), ENOMEM, EHIP. */
+int acopf_net_create(const acopf_net_desc* desc, acopf_net* out);
+
+/* N-1 child of a base net (paper: SCOPFLOW section, contingency cases of the
+ * security-constrained problem): branch `branch` of `base` is removed
+ * entirely.  Its two flow rows disappear (m drops by 2; later flow rows shift
+ * down by one) and its Jacobian/Hessian slots vanish unless a parallel branch
+ * still joins the same buses.  x keeps the base layout.  The child shares the
+ * base's device network data (it adds only a few bytes of scratch for the
+ * reduction of f); `base` cannot be destroyed while children exist (ESTATE).
+ * Errors: EINVAL, ESTATE, ENOMEM. */
+int acopf_net_create_outage(acopf_net base, int32_t branch, acopf_net* out);
+
+/* Destroy a net.  ESTATE if a child net or a batch still references it. */
+int acopf_net_destroy(acopf_net net);
+
+int acopf_dims_get(acopf_net net, acopf_dims* out);
+
+/* CSR patterns of J (m rows) and of the lower Hessian (n rows), as defined
+ * above, copied into caller-owned HOST arrays of sizes m+1, nnz_jac, n+1,
+ * nnz_hess.  Any pointer may be NULL to skip that array. */
+int acopf_pattern(acopf_net net, int32_t* jac_rowptr, int32_t* jac_col,
+                  int32_t* hess_rowptr, int32_t* hess_col);
+
+/* Host-only form of acopf_pattern for a description (no device needed):
+ * fills *dims (may be NULL) and, where non-NULL, the four arrays.
+ * `outage` = -1 for the base network, else the branch to remove. */
+int acopf_pattern_host(const acopf_net_desc* desc, int32_t outage, acopf_dims* dims,
+                       int32_t* jac_rowptr, int32_t* jac_col,
+                       int32_t* hess_rowptr, int32_t* hess_col);
+
+/* f (1 value), grad_f (n) and c (m) at x (n); DEVICE pointers.  Any output
+ * may be NULL to skip it (x may not). */
+int acopf_eval_f_g(acopf_net net, const double* x, double* f, double* grad_f,
+                   double* c, hipStream_t stream);
+
+/* Jacobian values (nnz_jac, pattern order) at x; DEVICE pointers. */
+int acopf_eval_jac(acopf_net net, const double* x, double* jac_val, hipStream_t stream);
+
+/* Lower Lagrangian-Hessian values (nnz_hess) of sigma f + lambda'c at x;
+ * lambda has m entries in the order of c; DEVICE pointers, sigma by value. */
+int acopf_eval_hess(acopf_net net, const double* x, double sigma, const double* lambda,
+                    double* hess_val, hipStream_t stream);
+
+/* u = w_f grad f(x) + J(x)' w_c, without forming J; w_c has m entries;
+ * u has n.  DEVICE pointers.  With (w_f, w_c) = (sigma, lambda) this is the
+ * gradient of the Lagrangian. */
+int acopf_vjp(acopf_net net, const double* x, double w_f, const double* w_c, double* u,
+              hipStream_t stream);
+
+/* Everything at once in a single launch: the outputs selected by `what`
+ * (ACOPF_* bits; the matching pointer must be non-NULL).  lambda is needed
+ * only for ACOPF_H. */
+int acopf_eval_all(acopf_net net, const double* x, double sigma, const double* lambda,
+                   double* f, double* grad_f, double* c, double* jac_val, double* hess_val,
+                   unsigned what, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched evaluation (paper: SCOPFLOW and SOPFLOW sections -- many
+ * contingency or scenario subproblems, each evaluated independently; the
+ * embarrassingly parallel structure).  Instance k uses nets[k]; its data lives
+ * in packed DEVICE buffers at the offsets returned by acopf_batch_offsets:
+ * x at x_off[k] (length n_k), lambda and c at c_off[k] (m_k), jac_val at
+ * j_off[k] (nnz_jac_k), hess_val at h_off[k] (nnz_hess_k), grad_f and u at
+ * x_off[k]; sigma, f and w_f are arrays of `count`.  The whole batch runs as
+ * one persistent kernel launch replayed from a HIP graph.
+ * ---------------------------------------------------------------------- */
+
+/* Tile/schedule configuration chosen by the autotuner (or fixed by hand). */
+typedef struct {
+  int32_t tile_be;    /* branch ends per bus tile: 128, 256 or 512        */
+  int32_t grid_mult;  /* workgroups per CU for the persistent grid; 0 = one
+                         workgroup per tile (no persistence)               */
+  int32_t xcd_group;  /* 1 = map each instance's tiles onto one XCD        */
+  int32_t no_graph;   /* 1 = launch directly instead of replaying a graph */
+} acopf_sched;
+
+/* Build a batch over `count` nets (they cannot be destroyed while the batch
+ * exists): per-instance offsets, the XCD-aware tile list and the device
+ * descriptor table.  `sched` may be NULL for the default schedule
+ * {256, 4, 1, 0}.  Errors: EINVAL (also when a bus exceeds the tile
+ * capacity of the schedule), ENOMEM, EHIP. */
+int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* sched,
+                       acopf_batch* out);
+int acopf_batch_destroy(acopf_batch batch);
+
+/* Offsets into the packed buffers (HOST arrays of count+1 entries each; the
+ * last entry is the total length).  Any pointer may be NULL. */
+int acopf_batch_offsets(acopf_batch batch, int64_t* x_off, int64_t* c_off, int64_t* j_off,
+                        int64_t* h_off);
+
+/* Evaluate the outputs selected by `what` for every instance in one launch
+ * (DEVICE pointers; an output not selected may be NULL).  The first call with
+ * a given set of buffers captures a HIP graph; later calls with the same
+ * buffers replay it. */
+int acopf_batch_eval(acopf_batch batch, const double* x, const double* sigma,
+                     const double* lambda, double* f, double* grad_f, double* c,
+                     double* jac_val, double* hess_val, unsigned what, hipStream_t stream);
+
+/* Batched VJP: u_k = w_f[k] grad f_k + J_k' w_c_k for every instance. */
+int acopf_batch_vjp(acopf_batch batch, const double* x, const double* w_f, const double* w_c,
+                    double* u, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ACOPF_ABI_H_ */

@@ -1,0 +1,327 @@
+// Batched evaluation: many instances (N-1 contingencies, scenarios, served
+// requests) in one kernel launch.  The batch owns
+//   - per-instance offsets into the caller's packed buffers,
+//   - a device descriptor table (one InstOff per instance),
+//   - a tile list over all instances, ordered so that each instance's tiles
+//     land on one XCD (workgroup b runs on XCD b mod 8, so tiles at list
+//     positions p = q (mod 8) form XCD queue q) and instances are spread over
+//     the eight queues largest-first,
+//   - the f-reduction scratch, and
+//   - a small cache of instantiated HIP graphs keyed by the buffer set.
+#include <algorithm>
+#include <array>
+#include <cstring>
+#include <list>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "acopf.h"
+#include "acopf_host.h"
+
+namespace acopf {
+constexpr int kXcds = 8;
+constexpr size_t kGraphCache = 8;
+
+struct GraphKey {
+  unsigned variant;
+  std::array<const void*, 11> ptrs;
+  bool operator==(const GraphKey& o) const { return variant == o.variant && ptrs == o.ptrs; }
+};
+
+}  // namespace acopf
+
+struct acopf_batch_s {
+  std::vector<acopf_net> nets;
+  int32_t count = 0;
+  acopf_sched sched{};
+  std::vector<int64_t> xo, co, jo, ho;
+  int device = 0;
+  void* mem = nullptr;
+  acopf::InstOff* d_table = nullptr;
+  acopf::Tile* d_tiles = nullptr;
+  double* d_fpart = nullptr;
+  uint32_t* d_ticket = nullptr;
+  int ntiles = 0;
+  int grid = 0;  // 0: one workgroup per tile
+  hipStream_t cap_stream = nullptr;
+  std::list<std::pair<acopf::GraphKey, hipGraphExec_t>> graphs;  // most recent first
+};
+
+using namespace acopf;
+
+namespace {
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+int cu_count(int device, int* cus) {
+  hipDeviceProp_t p;
+  hipError_t e = hipGetDeviceProperties(&p, device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  *cus = p.multiProcessorCount;
+  return ACOPF_OK;
+}
+
+void free_batch(acopf_batch_s* b) {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(b->device);
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  b->graphs.clear();
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->mem) (void)hipFree(b->mem);
+  (void)hipSetDevice(cur);
+  for (acopf_net n : b->nets) n->refs.fetch_sub(1);
+  delete b;
+}
+
+int run_batch(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStream_t stream) {
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != b->device) return fail(ACOPF_EINVAL, "batch lives on another device");
+  const int tile_be = b->sched.tile_be;
+  const InstOff none{};
+  if (b->sched.no_graph) {
+    e = launch_eval(variant, tile_be, bufs, b->d_table, none, b->d_tiles, b->ntiles, b->grid, stream);
+    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+    return ACOPF_OK;
+  }
+  GraphKey key{variant,
+               {bufs.x, bufs.lam, bufs.wc, bufs.sigma, bufs.wf, bufs.f, bufs.gradf, bufs.c,
+                bufs.jac, bufs.hess, bufs.u}};
+  hipGraphExec_t exec = nullptr;
+  for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
+    if (it->first == key) {
+      exec = it->second;
+      b->graphs.splice(b->graphs.begin(), b->graphs, it);
+      break;
+    }
+  }
+  if (!exec) {
+    if (!b->cap_stream) {
+      e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    }
+    e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le =
+        launch_eval(variant, tile_be, bufs, b->d_table, none, b->d_tiles, b->ntiles, b->grid, b->cap_stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(b->cap_stream, &graph);
+    if (le != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(le, "batch kernel capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    b->graphs.emplace_front(key, exec);
+    if (b->graphs.size() > kGraphCache) {
+      (void)hipGraphExecDestroy(b->graphs.back().second);
+      b->graphs.pop_back();
+    }
+  }
+  e = hipGraphLaunch(exec, stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return ACOPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* sched,
+                       acopf_batch* out) {
+  if (!out) return fail(ACOPF_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!nets || count < 1) return fail(ACOPF_EINVAL, "need at least one net");
+  acopf_sched s{kDefaultTileBe, 4, 1, 0};
+  if (sched) s = *sched;
+  TileCaps caps;
+  if (!caps_for(s.tile_be, &caps)) return fail(ACOPF_EINVAL, "tile_be must be 64, 128 or 256");
+  if (s.grid_mult < 0 || s.grid_mult > 64) return fail(ACOPF_EINVAL, "grid_mult must be in [0, 64]");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  for (int k = 0; k < count; ++k) {
+    if (!nets[k]) return fail(ACOPF_EINVAL, "null net at index " + std::to_string(k));
+    if (nets[k]->base->device != dev)
+      return fail(ACOPF_EINVAL, "net " + std::to_string(k) + " lives on another device");
+  }
+  acopf_batch_s* b = nullptr;
+  try {
+    b = new acopf_batch_s();
+    b->nets.assign(nets, nets + count);
+    for (acopf_net n : b->nets) n->refs.fetch_add(1);
+    b->count = count;
+    b->sched = s;
+    b->device = dev;
+    b->xo.assign(count + 1, 0);
+    b->co.assign(count + 1, 0);
+    b->jo.assign(count + 1, 0);
+    b->ho.assign(count + 1, 0);
+    std::vector<int32_t> fpo(count + 1, 0);
+    for (int k = 0; k < count; ++k) {
+      const acopf_dims& d = nets[k]->dims;
+      b->xo[k + 1] = b->xo[k] + d.n;
+      b->co[k + 1] = b->co[k] + d.m;
+      b->jo[k + 1] = b->jo[k] + d.nnz_jac;
+      b->ho[k + 1] = b->ho[k] + d.nnz_hess;
+      fpo[k + 1] = fpo[k] + nets[k]->base->topo.nchunks;
+    }
+    // per-base tile lists for this schedule (outage children share their base's)
+    std::map<const Base*, std::vector<Tile>> per_base;
+    for (int k = 0; k < count; ++k) {
+      const Base* B = nets[k]->base.get();
+      if (per_base.count(B)) continue;
+      std::vector<Tile> t;
+      int counts[3];
+      int rc = make_tiles(B->topo, s.tile_be, &t, counts);
+      if (rc) {
+        free_batch(b);
+        return rc;
+      }
+      per_base.emplace(B, std::move(t));
+    }
+    // XCD queues, largest instances first (LPT on tile counts)
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    auto ntile = [&](int k) { return int(per_base[nets[k]->base.get()].size()); };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return ntile(a) > ntile(c); });
+    std::vector<std::vector<Tile>> queue(s.xcd_group ? kXcds : 1);
+    std::vector<int64_t> load(queue.size(), 0);
+    for (int k : order) {
+      const size_t qi = std::min_element(load.begin(), load.end()) - load.begin();
+      for (Tile t : per_base[nets[k]->base.get()]) {
+        t.inst = k;
+        queue[qi].push_back(t);
+      }
+      load[qi] += ntile(k);
+    }
+    std::vector<Tile> tiles;
+    size_t total = 0;
+    for (auto& q : queue) total += q.size();
+    tiles.reserve(total);
+    std::vector<size_t> pos(queue.size(), 0);
+    while (tiles.size() < total) {
+      for (size_t qi = 0; qi < queue.size(); ++qi)
+        if (pos[qi] < queue[qi].size()) tiles.push_back(queue[qi][pos[qi]++]);
+    }
+    b->ntiles = int(tiles.size());
+    int cus = 256;
+    int rc = cu_count(dev, &cus);
+    if (rc) {
+      free_batch(b);
+      return rc;
+    }
+    b->grid = s.grid_mult > 0 ? std::min(b->ntiles, s.grid_mult * cus) : 0;
+    // device table, tiles, scratch
+    std::vector<InstOff> table(count);
+    for (int k = 0; k < count; ++k) {
+      InstOff I = net_inst(nets[k]);
+      I.xo = b->xo[k];
+      I.co = b->co[k];
+      I.jo = b->jo[k];
+      I.ho = b->ho[k];
+      I.k = k;
+      I.fpo = fpo[k];
+      table[k] = I;
+    }
+    const size_t s_table = align_up(table.size() * sizeof(InstOff));
+    const size_t s_tiles = align_up(tiles.size() * sizeof(Tile));
+    const size_t s_fpart = align_up(size_t(fpo[count]) * sizeof(double));
+    const size_t s_ticket = align_up(size_t(count) * sizeof(uint32_t));
+    e = hipMalloc(&b->mem, s_table + s_tiles + s_fpart + s_ticket);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      b->mem = nullptr;
+      free_batch(b);
+      return fail(ACOPF_ENOMEM, std::string("hipMalloc of batch tables: ") + hipGetErrorString(e));
+    }
+    char* base = static_cast<char*>(b->mem);
+    b->d_table = reinterpret_cast<InstOff*>(base);
+    b->d_tiles = reinterpret_cast<Tile*>(base + s_table);
+    b->d_fpart = reinterpret_cast<double*>(base + s_table + s_tiles);
+    b->d_ticket = reinterpret_cast<uint32_t*>(base + s_table + s_tiles + s_fpart);
+    e = hipMemcpy(b->d_table, table.data(), table.size() * sizeof(InstOff), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b->d_fpart, 0, s_fpart + s_ticket);
+    if (e != hipSuccess) {
+      free_batch(b);
+      return hip_fail(e, "batch table upload");
+    }
+    *out = b;
+    t_err.clear();
+    return ACOPF_OK;
+  } catch (const std::bad_alloc&) {
+    if (b) free_batch(b);
+    return fail(ACOPF_ENOMEM, "host allocation failed");
+  }
+}
+
+int acopf_batch_destroy(acopf_batch batch) {
+  if (!batch) return ACOPF_OK;
+  free_batch(batch);
+  return ACOPF_OK;
+}
+
+int acopf_batch_offsets(acopf_batch b, int64_t* x_off, int64_t* c_off, int64_t* j_off,
+                        int64_t* h_off) {
+  if (!b) return fail(ACOPF_EINVAL, "null batch");
+  const size_t n = (b->count + 1) * sizeof(int64_t);
+  if (x_off) std::memcpy(x_off, b->xo.data(), n);
+  if (c_off) std::memcpy(c_off, b->co.data(), n);
+  if (j_off) std::memcpy(j_off, b->jo.data(), n);
+  if (h_off) std::memcpy(h_off, b->ho.data(), n);
+  return ACOPF_OK;
+}
+
+int acopf_batch_eval(acopf_batch b, const double* x, const double* sigma, const double* lambda,
+                     double* f, double* grad_f, double* c, double* jac_val, double* hess_val,
+                     unsigned what, hipStream_t stream) {
+  if (!b || !x) return fail(ACOPF_EINVAL, "null batch or x");
+  if (what & ~unsigned(ACOPF_ALL)) return fail(ACOPF_EINVAL, "unknown bits in what");
+  if (((what & ACOPF_F) && !f) || ((what & ACOPF_GRADF) && !grad_f) || ((what & ACOPF_C) && !c) ||
+      ((what & ACOPF_J) && !jac_val) ||
+      ((what & ACOPF_H) && (!hess_val || !lambda || !sigma)))
+    return fail(ACOPF_EINVAL, "a selected output (or lambda/sigma for ACOPF_H) is null");
+  if (!what) return ACOPF_OK;
+  Bufs bufs{};
+  bufs.x = x;
+  bufs.lam = (what & ACOPF_H) ? lambda : nullptr;
+  bufs.sigma = (what & ACOPF_H) ? sigma : nullptr;
+  bufs.f = (what & ACOPF_F) ? f : nullptr;
+  bufs.gradf = (what & ACOPF_GRADF) ? grad_f : nullptr;
+  bufs.c = (what & ACOPF_C) ? c : nullptr;
+  bufs.jac = (what & ACOPF_J) ? jac_val : nullptr;
+  bufs.hess = (what & ACOPF_H) ? hess_val : nullptr;
+  bufs.fpart = b->d_fpart;
+  bufs.ticket = b->d_ticket;
+  unsigned variant = K_ALL;
+  if ((what & ~unsigned(ACOPF_F | ACOPF_GRADF | ACOPF_C)) == 0)
+    variant = K_FG;
+  else if (what == ACOPF_J)
+    variant = K_J;
+  else if (what == ACOPF_H)
+    variant = K_H;
+  return run_batch(b, variant, bufs, stream);
+}
+
+int acopf_batch_vjp(acopf_batch b, const double* x, const double* w_f, const double* w_c,
+                    double* u, hipStream_t stream) {
+  if (!b || !x || !w_f || !w_c || !u) return fail(ACOPF_EINVAL, "null argument");
+  Bufs bufs{};
+  bufs.x = x;
+  bufs.wf = w_f;
+  bufs.wc = w_c;
+  bufs.u = u;
+  bufs.fpart = b->d_fpart;
+  bufs.ticket = b->d_ticket;
+  return run_batch(b, K_VJP, bufs, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Host-side objects behind the C ABI handles.
+#pragma once
+
+#include <atomic>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "acopf.h"
+#include "acopf_internal.h"
+
+namespace acopf {
+
+// Host copy of a base network and everything derived from it.
+struct Topology {
+  int32_t nb = 0, nl = 0, ng = 0, nchunks = 1;
+  double base = 100.0;
+  std::vector<int2> ft;
+  std::vector<BranchY> y;
+  std::vector<double4> bus;
+  std::vector<int32_t> gen_bus;
+  std::vector<double> c2, c1, c0;
+  std::vector<int32_t> be_ptr, be;
+  std::vector<int2> acnt;
+  std::vector<int4> rows;
+  std::vector<int32_t> gen_ptr, gen_list;
+  int64_t nnz_jac = 0, nnz_hess = 0;
+  int32_t jflow = 0, hpg = 0;
+};
+
+// A base network resident on one device; shared by its outage children.
+struct Base {
+  Topology topo;
+  int device = 0;
+  void* mem = nullptr;
+  size_t bytes = 0;
+  NetDev* d_net = nullptr;
+  Tile* d_tiles = nullptr;           // plain-path tiles [branch][bus][gen]
+  std::vector<Tile> plain_tiles;
+  int plain_counts[3] = {0, 0, 0};
+  ~Base();
+};
+
+}  // namespace acopf
+
+struct acopf_net_s {
+  std::shared_ptr<acopf::Base> base;
+  acopf_net_s* parent = nullptr;
+  int32_t out_l = -1, out_p = -1, out_q = -1, out_rm = 0;
+  acopf_dims dims{};
+  void* scratch = nullptr;           // f partials + ticket of the plain path
+  double* d_fpart = nullptr;
+  uint32_t* d_ticket = nullptr;
+  std::atomic<int> refs{0};          // outage children and batches using this net
+};
+
+namespace acopf {
+
+extern thread_local std::string t_err;
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+int build_topology(const acopf_net_desc* d, Topology* T);
+int outage_info(const Topology& T, int32_t l, int32_t* p, int32_t* q, int32_t* rm);
+void fill_dims(const Topology& T, int32_t outage, int32_t rm, acopf_dims* d);
+void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,
+                   std::vector<int32_t>* jc, std::vector<int32_t>* hp, std::vector<int32_t>* hc);
+int make_tiles(const Topology& T, int tile_be, std::vector<Tile>* out, int counts[3]);
+int upload_base(Base* B);
+int net_init_scratch(acopf_net_s* net);
+InstOff net_inst(const acopf_net_s* net);
+int check_device(const acopf_net_s* net);
+
+}  // namespace acopf

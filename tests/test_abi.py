@@ -1,0 +1,111 @@
+"""The C-ABI library on the host: it loads, exports every function the header
+declares, and its host-side pattern builder agrees bit for bit with the
+oracle's structural rule (base nets and N-1 outages).  No GPU needed."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2203_10587_amd import acopf as A
+from paper_2203_10587_amd import synth as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "acopf.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(acopf_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    names = header_functions()
+    assert len(names) >= 18
+    L = A.lib()
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in A._SIGS, f"binding lacks {n}"
+    assert L.acopf_version() >= 10000
+
+
+def _grids():
+    yield "ring9", S.config0(0)[0]
+    yield "rand30", S.random_grid(30, 50, 11, seed=3, parallel=3)
+    yield "star40", S.random_grid(40, 45, 6, seed=8, star=True, parallel=2)
+    yield "rgg800", S.rgg_grid(800, 1040, seed=2)
+    yield "nogen", S.random_grid(12, 15, 0, seed=1)
+    yield "isolated", S.Grid(**{**S.random_grid(6, 5, 2, seed=4).__dict__, "nbus": 8,
+                                "bus_pd": np.zeros(8), "bus_qd": np.zeros(8),
+                                "bus_gs": np.zeros(8), "bus_bs": np.zeros(8)})
+
+
+@pytest.mark.parametrize("name,g", list(_grids()))
+def test_host_pattern_bit_exact(name, g):
+    dims, jp, jc, hp, hc = A.acopf_pattern_host(g)
+    ojp, ojc, ohp, ohc = O.pattern(g)
+    np.testing.assert_array_equal(jp, ojp)
+    np.testing.assert_array_equal(jc, ojc)
+    np.testing.assert_array_equal(hp, ohp)
+    np.testing.assert_array_equal(hc, ohc)
+    assert (dims.n, dims.m) == (g.n, g.m)
+    assert dims.outage == -1
+
+
+@pytest.mark.parametrize("name,g", [x for x in _grids() if x[1].nbranch > 0])
+def test_host_pattern_bit_exact_outages(name, g):
+    rng = np.random.default_rng(0)
+    picks = rng.choice(g.nbranch, min(g.nbranch, 12), replace=False)
+    # include every parallel branch: the slot must survive their removal
+    pairs = {}
+    for l in range(g.nbranch):
+        pairs.setdefault(frozenset((int(g.br_from[l]), int(g.br_to[l]))), []).append(l)
+    par = [l for ls in pairs.values() if len(ls) > 1 for l in ls]
+    for l in sorted(set(picks.tolist()) | set(par)):
+        dims, jp, jc, hp, hc = A.acopf_pattern_host(g, int(l))
+        g2 = S.remove_branch(g, int(l))
+        ojp, ojc, ohp, ohc = O.pattern(g2)
+        np.testing.assert_array_equal(jp, ojp)
+        np.testing.assert_array_equal(jc, ojc)
+        np.testing.assert_array_equal(hp, ohp)
+        np.testing.assert_array_equal(hc, ohc)
+        assert (dims.m, dims.nbranch, dims.outage) == (g2.m, g2.nbranch, l)
+
+
+def _bad(g, **kw):
+    return S.Grid(**{**g.__dict__, **kw})
+
+
+@pytest.mark.parametrize("mut,msg", [
+    (lambda g: _bad(g, br_to=np.where(np.arange(g.nbranch) == 2, g.br_from, g.br_to)), "from == to"),
+    (lambda g: _bad(g, br_to=np.where(np.arange(g.nbranch) == 1, 99, g.br_to)), "out of range"),
+    (lambda g: _bad(g, br_r=np.where(np.arange(g.nbranch) == 0, 0.0, g.br_r),
+                    br_x=np.where(np.arange(g.nbranch) == 0, 0.0, g.br_x)), "zero impedance"),
+    (lambda g: _bad(g, br_tap=np.where(np.arange(g.nbranch) == 3, 0.0, g.br_tap)), "tap"),
+    (lambda g: _bad(g, bus_pd=np.where(np.arange(g.nbus) == 3, np.nan, g.bus_pd)), "non-finite"),
+    (lambda g: _bad(g, gen_bus=np.array([0, 1, 12], np.int32)), "bus out of range"),
+    (lambda g: _bad(g, base_mva=0.0), "base_mva"),
+])
+def test_validation_errors(mut, msg):
+    g = mut(S.config0(0)[0])
+    with pytest.raises(A.AcopfError) as ei:
+        A.acopf_pattern_host(g)
+    assert ei.value.code == A.ACOPF_EINVAL
+    assert msg in str(ei.value)
+
+
+def test_outage_index_validation():
+    g = S.config0(0)[0]
+    for bad in (-2, 12, 100):
+        with pytest.raises(A.AcopfError):
+            A.acopf_pattern_host(g, bad)
+
+
+def test_null_arguments_return_einval():
+    L = A.lib()
+    assert L.acopf_net_create(None, None) == A.ACOPF_EINVAL
+    assert L.acopf_eval_f_g(None, None, None, None, None, None) == A.ACOPF_EINVAL
+    assert L.acopf_batch_create(None, 0, None, C.byref(C.c_void_p())) == A.ACOPF_EINVAL
+    assert L.acopf_last_error()
