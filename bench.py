@@ -1,0 +1,312 @@
+"""Benchmark: ACOPF model evaluation (f, g, grad f, J, H in FP64) on one GPU.
+
+Default workload: the batched N-1 security set -- a 2,000-bus / 3,000-branch
+grid with 1,000 single-branch outages, each with its own iterate and
+multipliers, evaluated in one persistent kernel launch replayed from a HIP
+graph.  One step = one full evaluation of every instance.  Reported beside
+it: the plain path (the same kernels, one instance per launch), per-step
+latency percentiles, the roofline of the batched kernel, and the CPU
+oracle timed on a bounded sample on this host.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--workload c2|c1|c3]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "bus-evals/sec for f,g,∇f,J,H (batched vs plain, FP64); p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2203_10587_amd/csrc/acopf_kernels.hip",
+                  "paper_2203_10587_amd/csrc/acopf_internal.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+# ---------------------------------------------------------------------------
+# workloads
+
+
+def workload_c2():
+    from paper_2203_10587_amd import synth as S
+    os_ = S.config2(0)
+    return {"name": "n1_security_2000bus_x1000", "base": os_.base, "outages": os_.outages,
+            "iterates": os_.iterates, "kind": "outage"}
+
+
+def workload_c1():
+    from paper_2203_10587_amd import synth as S
+    g, it = S.config1(0)
+    return {"name": "single_10000bus", "grids": [g], "iterates": [it], "kind": "grids"}
+
+
+def workload_c3():
+    from paper_2203_10587_amd import synth as S
+    inst = S.config3(0)
+    return {"name": "uneven_scenarios_x512", "grids": [g for _, g, _ in inst],
+            "iterates": [it for _, _, it in inst], "kind": "grids"}
+
+
+def instance_grid(w, k):
+    from paper_2203_10587_amd import synth as S
+    if w["kind"] == "outage":
+        return S.remove_branch(w["base"], int(w["outages"][k]))
+    return w["grids"][k]
+
+
+def count(w):
+    return len(w["iterates"])
+
+
+def algorithmic_bytes(w):
+    """Bytes the method must move per full evaluation of the batch: inputs
+    x (8n), lambda (8m), sigma (8); outputs 8 (1 + n + m + nnzJ + nnzH); the
+    network primitives (56 B per branch, 32 B per bus, 28 B per generator)
+    counted once per distinct network."""
+    from paper_2203_10587_amd import acopf as A
+    tot = 0
+    nets = set()
+    for k in range(count(w)):
+        g = w["base"] if w["kind"] == "outage" else w["grids"][k]
+        d, *_ = A.acopf_pattern_host(g, int(w["outages"][k]) if w["kind"] == "outage" else -1)
+        tot += 8 * d.n + 8 * d.m + 8 + 8 * (1 + d.n + d.m + d.nnz_jac + d.nnz_hess)
+        key = id(g)
+        if key not in nets:
+            nets.add(key)
+            tot += 56 * g.nbranch + 32 * g.nbus + 28 * g.ngen
+    return tot
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands, single thread, bounded sample
+
+
+def cpu_baseline(w, budget_s=15.0):
+    import oracle as O
+    prepared = []
+    k = 0
+    t_eval = 0.0
+    buses = 0
+    n_inst = count(w)
+    order = np.random.default_rng(0).permutation(n_inst)
+    while k < n_inst and (t_eval < budget_s or k < 2):
+        idx = int(order[k])
+        g = instance_grid(w, idx)
+        it = w["iterates"][idx]
+        mdl = O.prepare(g)                      # Y_bus and patterns: not timed
+        t0 = time.perf_counter()
+        O.evaluate(mdl, it.x, it.sigma, it.lam)
+        t_eval += time.perf_counter() - t0
+        buses += g.nbus
+        k += 1
+        prepared.append(idx)
+    return {"value": buses / t_eval, "unit": "bus-evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} of {n_inst} instances of {w['name']}, full f, grad f, c, J, H "
+                      f"(NumPy/SciPy FP64, one thread; Y_bus and pattern build untimed), "
+                      f"{t_eval:.1f} s of evaluation"}
+
+
+# ---------------------------------------------------------------------------
+
+
+def load_traffic(kernel_name, workload):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        doc = json.load(open(p))
+        ent = doc.get(workload)
+        if not ent or ent.get("kernel_hash") != kernel_hash():
+            return None
+        return float(ent["fetch_bytes"]) + float(ent["write_bytes"])
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tile-be", type=int, default=0)
+    ap.add_argument("--grid-mult", type=int, default=-1)
+    ap.add_argument("--xcd", type=int, default=-1)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB five times (the "
+                         "reference kernel for scaling HBM traffic counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / 5
+        print(json.dumps({"copy_bytes_each_way": n * 8, "ms": ms,
+                          "GBps_read_plus_write": 2 * n * 8 / ms / 1e6}), flush=True)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(instances would shard across GPUs with no exchange); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    t0 = time.time()
+    w = {"c1": workload_c1, "c2": workload_c2, "c3": workload_c3}[args.workload]()
+    log(f"[bench] workload {w['name']}: {count(w)} instances, generated in {time.time() - t0:.1f}s")
+    cpu = None if args.no_cpu else cpu_baseline(w)
+    if cpu:
+        log(f"[bench] cpu oracle: {cpu['value']:.3e} bus-evals/s ({cpu['sample']})")
+
+    import torch
+    from paper_2203_10587_amd import acopf as A
+    from paper_2203_10587_amd import tune
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    K = count(w)
+    if w["kind"] == "outage":
+        base = A.acopf_net_create(w["base"])
+        nets = [A.acopf_net_create_outage(base, int(l)) for l in w["outages"]]
+    else:
+        nets = [A.acopf_net_create(g) for g in w["grids"]]
+    sched = tune.lookup_or_default(nets)
+    if args.tile_be:
+        sched["tile_be"] = args.tile_be
+    if args.grid_mult >= 0:
+        sched["grid_mult"] = args.grid_mult
+    if args.xcd >= 0:
+        sched["xcd_group"] = args.xcd
+    if args.no_graph:
+        sched["no_graph"] = 1
+    batch = A.acopf_batch_create(nets, **sched)
+    nx, nc = int(batch.x_off[-1]), int(batch.c_off[-1])
+    nj, nh = int(batch.j_off[-1]), int(batch.h_off[-1])
+    x = torch.empty(nx, dtype=torch.float64)
+    lam = torch.empty(nc, dtype=torch.float64)
+    for k, it in enumerate(w["iterates"]):
+        x[batch.x_off[k]:batch.x_off[k + 1]] = torch.from_numpy(it.x)
+        lam[batch.c_off[k]:batch.c_off[k + 1]] = torch.from_numpy(it.lam)
+    x, lam = x.to(dev), lam.to(dev)
+    sigma = torch.tensor([it.sigma for it in w["iterates"]], dtype=torch.float64, device=dev)
+    f = torch.empty(K, dtype=torch.float64, device=dev)
+    gf = torch.empty(nx, dtype=torch.float64, device=dev)
+    c = torch.empty(nc, dtype=torch.float64, device=dev)
+    jv = torch.empty(nj, dtype=torch.float64, device=dev)
+    hv = torch.empty(nh, dtype=torch.float64, device=dev)
+    nbus_total = sum(int(n.dims.nbus) for n in nets)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        A.acopf_batch_eval(batch, x, sigma, lam, f, gf, c, jv, hv, A.ACOPF_ALL, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record(stream)
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        step()
+        ev[k][1].record(stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = start.elapsed_time(end)
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    value = nbus_total * args.steps / (total_ms / 1e3)
+    log(f"[bench] batched: {total_ms / args.steps:.4f} ms/step, {value:.4e} bus-evals/s "
+        f"(wall {wall:.3f}s)")
+
+    # plain path: the same kernels, one instance per launch, into the same buffers
+    L = A.lib()
+    import ctypes as C
+    xp, lp = x.data_ptr(), lam.data_ptr()
+    ptrs = []
+    for k, n in enumerate(nets):
+        xo, co, jo, ho = (int(batch.x_off[k]), int(batch.c_off[k]), int(batch.j_off[k]),
+                          int(batch.h_off[k]))
+        ptrs.append((n.handle, C.c_void_p(xp + 8 * xo), C.c_double(w["iterates"][k].sigma),
+                     C.c_void_p(lp + 8 * co), C.c_void_p(f.data_ptr() + 8 * k),
+                     C.c_void_p(gf.data_ptr() + 8 * xo), C.c_void_p(c.data_ptr() + 8 * co),
+                     C.c_void_p(jv.data_ptr() + 8 * jo), C.c_void_p(hv.data_ptr() + 8 * ho)))
+    sp = C.c_void_p(stream.cuda_stream)
+
+    def plain_step():
+        for p in ptrs:
+            rc = L.acopf_eval_all(*p, A.ACOPF_ALL, sp)
+            if rc:
+                raise RuntimeError(L.acopf_last_error().decode())
+
+    plain = None
+    if args.plain_steps > 0:
+        plain_step()
+        torch.cuda.synchronize()
+        ps, pe = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ps.record(stream)
+        for _ in range(args.plain_steps):
+            plain_step()
+        pe.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = ps.elapsed_time(pe) / args.plain_steps
+        plain_value = nbus_total / (plain_ms / 1e3)
+        plain = {"value": plain_value, "unit": "bus-evals/s", "ms_per_step": plain_ms,
+                 "launches_per_step": K}
+        log(f"[bench] plain: {plain_ms:.3f} ms/step, {plain_value:.4e} bus-evals/s")
+
+    alg = algorithmic_bytes(w)
+    avg_ms = float(np.mean(lat))
+    achieved = alg / (avg_ms / 1e3) / 1e9
+    traffic = load_traffic("k_eval_all", w["name"])
+    out = {
+        "metric": METRIC, "value": value, "unit": "bus-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "instances": K, "buses_per_step": nbus_total,
+                   "outputs": "f, grad_f, c, J, H", "schedule": sched},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "plain": plain,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes": alg, "kernel_ms": avg_ms},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -198,7 +198,7 @@ typedef struct {
 /* Build a batch over `count` nets (they cannot be destroyed while the batch
  * exists): per-instance offsets, the XCD-aware tile list and the device
  * descriptor table.  `sched` may be NULL for the default schedule
- * {256, 4, 1, 0}.  Errors: EINVAL (also when a bus exceeds the tile
+ * {128, 0, 1, 0}.  Errors: EINVAL (also when a bus exceeds the tile
  * capacity of the schedule), ENOMEM, EHIP. */
 int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* sched,
                        acopf_batch* out);

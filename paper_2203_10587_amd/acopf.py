@@ -179,14 +179,16 @@ class Net:
         return int(self.dims.nnz_hess)
 
     def close(self):
+        b = self.__dict__.pop("_vjp_batch", None)
+        if b is not None:
+            b.close()
         if self.handle:
             _check(lib().acopf_net_destroy(self.handle))
             self.handle = None
 
     def __del__(self):
         try:
-            if self.handle:
-                lib().acopf_net_destroy(self.handle)
+            self.close()
         except Exception:
             pass
 

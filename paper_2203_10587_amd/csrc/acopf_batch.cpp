@@ -138,10 +138,12 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
   if (!out) return fail(ACOPF_EINVAL, "null output handle");
   *out = nullptr;
   if (!nets || count < 1) return fail(ACOPF_EINVAL, "need at least one net");
-  acopf_sched s{kDefaultTileBe, 4, 1, 0};
+  acopf_sched s{kDefaultTileBe, 0, 1, 0};
   if (sched) s = *sched;
   TileCaps caps;
   if (!caps_for(s.tile_be, &caps)) return fail(ACOPF_EINVAL, "tile_be must be 64, 128 or 256");
+  if (s.xcd_group < 0 || s.xcd_group > 1 || s.no_graph < 0 || s.no_graph > 1)
+    return fail(ACOPF_EINVAL, "xcd_group and no_graph must be 0 or 1");
   if (s.grid_mult < 0 || s.grid_mult > 64) return fail(ACOPF_EINVAL, "grid_mult must be in [0, 64]");
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -172,30 +174,38 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
       b->ho[k + 1] = b->ho[k] + d.nnz_hess;
       fpo[k + 1] = fpo[k] + nets[k]->base->topo.nchunks;
     }
-    // per-base tile lists for this schedule (outage children share their base's)
-    std::map<const Base*, std::vector<Tile>> per_base;
+    // per-base tile and work lists for this schedule (outage children share their base's)
+    struct PerBase {
+      std::vector<Tile> tiles;
+      std::vector<WorkItem> work;
+      size_t work_off = 0;  // into the batch's work array
+    };
+    std::map<const Base*, PerBase> per_base;
+    size_t work_total = 0;
     for (int k = 0; k < count; ++k) {
       const Base* B = nets[k]->base.get();
       if (per_base.count(B)) continue;
-      std::vector<Tile> t;
-      int counts[3];
-      int rc = make_tiles(B->topo, s.tile_be, &t, counts);
+      PerBase pb;
+      int counts[2];
+      int rc = make_tiles(B->topo, s.tile_be, &pb.tiles, &pb.work, counts);
       if (rc) {
         free_batch(b);
         return rc;
       }
-      per_base.emplace(B, std::move(t));
+      pb.work_off = work_total;
+      work_total += pb.work.size();
+      per_base.emplace(B, std::move(pb));
     }
     // XCD queues, largest instances first (LPT on tile counts)
     std::vector<int> order(count);
     std::iota(order.begin(), order.end(), 0);
-    auto ntile = [&](int k) { return int(per_base[nets[k]->base.get()].size()); };
+    auto ntile = [&](int k) { return int(per_base[nets[k]->base.get()].tiles.size()); };
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return ntile(a) > ntile(c); });
     std::vector<std::vector<Tile>> queue(s.xcd_group ? kXcds : 1);
     std::vector<int64_t> load(queue.size(), 0);
     for (int k : order) {
       const size_t qi = std::min_element(load.begin(), load.end()) - load.begin();
-      for (Tile t : per_base[nets[k]->base.get()]) {
+      for (Tile t : per_base[nets[k]->base.get()].tiles) {
         t.inst = k;
         queue[qi].push_back(t);
       }
@@ -218,23 +228,13 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
       return rc;
     }
     b->grid = s.grid_mult > 0 ? std::min(b->ntiles, s.grid_mult * cus) : 0;
-    // device table, tiles, scratch
-    std::vector<InstOff> table(count);
-    for (int k = 0; k < count; ++k) {
-      InstOff I = net_inst(nets[k]);
-      I.xo = b->xo[k];
-      I.co = b->co[k];
-      I.jo = b->jo[k];
-      I.ho = b->ho[k];
-      I.k = k;
-      I.fpo = fpo[k];
-      table[k] = I;
-    }
-    const size_t s_table = align_up(table.size() * sizeof(InstOff));
+    // device table, tiles, work items, scratch
+    const size_t s_table = align_up(size_t(count) * sizeof(InstOff));
     const size_t s_tiles = align_up(tiles.size() * sizeof(Tile));
+    const size_t s_work = align_up(std::max<size_t>(work_total, 1) * sizeof(WorkItem));
     const size_t s_fpart = align_up(size_t(fpo[count]) * sizeof(double));
     const size_t s_ticket = align_up(size_t(count) * sizeof(uint32_t));
-    e = hipMalloc(&b->mem, s_table + s_tiles + s_fpart + s_ticket);
+    e = hipMalloc(&b->mem, s_table + s_tiles + s_work + s_fpart + s_ticket);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       b->mem = nullptr;
@@ -244,11 +244,29 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     char* base = static_cast<char*>(b->mem);
     b->d_table = reinterpret_cast<InstOff*>(base);
     b->d_tiles = reinterpret_cast<Tile*>(base + s_table);
-    b->d_fpart = reinterpret_cast<double*>(base + s_table + s_tiles);
-    b->d_ticket = reinterpret_cast<uint32_t*>(base + s_table + s_tiles + s_fpart);
+    WorkItem* d_work = reinterpret_cast<WorkItem*>(base + s_table + s_tiles);
+    b->d_fpart = reinterpret_cast<double*>(base + s_table + s_tiles + s_work);
+    b->d_ticket = reinterpret_cast<uint32_t*>(base + s_table + s_tiles + s_work + s_fpart);
+    std::vector<InstOff> table(count);
+    for (int k = 0; k < count; ++k) {
+      InstOff I = net_inst(nets[k]);
+      I.work = d_work + per_base[nets[k]->base.get()].work_off;
+      I.xo = b->xo[k];
+      I.co = b->co[k];
+      I.jo = b->jo[k];
+      I.ho = b->ho[k];
+      I.k = k;
+      I.fpo = fpo[k];
+      table[k] = I;
+    }
     e = hipMemcpy(b->d_table, table.data(), table.size() * sizeof(InstOff), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(b->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice);
+    for (auto& kv : per_base) {
+      if (e != hipSuccess || kv.second.work.empty()) continue;
+      e = hipMemcpy(d_work + kv.second.work_off, kv.second.work.data(),
+                    kv.second.work.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMemset(b->d_fpart, 0, s_fpart + s_ticket);
     if (e != hipSuccess) {
       free_batch(b);

@@ -268,13 +268,40 @@ void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,
   for (int k = 0; k < ng; ++k) hp->push_back(int32_t(hc->size()));
 }
 
-int make_tiles(const Topology& T, int tile_be, std::vector<Tile>* out, int counts[3]) {
+int make_tiles(const Topology& T, int tile_be, std::vector<Tile>* out, std::vector<WorkItem>* work,
+               int counts[2]) {
   TileCaps caps;
   if (!caps_for(tile_be, &caps)) return fail(ACOPF_EINVAL, "unsupported tile size");
   out->clear();
-  for (int l0 = 0; l0 < T.nl; l0 += caps.wg)
-    out->push_back({0, TILE_BRANCH, l0, std::min(T.nl, l0 + caps.wg)});
-  counts[0] = int(out->size());
+  work->clear();
+  // adjacency position of each branch end
+  std::vector<int32_t> pos_from(T.nl), pos_to(T.nl);
+  for (int e = 0; e < int(T.be.size()); ++e) {
+    const int code = T.be[e];
+    ((code & 1) ? pos_to : pos_from)[code >> 1] = e;
+  }
+  std::vector<int32_t> seen(T.nl, -1);
+  std::vector<int32_t> items;
+  auto close = [&](int b0, int b1) {
+    const int e0 = T.be_ptr[b0], e1 = T.be_ptr[b1];
+    items.clear();
+    for (int e = e0; e < e1; ++e) {
+      const int l = T.be[e] >> 1;
+      if (seen[l] != b0) {
+        seen[l] = b0;
+        items.push_back(l);
+      }
+    }
+    std::sort(items.begin(), items.end());
+    const int w0 = int(work->size());
+    for (int l : items) {
+      const int f = T.ft[l].x, t = T.ft[l].y;
+      const uint32_t sf = (f >= b0 && f < b1) ? uint32_t(pos_from[l] - e0) : kNoSlot;
+      const uint32_t st = (t >= b0 && t < b1) ? uint32_t(pos_to[l] - e0) : kNoSlot;
+      work->push_back({l, f, t, sf | (st << 16)});
+    }
+    out->push_back({0, TILE_BUS, b0, b1, e0, e1 - e0, w0, int(work->size()) - w0});
+  };
   int b0 = 0, cur_be = 0, cur_st = 0;
   for (int i = 0; i < T.nb; ++i) {
     const int d = T.be_ptr[i + 1] - T.be_ptr[i];
@@ -286,7 +313,7 @@ int make_tiles(const Topology& T, int tile_be, std::vector<Tile>* out, int count
                                     " row entries; a bus tile of this schedule holds at most " +
                                     std::to_string(caps.be) + " and " + std::to_string(caps.stage));
     if (i > b0 && (cur_be + d > caps.be || cur_st + st > caps.stage)) {
-      out->push_back({0, TILE_BUS, b0, i});
+      close(b0, i);
       b0 = i;
       cur_be = 0;
       cur_st = 0;
@@ -294,11 +321,12 @@ int make_tiles(const Topology& T, int tile_be, std::vector<Tile>* out, int count
     cur_be += d;
     cur_st += st;
   }
-  out->push_back({0, TILE_BUS, b0, T.nb});
-  counts[1] = int(out->size()) - counts[0];
+  close(b0, T.nb);
+  counts[0] = int(out->size());
   for (int c = 0; c < T.nchunks; ++c)
-    out->push_back({0, (c << 2) | TILE_GEN, c * kGenChunk, std::min(T.ng, (c + 1) * kGenChunk)});
-  counts[2] = int(out->size()) - counts[0] - counts[1];
+    out->push_back({0, (c << 2) | TILE_GEN, c * kGenChunk, std::min(T.ng, (c + 1) * kGenChunk), 0, 0,
+                    0, 0});
+  counts[1] = int(out->size()) - counts[0];
   return ACOPF_OK;
 }
 
@@ -319,7 +347,7 @@ Base::~Base() {
 
 int upload_base(Base* B) {
   const Topology& T = B->topo;
-  int rc = make_tiles(T, kDefaultTileBe, &B->plain_tiles, B->plain_counts);
+  int rc = make_tiles(T, kDefaultTileBe, &B->plain_tiles, &B->plain_work, B->plain_counts);
   if (rc) return rc;
   struct Part {
     const void* src;
@@ -327,11 +355,9 @@ int upload_base(Base* B) {
     size_t off;
   };
   std::vector<Part> parts = {
-      {T.ft.data(), T.ft.size() * sizeof(int2), 0},
       {T.y.data(), T.y.size() * sizeof(BranchY), 0},
       {T.bus.data(), T.bus.size() * sizeof(double4), 0},
       {T.be_ptr.data(), T.be_ptr.size() * sizeof(int32_t), 0},
-      {T.be.data(), T.be.size() * sizeof(int32_t), 0},
       {T.acnt.data(), T.acnt.size() * sizeof(int2), 0},
       {T.rows.data(), T.rows.size() * sizeof(int4), 0},
       {T.gen_ptr.data(), T.gen_ptr.size() * sizeof(int32_t), 0},
@@ -341,6 +367,7 @@ int upload_base(Base* B) {
       {T.c1.data(), T.c1.size() * sizeof(double), 0},
       {T.c0.data(), T.c0.size() * sizeof(double), 0},
       {B->plain_tiles.data(), B->plain_tiles.size() * sizeof(Tile), 0},
+      {B->plain_work.data(), B->plain_work.size() * sizeof(WorkItem), 0},
       {nullptr, sizeof(NetDev), 0},
   };
   size_t total = 0;
@@ -366,25 +393,24 @@ int upload_base(Base* B) {
   nd.nl = T.nl;
   nd.ng = T.ng;
   nd.nchunks = T.nchunks;
-  nd.br_ft = static_cast<const int2*>(at(0));
-  nd.br_y = static_cast<const BranchY*>(at(1));
-  nd.bus = static_cast<const double4*>(at(2));
-  nd.be_ptr = static_cast<const int32_t*>(at(3));
-  nd.be = static_cast<const int32_t*>(at(4));
-  nd.acnt = static_cast<const int2*>(at(5));
-  nd.rows = static_cast<const int4*>(at(6));
-  nd.gen_ptr = static_cast<const int32_t*>(at(7));
-  nd.gen_list = static_cast<const int32_t*>(at(8));
-  nd.gen_bus = static_cast<const int32_t*>(at(9));
-  nd.gen_c2 = static_cast<const double*>(at(10));
-  nd.gen_c1 = static_cast<const double*>(at(11));
-  nd.gen_c0 = static_cast<const double*>(at(12));
+  nd.br_y = static_cast<const BranchY*>(at(0));
+  nd.bus = static_cast<const double4*>(at(1));
+  nd.be_ptr = static_cast<const int32_t*>(at(2));
+  nd.acnt = static_cast<const int2*>(at(3));
+  nd.rows = static_cast<const int4*>(at(4));
+  nd.gen_ptr = static_cast<const int32_t*>(at(5));
+  nd.gen_list = static_cast<const int32_t*>(at(6));
+  nd.gen_bus = static_cast<const int32_t*>(at(7));
+  nd.gen_c2 = static_cast<const double*>(at(8));
+  nd.gen_c1 = static_cast<const double*>(at(9));
+  nd.gen_c0 = static_cast<const double*>(at(10));
   nd.base_mva = T.base;
   nd.jflow = T.jflow;
   nd.hpg = T.hpg;
-  B->d_tiles = static_cast<Tile*>(at(13));
-  B->d_net = static_cast<NetDev*>(at(14));
-  parts[14].src = &nd;
+  B->d_tiles = static_cast<Tile*>(at(11));
+  B->d_work = static_cast<WorkItem*>(at(12));
+  B->d_net = static_cast<NetDev*>(at(13));
+  parts[13].src = &nd;
   for (const Part& p : parts) {
     if (p.bytes == 0) continue;
     e = hipMemcpy(base + p.off, p.src, p.bytes, hipMemcpyHostToDevice);
@@ -559,6 +585,7 @@ int net_init_scratch(acopf_net_s* net) {
 InstOff net_inst(const acopf_net_s* net) {
   InstOff I{};
   I.net = net->base->d_net;
+  I.work = net->base->d_work;
   I.out_l = net->out_l;
   I.out_p = net->out_p;
   I.out_q = net->out_q;
@@ -578,19 +605,18 @@ int check_device(const acopf_net_s* net) {
   return ACOPF_OK;
 }
 
-// Plain path: the net's own tile list [branch][bus][gen], one workgroup per tile.
-static int run_plain(const acopf_net_s* net, unsigned variant, Bufs b, bool branch, bool bus,
-                     bool gen, hipStream_t s) {
+// Plain path: the net's own tile list [bus][gen], one workgroup per tile.
+static int run_plain(const acopf_net_s* net, unsigned variant, Bufs b, bool bus, bool gen,
+                     hipStream_t s) {
   int rc = check_device(net);
   if (rc) return rc;
   const Base& B = *net->base;
   b.fpart = net->d_fpart;
   b.ticket = net->d_ticket;
-  const int nbt = B.plain_counts[0], nbu = B.plain_counts[1], ngt = B.plain_counts[2];
-  int t0 = branch ? 0 : (bus ? nbt : nbt + nbu);
-  int t1 = gen ? nbt + nbu + ngt : (bus ? nbt + nbu : nbt);
-  if (!branch && !bus && !gen) return ACOPF_OK;
-  if (branch && !bus && gen) return fail(ACOPF_EINVAL, "internal: non-contiguous tile range");
+  const int nbu = B.plain_counts[0], ngt = B.plain_counts[1];
+  if (!bus && !gen) return ACOPF_OK;
+  const int t0 = bus ? 0 : nbu;
+  const int t1 = gen ? nbu + ngt : nbu;
   const InstOff one = net_inst(net);
   hipError_t e = launch_eval(variant, kDefaultTileBe, b, nullptr, one, B.d_tiles + t0, t1 - t0, 0, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -609,7 +635,7 @@ int acopf_eval_f_g(acopf_net net, const double* x, double* f, double* grad_f, do
   b.f = f;
   b.gradf = grad_f;
   b.c = c;
-  return run_plain(net, K_FG, b, c != nullptr, c != nullptr || grad_f != nullptr,
+  return run_plain(net, K_FG, b, c != nullptr || grad_f != nullptr,
                    f != nullptr || grad_f != nullptr, stream);
 }
 
@@ -618,7 +644,7 @@ int acopf_eval_jac(acopf_net net, const double* x, double* jac_val, hipStream_t 
   Bufs b{};
   b.x = x;
   b.jac = jac_val;
-  return run_plain(net, K_J, b, true, true, false, stream);
+  return run_plain(net, K_J, b, true, false, stream);
 }
 
 int acopf_eval_hess(acopf_net net, const double* x, double sigma, const double* lambda,
@@ -629,7 +655,7 @@ int acopf_eval_hess(acopf_net net, const double* x, double sigma, const double* 
   b.lam = lambda;
   b.sigma_v = sigma;
   b.hess = hess_val;
-  return run_plain(net, K_H, b, false, true, true, stream);
+  return run_plain(net, K_H, b, true, true, stream);
 }
 
 int acopf_vjp(acopf_net net, const double* x, double w_f, const double* w_c, double* u,
@@ -640,7 +666,7 @@ int acopf_vjp(acopf_net net, const double* x, double w_f, const double* w_c, dou
   b.wc = w_c;
   b.wf_v = w_f;
   b.u = u;
-  return run_plain(net, K_VJP, b, false, true, true, stream);
+  return run_plain(net, K_VJP, b, true, true, stream);
 }
 
 int acopf_eval_all(acopf_net net, const double* x, double sigma, const double* lambda, double* f,
@@ -661,7 +687,7 @@ int acopf_eval_all(acopf_net net, const double* x, double sigma, const double* l
   b.jac = (what & ACOPF_J) ? jac_val : nullptr;
   b.hess = (what & ACOPF_H) ? hess_val : nullptr;
   if (!what) return ACOPF_OK;
-  return run_plain(net, K_ALL, b, true, true, true, stream);
+  return run_plain(net, K_ALL, b, true, true, stream);
 }
 
 }  // extern "C"

@@ -35,9 +35,11 @@ struct Base {
   void* mem = nullptr;
   size_t bytes = 0;
   NetDev* d_net = nullptr;
-  Tile* d_tiles = nullptr;           // plain-path tiles [branch][bus][gen]
+  Tile* d_tiles = nullptr;           // plain-path tiles [bus][gen]
+  WorkItem* d_work = nullptr;        // plain-path work items
   std::vector<Tile> plain_tiles;
-  int plain_counts[3] = {0, 0, 0};
+  std::vector<WorkItem> plain_work;
+  int plain_counts[2] = {0, 0};
   ~Base();
 };
 
@@ -64,7 +66,8 @@ int outage_info(const Topology& T, int32_t l, int32_t* p, int32_t* q, int32_t* r
 void fill_dims(const Topology& T, int32_t outage, int32_t rm, acopf_dims* d);
 void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,
                    std::vector<int32_t>* jc, std::vector<int32_t>* hp, std::vector<int32_t>* hc);
-int make_tiles(const Topology& T, int tile_be, std::vector<Tile>* out, int counts[3]);
+int make_tiles(const Topology& T, int tile_be, std::vector<Tile>* out, std::vector<WorkItem>* work,
+               int counts[2]);
 int upload_base(Base* B);
 int net_init_scratch(acopf_net_s* net);
 InstOff net_inst(const acopf_net_s* net);

@@ -3,11 +3,14 @@
 // Everything a kernel reads about a network lives in one NetDev record in
 // device memory; everything about one evaluation instance (which net, which
 // outage, where its slices of the packed buffers start) in one InstOff.
-// Work is cut into tiles of three kinds:
-//   branch tile  a range of branches: flow limits h and their Jacobian rows
-//   bus tile     a range of buses: power balance g, the balance rows of J and
-//                the theta/v rows of the Hessian (or the VJP's theta/v part)
-//   gen tile     a fixed chunk of generators: f, grad f, the Pg diagonal of H
+// Work is cut into tiles of two kinds:
+//   bus tile  a contiguous range of buses: every branch touching them is
+//             evaluated once (a host-built work list names the branch, its
+//             endpoints and the LDS slots of its ends inside the tile); the
+//             tile writes the power-balance rows of c and J, the theta/v rows
+//             of the Hessian (or the VJP's theta/v entries), and the flow-limit
+//             rows of the branches whose from-bus it owns
+//   gen tile  a fixed chunk of generators: f, grad f, the Pg diagonal of H
 #pragma once
 
 #include <cstdint>
@@ -16,15 +19,23 @@
 namespace acopf {
 
 constexpr int kGenChunk = 256;   // generators per gen tile; fixes the f reduction tree
-constexpr int kMaxWG = 256;
+constexpr uint32_t kNoSlot = 0xFFFFu;
 
-enum TileKind : int32_t { TILE_BRANCH = 0, TILE_BUS = 1, TILE_GEN = 2 };
+enum TileKind : int32_t { TILE_BUS = 1, TILE_GEN = 2 };
 
-// A unit of work: instance index, kind and range ([a0, a1) branches, buses or
-// generators).  kind_aux = (aux << 2) | kind; aux is the generator chunk index
-// of a gen tile.
+// A unit of work.  Bus tile: buses [a0, a1), branch ends [e0, e0 + ne) of the
+// adjacency, work items [w0, w0 + nw).  Gen tile: generators [a0, a1);
+// kind_aux = (chunk << 2) | kind.
 struct Tile {
-  int32_t inst, kind_aux, a0, a1;
+  int32_t inst, kind_aux, a0, a1, e0, ne, w0, nw;
+};
+
+// One branch evaluated by a bus tile: branch id, its from and to bus, and
+// the tile-local branch-end slots of the two ends (kNoSlot if that end's bus
+// is outside the tile), packed as slot_from | slot_to << 16.
+struct WorkItem {
+  int32_t l, f, t;
+  uint32_t slots;
 };
 
 // Admittances of one branch (pi model, from-side ideal transformer).
@@ -34,12 +45,9 @@ struct BranchY {
 
 struct NetDev {
   int32_t nb, nl, ng, nchunks;
-  const int2* br_ft;        // [nl] (from, to)
   const BranchY* br_y;      // [nl]
   const double4* bus;       // [nb] (pd, qd, gs, bs)
-  const int32_t* be_ptr;    // [nb + 1] branch ends of bus i: be[be_ptr[i] .. be_ptr[i+1])
-  const int32_t* be;        // [2 nl] (branch << 1) | (1 if bus i is the to-end); sorted by
-                            //        (bus, other end, branch)
+  const int32_t* be_ptr;    // [nb + 1] branch ends of bus i: adjacency positions be_ptr[i] ..
   const int2* acnt;         // [nb] (|{i} u N(i)|, #distinct neighbours below i)
   const int4* rows;         // [nb + 1] base starts of (J P row, J Q row, H theta row, H v row)
   const int32_t* gen_ptr;   // [nb + 1] generators at bus i: gen_list[gen_ptr[i] .. gen_ptr[i+1])
@@ -56,6 +64,7 @@ struct NetDev {
 // One evaluation instance.  Offsets index the packed buffers of Bufs.
 struct InstOff {
   const NetDev* net;
+  const WorkItem* work;     // work items of the schedule in use
   int32_t out_l;            // removed branch, -1 for none
   int32_t out_p, out_q;     // its endpoints, p < q
   int32_t out_rm;           // 1 if no parallel branch keeps the (p, q) slots
@@ -88,8 +97,8 @@ enum : unsigned {
   W_F = 1u, W_GRADF = 2u, W_C = 4u, W_J = 8u, W_H = 16u, W_VJP = 32u,
 };
 
-// Tile capacities of one schedule: branch ends per bus tile, and the LDS
-// staging capacity (doubles) for the tile's J and H row segments.
+// Tile capacities of one schedule: workgroup size, branch ends per bus tile
+// and the LDS staging capacity (doubles) for the tile's J and H row segments.
 struct TileCaps {
   int32_t wg, be, stage;
 };
@@ -99,7 +108,7 @@ struct TileCaps {
 constexpr TileCaps kCaps64 = {64, 64, 640};
 constexpr TileCaps kCaps128 = {128, 128, 1280};
 constexpr TileCaps kCaps256 = {256, 256, 2560};
-constexpr int kDefaultTileBe = 256;
+constexpr int kDefaultTileBe = 128;
 
 inline bool caps_for(int tile_be, TileCaps* out) {
   switch (tile_be) {

@@ -2,41 +2,42 @@
 //
 // One kernel template covers every entry point; the compile-time variant
 // selects which outputs a tile produces.  A workgroup walks a list of tiles
-// (one tile per workgroup, or a persistent grid striding over the list):
+// (one tile per workgroup, or a persistent grid striding over the list).
 //
-//  branch tile  lane per branch: one sincos of theta_f - theta_t, the four end
-//               flows, h = P^2 + Q^2 at both ends and their Jacobian rows
-//               (2 (P dP + Q dQ) on theta_f, theta_t, v_f, v_t).  The Jacobian
-//               rows are staged in LDS and stored as one contiguous segment.
-//  bus tile     a contiguous range of buses and all their branch ends.
-//               Phase A, lane per branch end (uniform work): the branch seen
-//               from bus i -- flows, first derivatives with respect to
-//               (theta_i, v_i, v_j) and, for the Hessian, the four second
-//               derivatives of this branch's share of the Lagrangian that
-//               bus i's rows need -- into LDS records.
-//               Phase B, lane per bus: a segmented sum over the bus's branch
-//               ends in their fixed (neighbour, branch) order -- diagonal
-//               entries over all of them, one off-diagonal entry per distinct
-//               neighbour -- written into an LDS image of the tile's four
-//               contiguous CSR row segments (J P rows, J Q rows, H theta rows,
-//               H v rows).  No atomics: every sum has one owner and a fixed
-//               order, so results are bitwise reproducible.
-//               Phase C: the LDS image is streamed out with coalesced stores.
-//  gen tile     a fixed chunk of 256 generators: grad f, the Pg diagonal of
-//               H and a fixed-tree partial sum of the cost; the last chunk of
-//               an instance to finish (ticket counter) adds the partials in
-//               chunk order into f and re-arms the counter.
+//  bus tile  a contiguous range of buses.
+//            Phase A, lane per branch touching the tile (uniform work): one
+//            sincos of theta_f - theta_t, both end flows, their first
+//            derivatives and the second derivatives of the branch's share of
+//            the Lagrangian; per end inside the tile an LDS record (flows,
+//            the six Jacobian terms, the four Hessian terms, or the two VJP
+//            terms).  A branch whose from-bus the tile owns also writes its
+//            flow-limit rows: h = P^2 + Q^2 at both ends and their Jacobian
+//            rows 2 (P dP + Q dQ) on (theta_f, theta_t, v_f, v_t).
+//            Phase B, lane per bus: a segmented sum over the bus's branch
+//            ends in their fixed (far bus, branch) order -- diagonal entries
+//            over all of them, one off-diagonal entry per distinct neighbour
+//            -- written into an LDS image of the tile's four contiguous CSR
+//            row segments (J P rows, J Q rows, H theta rows, H v rows).  No
+//            atomics: every sum has one owner and a fixed order, so results
+//            are bitwise reproducible whatever the tiling.
+//            Phase C: the LDS image is streamed out with coalesced stores.
+//  gen tile  a fixed chunk of 256 generators: grad f, the Pg diagonal of H,
+//            the Pg/Qg part of the VJP and a fixed-tree partial sum of the
+//            cost; the last chunk of an instance to finish (ticket counter)
+//            adds the partials in chunk order into f and re-arms the counter.
 //
 // The model (paper: OPFLOW section, power-balance-polar representation; the
 // formulation itself is the standard polar pi-model one the paper refers to):
-// for a branch seen from end i with other end j, theta = theta_i - theta_j,
-// self admittance (g_ii, b_ii) and transfer admittance (g_ij, b_ij),
-//   P_i =  g_ii v_i^2 + v_i v_j (g_ij cos theta + b_ij sin theta)
-//   Q_i = -b_ii v_i^2 + v_i v_j (g_ij sin theta - b_ij cos theta)
-// and symmetrically for end j with theta_j - theta_i.  The branch's share of
-// the Lagrangian is  sum over its ends e of  lP_e P_e + lQ_e Q_e +
-// mu_e (P_e^2 + Q_e^2),  with lP, lQ the balance multipliers of the end buses
-// and mu_e the multiplier of the end's flow-limit row.
+// for a branch with from bus f and to bus t, theta = theta_f - theta_t,
+//   P_f =  g_ff v_f^2 + v_f v_t (g_ft cos theta + b_ft sin theta)
+//   Q_f = -b_ff v_f^2 + v_f v_t (g_ft sin theta - b_ft cos theta)
+//   P_t =  g_tt v_t^2 + v_f v_t (g_tf cos theta - b_tf sin theta)
+//   Q_t = -b_tt v_t^2 - v_f v_t (g_tf sin theta + b_tf cos theta)
+// The branch's share of the Lagrangian is, over its two ends e,
+//   lP_e P_e + lQ_e Q_e + mu_e (P_e^2 + Q_e^2)
+// with lP, lQ the balance multipliers of the end buses and mu_e the
+// multiplier of the end's flow-limit row.  All flows depend on the angles only
+// through theta, so every d/dtheta_t is the negative of d/dtheta_f.
 #include <hip/hip_runtime.h>
 
 #include "acopf_internal.h"
@@ -45,50 +46,49 @@ namespace acopf {
 namespace {
 
 // ---------------------------------------------------------------------------
-// The branch seen from end i (far end j): flows at both ends and their first
-// derivatives with respect to (theta_i, v_i, v_j).  Flows depend on the
-// angles only through their difference, so d/dtheta_j = -d/dtheta_i.
-struct EndView {
-  double vi, vj, w, cP, cQ, cPj, cQj;
-  double Pi, Qi, Pj, Qj;
-  double dPi_t, dPi_vi, dPi_vj, dQi_t, dQi_vi, dQi_vj;  // bus i's own end
-  double dPj_t, dPj_vi, dPj_vj, dQj_t, dQj_vi, dQj_vj;  // the far end
+// one branch: both end flows and first derivatives with respect to
+// (theta_f, v_f, v_t)
+
+struct Br {
+  double vf, vt, w, cP, cQ, cPt, cQt;
+  double Pf, Qf, Pt, Qt;
+  double Pf_a, Pf_f, Pf_t, Qf_a, Qf_f, Qf_t;  // d/dtheta_f, d/dv_f, d/dv_t of the from flow
+  double Pt_a, Pt_f, Pt_t, Qt_a, Qt_f, Qt_t;  // ... of the to flow
 };
 
-__device__ __forceinline__ void end_view(double thi, double thj, double vi, double vj,
-                                         double gii, double bii, double gij, double bij,
-                                         double gjj, double bjj, double gji, double bji,
-                                         EndView& o) {
+__device__ __forceinline__ void branch_eval(double thf, double tht, double vf, double vt,
+                                            const BranchY& y, Br& o) {
   double sn, cs;
-  sincos(thi - thj, &sn, &cs);
-  const double w = vi * vj;
-  const double cP = gij * cs + bij * sn;
-  const double cQ = gij * sn - bij * cs;
-  const double cPj = gji * cs - bji * sn;  // far end: sin(theta_j - theta_i) = -sn
-  const double cQj = -gji * sn - bji * cs;
-  o.vi = vi;
-  o.vj = vj;
+  sincos(thf - tht, &sn, &cs);
+  const double w = vf * vt;
+  const double cP = fma(y.gft, cs, y.bft * sn);
+  const double cQ = fma(y.gft, sn, -(y.bft * cs));
+  const double cPt = fma(y.gtf, cs, -(y.btf * sn));
+  const double cQt = -fma(y.gtf, sn, y.btf * cs);
+  o.vf = vf;
+  o.vt = vt;
   o.w = w;
   o.cP = cP;
   o.cQ = cQ;
-  o.cPj = cPj;
-  o.cQj = cQj;
-  o.Pi = gii * vi * vi + w * cP;
-  o.Qi = -bii * vi * vi + w * cQ;
-  o.Pj = gjj * vj * vj + w * cPj;
-  o.Qj = -bjj * vj * vj + w * cQj;
-  o.dPi_t = -w * cQ;
-  o.dPi_vi = 2.0 * gii * vi + vj * cP;
-  o.dPi_vj = vi * cP;
-  o.dQi_t = w * cP;
-  o.dQi_vi = -2.0 * bii * vi + vj * cQ;
-  o.dQi_vj = vi * cQ;
-  o.dPj_t = w * cQj;
-  o.dPj_vi = vj * cPj;
-  o.dPj_vj = 2.0 * gjj * vj + vi * cPj;
-  o.dQj_t = -w * cPj;
-  o.dQj_vi = vj * cQj;
-  o.dQj_vj = -2.0 * bjj * vj + vi * cQj;
+  o.cPt = cPt;
+  o.cQt = cQt;
+  const double vf2 = vf * vf, vt2 = vt * vt;
+  o.Pf = fma(y.gff, vf2, w * cP);
+  o.Qf = fma(-y.bff, vf2, w * cQ);
+  o.Pt = fma(y.gtt, vt2, w * cPt);
+  o.Qt = fma(-y.btt, vt2, w * cQt);
+  o.Pf_a = -(w * cQ);
+  o.Pf_f = fma(2.0 * y.gff, vf, vt * cP);
+  o.Pf_t = vf * cP;
+  o.Qf_a = w * cP;
+  o.Qf_f = fma(-2.0 * y.bff, vf, vt * cQ);
+  o.Qf_t = vf * cQ;
+  o.Pt_a = w * cQt;
+  o.Pt_f = vt * cPt;
+  o.Pt_t = fma(2.0 * y.gtt, vt, vf * cPt);
+  o.Qt_a = -(w * cPt);
+  o.Qt_f = vt * cQt;
+  o.Qt_t = fma(-2.0 * y.btt, vt, vf * cQt);
 }
 
 // Record layout of phase A (structure of arrays in LDS, BE entries per field).
@@ -98,10 +98,10 @@ struct Rec {
   static constexpr bool J = (WHAT & W_J) != 0;
   static constexpr bool H = (WHAT & W_H) != 0;
   static constexpr bool V = (WHAT & W_VJP) != 0;
-  static constexpr int oC = 0;                    // P_i, Q_i
-  static constexpr int oJ = oC + (C ? 2 : 0);     // dP/dth_i, dP/dv_i, dP/dv_j, dQ/...
-  static constexpr int oH = oJ + (J ? 6 : 0);     // a, beta, vv_ii, vv_ij
-  static constexpr int oV = oH + (H ? 4 : 0);     // u_theta_i, u_v_i
+  static constexpr int oC = 0;                  // P_e, Q_e
+  static constexpr int oJ = oC + (C ? 2 : 0);   // dP/dth_e, dP/dv_e, dP/dv_o, dQ/... (o = far end)
+  static constexpr int oH = oJ + (J ? 6 : 0);   // d2/dth_e2, d2/dv_e dth_e, d2/dv_e2, d2/dv_e dv_o
+  static constexpr int oV = oH + (H ? 4 : 0);   // u_th_e, u_v_e
   static constexpr int N = oV + (V ? 2 : 0);
 };
 
@@ -109,86 +109,11 @@ template <unsigned WHAT, int WG, int BE, int STAGE>
 struct Lds {
   static constexpr bool kStage = (WHAT & (W_J | W_H)) != 0;
   static constexpr int kBus = Rec<WHAT>::N * BE + BE / 2 + (kStage ? STAGE : 0);
-  static constexpr int kBranch = (WHAT & W_J) ? 8 * WG : 1;
   static constexpr int kGen = kGenChunk;
-  static constexpr int kA = kBus > kBranch ? kBus : kBranch;
-  static constexpr int kMax = kA > kGen ? kA : kGen;
+  static constexpr int kMax = kBus > kGen ? kBus : kGen;
 };
 
-__device__ __forceinline__ int live_branches(const NetDev& N, const InstOff& I) {
-  return N.nl - (I.out_l >= 0 ? 1 : 0);
-}
-
-__device__ __forceinline__ int after_outage(int l, int ol) {
-  return (ol >= 0 && l > ol) ? 1 : 0;
-}
-
-// ---------------------------------------------------------------------------
-// branch tile: flow-limit rows
-
-template <unsigned WHAT, int WG>
-__device__ void branch_tile(const Bufs& B, const InstOff& I, const NetDev& N, int l0, int l1,
-                            double* smem) {
-  constexpr bool DO_C = (WHAT & W_C) != 0;
-  constexpr bool DO_J = (WHAT & W_J) != 0;
-  const int tid = threadIdx.x;
-  const int nb = N.nb;
-  const int nll = live_branches(N, I);
-  const int ol = I.out_l;
-  const int lp0 = l0 - after_outage(l0, ol);
-  const int lp1 = l1 - after_outage(l1, ol);
-  const double* x = B.x + I.xo;
-  double* c = (DO_C && B.c) ? B.c + I.co : nullptr;
-  const bool jout = DO_J && B.jac != nullptr;
-  for (int l = l0 + tid; l < l1; l += WG) {
-    if (l == ol) continue;
-    const int lp = l - after_outage(l, ol);
-    const int2 ft = N.br_ft[l];
-    const BranchY y = N.br_y[l];
-    EndView e;  // i = from end, j = to end
-    end_view(x[ft.x], x[ft.y], x[nb + ft.x], x[nb + ft.y], y.gff, y.bff, y.gft, y.bft, y.gtt,
-             y.btt, y.gtf, y.btf, e);
-    if (c) {
-      c[2 * nb + lp] = e.Pi * e.Pi + e.Qi * e.Qi;
-      c[2 * nb + nll + lp] = e.Pj * e.Pj + e.Qj * e.Qj;
-    }
-    if (jout) {
-      // d h / d(theta_f, v_f, v_t); d/dtheta_t = -d/dtheta_f
-      const double hf_t = 2.0 * (e.Pi * e.dPi_t + e.Qi * e.dQi_t);
-      const double hf_vf = 2.0 * (e.Pi * e.dPi_vi + e.Qi * e.dQi_vi);
-      const double hf_vt = 2.0 * (e.Pi * e.dPi_vj + e.Qi * e.dQi_vj);
-      const double ht_t = 2.0 * (e.Pj * e.dPj_t + e.Qj * e.dQj_t);
-      const double ht_vf = 2.0 * (e.Pj * e.dPj_vi + e.Qj * e.dQj_vi);
-      const double ht_vt = 2.0 * (e.Pj * e.dPj_vj + e.Qj * e.dQj_vj);
-      const bool asc = ft.x < ft.y;  // columns ascend: theta_lo, theta_hi, v_lo, v_hi
-      double* sf = smem + 4 * (lp - lp0);
-      double* st = smem + 4 * WG + 4 * (lp - lp0);
-      sf[0] = asc ? hf_t : -hf_t;
-      sf[1] = asc ? -hf_t : hf_t;
-      sf[2] = asc ? hf_vf : hf_vt;
-      sf[3] = asc ? hf_vt : hf_vf;
-      st[0] = asc ? ht_t : -ht_t;
-      st[1] = asc ? -ht_t : ht_t;
-      st[2] = asc ? ht_vf : ht_vt;
-      st[3] = asc ? ht_vt : ht_vf;
-    }
-  }
-  if (jout) {
-    __syncthreads();
-    const int n4 = 4 * (lp1 - lp0);
-    double* jac = B.jac + I.jo;
-    const int jflow = N.jflow - 8 * I.out_rm;
-    double* df = jac + jflow + 4 * lp0;
-    double* dt = jac + jflow + 4 * nll + 4 * lp0;
-    for (int k = tid; k < n4; k += WG) {
-      df[k] = smem[k];
-      dt[k] = smem[4 * WG + k];
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// bus tile: balance rows of c and J, theta/v rows of H, theta/v part of the VJP
+__device__ __forceinline__ int after_outage(int l, int ol) { return (ol >= 0 && l > ol) ? 1 : 0; }
 
 // Row starts of an instance: the base pattern's, shifted for a removed
 // (p, q) slot pair (p < q): rows p and q of the J balance blocks lose two
@@ -205,99 +130,162 @@ struct RowShift {
   }
 };
 
+// ---------------------------------------------------------------------------
+// bus tile
+
 template <unsigned WHAT, int WG, int BE, int STAGE>
-__device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, int b0, int b1,
+__device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const Tile& T,
                          double* smem) {
   using R = Rec<WHAT>;
   constexpr bool DO_GF = (WHAT & W_GRADF) != 0 && !R::V;
   const int tid = threadIdx.x;
   const int nb = N.nb;
-  const int nll = live_branches(N, I);
   const int ol = I.out_l;
-  const int e0 = N.be_ptr[b0];
-  const int ne = N.be_ptr[b1] - e0;
+  const int nll = N.nl - (ol >= 0 ? 1 : 0);
+  const int b0 = T.a0, b1 = T.a1, e0 = T.e0;
   double* rec = smem;
   int* nbr = reinterpret_cast<int*>(smem + R::N * BE);
   double* stage = smem + R::N * BE + BE / 2;
   const double* x = B.x + I.xo;
   const double* mul = R::H ? B.lam + I.co : (R::V ? B.wc + I.co : nullptr);
+  const bool hneed = R::V || (R::H && B.hess != nullptr);
+  double* cflow = (R::C && B.c) ? B.c + I.co + 2 * nb : nullptr;
+  double* jflow = (R::J && B.jac) ? B.jac + I.jo + (N.jflow - 8 * I.out_rm) : nullptr;
 
-  // ---- phase A: lane per branch end
-  for (int e = tid; e < ne; e += WG) {
-    const int code = N.be[e0 + e];
-    const int l = code >> 1;
-    const bool ito = (code & 1) != 0;
-    const int2 ft = N.br_ft[l];
-    const int i = ito ? ft.y : ft.x;
-    const int j = ito ? ft.x : ft.y;
-    if (l == ol) {
-      nbr[e] = -1 - j;  // removed branch: keeps its place in the order, adds nothing
+  // ---- phase A: lane per branch touching the tile
+  for (int k = tid; k < T.nw; k += WG) {
+    const WorkItem wi = I.work[T.w0 + k];
+    const int l = wi.l, f = wi.f, t = wi.t;
+    const uint32_t sf = wi.slots & 0xFFFFu, st = wi.slots >> 16;
+    if (l == ol) {  // removed branch: keeps its place in the adjacency order, adds nothing
+      if (sf != kNoSlot) nbr[sf] = -1 - t;
+      if (st != kNoSlot) nbr[st] = -1 - f;
       continue;
     }
-    nbr[e] = j;
+    if (sf != kNoSlot) nbr[sf] = t;
+    if (st != kNoSlot) nbr[st] = f;
     const BranchY y = N.br_y[l];
-    EndView v;
-    end_view(x[i], x[j], x[nb + i], x[nb + j], ito ? y.gtt : y.gff, ito ? y.btt : y.bff,
-             ito ? y.gtf : y.gft, ito ? y.btf : y.bft, ito ? y.gff : y.gtt, ito ? y.bff : y.btt,
-             ito ? y.gft : y.gtf, ito ? y.bft : y.btf, v);
+    Br b;
+    branch_eval(x[f], x[t], x[nb + f], x[nb + t], y, b);
+    const int lp = l - after_outage(l, ol);
     if constexpr (R::C) {
-      rec[(R::oC + 0) * BE + e] = v.Pi;
-      rec[(R::oC + 1) * BE + e] = v.Qi;
+      if (sf != kNoSlot) {
+        rec[(R::oC + 0) * BE + sf] = b.Pf;
+        rec[(R::oC + 1) * BE + sf] = b.Qf;
+      }
+      if (st != kNoSlot) {
+        rec[(R::oC + 0) * BE + st] = b.Pt;
+        rec[(R::oC + 1) * BE + st] = b.Qt;
+      }
     }
     if constexpr (R::J) {
-      rec[(R::oJ + 0) * BE + e] = v.dPi_t;
-      rec[(R::oJ + 1) * BE + e] = v.dPi_vi;
-      rec[(R::oJ + 2) * BE + e] = v.dPi_vj;
-      rec[(R::oJ + 3) * BE + e] = v.dQi_t;
-      rec[(R::oJ + 4) * BE + e] = v.dQi_vi;
-      rec[(R::oJ + 5) * BE + e] = v.dQi_vj;
+      if (sf != kNoSlot) {
+        rec[(R::oJ + 0) * BE + sf] = b.Pf_a;
+        rec[(R::oJ + 1) * BE + sf] = b.Pf_f;
+        rec[(R::oJ + 2) * BE + sf] = b.Pf_t;
+        rec[(R::oJ + 3) * BE + sf] = b.Qf_a;
+        rec[(R::oJ + 4) * BE + sf] = b.Qf_f;
+        rec[(R::oJ + 5) * BE + sf] = b.Qf_t;
+      }
+      if (st != kNoSlot) {  // to end: d/dtheta_t = -d/dtheta_f
+        rec[(R::oJ + 0) * BE + st] = -b.Pt_a;
+        rec[(R::oJ + 1) * BE + st] = b.Pt_t;
+        rec[(R::oJ + 2) * BE + st] = b.Pt_f;
+        rec[(R::oJ + 3) * BE + st] = -b.Qt_a;
+        rec[(R::oJ + 4) * BE + st] = b.Qt_t;
+        rec[(R::oJ + 5) * BE + st] = b.Qt_f;
+      }
+    }
+    if (sf != kNoSlot) {  // the from-bus owner writes the flow-limit rows
+      if (cflow) {
+        cflow[lp] = fma(b.Pf, b.Pf, b.Qf * b.Qf);
+        cflow[nll + lp] = fma(b.Pt, b.Pt, b.Qt * b.Qt);
+      }
+      if (jflow) {
+        const double hf_a = 2.0 * fma(b.Pf, b.Pf_a, b.Qf * b.Qf_a);
+        const double hf_f = 2.0 * fma(b.Pf, b.Pf_f, b.Qf * b.Qf_f);
+        const double hf_t = 2.0 * fma(b.Pf, b.Pf_t, b.Qf * b.Qf_t);
+        const double ht_a = 2.0 * fma(b.Pt, b.Pt_a, b.Qt * b.Qt_a);
+        const double ht_f = 2.0 * fma(b.Pt, b.Pt_f, b.Qt * b.Qt_f);
+        const double ht_t = 2.0 * fma(b.Pt, b.Pt_t, b.Qt * b.Qt_t);
+        const bool asc = f < t;  // columns ascend: theta_lo, theta_hi, v_lo, v_hi
+        double* rf = jflow + 4 * lp;
+        double* rt = jflow + 4 * nll + 4 * lp;
+        rf[0] = asc ? hf_a : -hf_a;
+        rf[1] = asc ? -hf_a : hf_a;
+        rf[2] = asc ? hf_f : hf_t;
+        rf[3] = asc ? hf_t : hf_f;
+        rt[0] = asc ? ht_a : -ht_a;
+        rt[1] = asc ? -ht_a : ht_a;
+        rt[2] = asc ? ht_f : ht_t;
+        rt[3] = asc ? ht_t : ht_f;
+      }
     }
     if constexpr (R::H || R::V) {
-      // the full-evaluation variant reads multipliers only when H is wanted
-      if (!R::V && B.hess == nullptr) continue;
-      const int lp = l - after_outage(l, ol);
+      if (!hneed) continue;  // the full variant reads multipliers only when H is wanted
       const double mf = mul[2 * nb + lp];
       const double mt = mul[2 * nb + nll + lp];
-      const double mi = ito ? mt : mf;
-      const double mj = ito ? mf : mt;
       // weights of dP, dQ in  lP P + lQ Q + mu (P^2 + Q^2)
-      const double oPi = mul[i] + 2.0 * mi * v.Pi;
-      const double oQi = mul[nb + i] + 2.0 * mi * v.Qi;
-      const double oPj = mul[j] + 2.0 * mj * v.Pj;
-      const double oQj = mul[nb + j] + 2.0 * mj * v.Qj;
+      const double oPf = fma(2.0 * mf, b.Pf, mul[f]);
+      const double oQf = fma(2.0 * mf, b.Qf, mul[nb + f]);
+      const double oPt = fma(2.0 * mt, b.Pt, mul[t]);
+      const double oQt = fma(2.0 * mt, b.Qt, mul[nb + t]);
       if constexpr (R::H) {
-        const double s = oPi * v.cP + oQi * v.cQ + oPj * v.cPj + oQj * v.cQj;
-        const double a =  // d2 / dtheta_i^2
-            -v.w * s + 2.0 * mi * (v.dPi_t * v.dPi_t + v.dQi_t * v.dQi_t) +
-            2.0 * mj * (v.dPj_t * v.dPj_t + v.dQj_t * v.dQj_t);
-        const double beta =  // d2 / dv_i dtheta_i
-            v.vj * (oQi * v.cP - oPi * v.cQ + oPj * v.cQj - oQj * v.cPj) +
-            2.0 * mi * (v.dPi_vi * v.dPi_t + v.dQi_vi * v.dQi_t) +
-            2.0 * mj * (v.dPj_vi * v.dPj_t + v.dQj_vi * v.dQj_t);
-        const double b_self = ito ? y.btt : y.bff;
-        const double g_self = ito ? y.gtt : y.gff;
-        const double vvii =  // d2 / dv_i^2
-            2.0 * (oPi * g_self - oQi * b_self) +
-            2.0 * mi * (v.dPi_vi * v.dPi_vi + v.dQi_vi * v.dQi_vi) +
-            2.0 * mj * (v.dPj_vi * v.dPj_vi + v.dQj_vi * v.dQj_vi);
-        const double vvij =  // d2 / dv_i dv_j
-            s + 2.0 * mi * (v.dPi_vi * v.dPi_vj + v.dQi_vi * v.dQi_vj) +
-            2.0 * mj * (v.dPj_vi * v.dPj_vj + v.dQj_vi * v.dQj_vj);
-        rec[(R::oH + 0) * BE + e] = a;
-        rec[(R::oH + 1) * BE + e] = beta;
-        rec[(R::oH + 2) * BE + e] = vvii;
-        rec[(R::oH + 3) * BE + e] = vvij;
+        // s: the weighted transfer terms; d2L/dv_f dv_t starts with s and
+        // d2L/dtheta_f^2 with -w s
+        const double s = fma(oPf, b.cP, fma(oQf, b.cQ, fma(oPt, b.cPt, oQt * b.cQt)));
+        const double m2f = 2.0 * mf, m2t = 2.0 * mt;
+        const double a = fma(-b.w, s,
+                             fma(m2f, fma(b.Pf_a, b.Pf_a, b.Qf_a * b.Qf_a),
+                                 m2t * fma(b.Pt_a, b.Pt_a, b.Qt_a * b.Qt_a)));
+        // d2L/dv_f dtheta_f
+        const double r = fma(oQf, b.cP, fma(-oPf, b.cQ, fma(oPt, b.cQt, -(oQt * b.cPt))));
+        const double beta_f = fma(b.vt, r,
+                                  fma(m2f, fma(b.Pf_f, b.Pf_a, b.Qf_f * b.Qf_a),
+                                      m2t * fma(b.Pt_f, b.Pt_a, b.Qt_f * b.Qt_a)));
+        // d2L/dv_t dtheta_t = -d2L/dv_t dtheta_f
+        const double beta_t = -fma(b.vf, r,
+                                   fma(m2f, fma(b.Pf_t, b.Pf_a, b.Qf_t * b.Qf_a),
+                                       m2t * fma(b.Pt_t, b.Pt_a, b.Qt_t * b.Qt_a)));
+        const double vv_ff = fma(2.0, fma(oPf, y.gff, -(oQf * y.bff)),
+                                 fma(m2f, fma(b.Pf_f, b.Pf_f, b.Qf_f * b.Qf_f),
+                                     m2t * fma(b.Pt_f, b.Pt_f, b.Qt_f * b.Qt_f)));
+        const double vv_tt = fma(2.0, fma(oPt, y.gtt, -(oQt * y.btt)),
+                                 fma(m2f, fma(b.Pf_t, b.Pf_t, b.Qf_t * b.Qf_t),
+                                     m2t * fma(b.Pt_t, b.Pt_t, b.Qt_t * b.Qt_t)));
+        const double vv_ft = s + fma(m2f, fma(b.Pf_f, b.Pf_t, b.Qf_f * b.Qf_t),
+                                     m2t * fma(b.Pt_f, b.Pt_t, b.Qt_f * b.Qt_t));
+        if (sf != kNoSlot) {
+          rec[(R::oH + 0) * BE + sf] = a;
+          rec[(R::oH + 1) * BE + sf] = beta_f;
+          rec[(R::oH + 2) * BE + sf] = vv_ff;
+          rec[(R::oH + 3) * BE + sf] = vv_ft;
+        }
+        if (st != kNoSlot) {
+          rec[(R::oH + 0) * BE + st] = a;
+          rec[(R::oH + 1) * BE + st] = beta_t;
+          rec[(R::oH + 2) * BE + st] = vv_tt;
+          rec[(R::oH + 3) * BE + st] = vv_ft;
+        }
       }
       if constexpr (R::V) {
-        rec[(R::oV + 0) * BE + e] = oPi * v.dPi_t + oQi * v.dQi_t + oPj * v.dPj_t + oQj * v.dQj_t;
-        rec[(R::oV + 1) * BE + e] =
-            oPi * v.dPi_vi + oQi * v.dQi_vi + oPj * v.dPj_vi + oQj * v.dQj_vi;
+        const double u_a = fma(oPf, b.Pf_a, fma(oQf, b.Qf_a, fma(oPt, b.Pt_a, oQt * b.Qt_a)));
+        if (sf != kNoSlot) {
+          rec[(R::oV + 0) * BE + sf] = u_a;
+          rec[(R::oV + 1) * BE + sf] =
+              fma(oPf, b.Pf_f, fma(oQf, b.Qf_f, fma(oPt, b.Pt_f, oQt * b.Qt_f)));
+        }
+        if (st != kNoSlot) {
+          rec[(R::oV + 0) * BE + st] = -u_a;
+          rec[(R::oV + 1) * BE + st] =
+              fma(oPf, b.Pf_t, fma(oQf, b.Qf_t, fma(oPt, b.Pt_t, oQt * b.Qt_t)));
+        }
       }
     }
   }
   __syncthreads();
 
-  // ---- phase B: lane per bus, segmented sums in (neighbour, branch) order
+  // ---- phase B: lane per bus, segmented sums in (far bus, branch) order
   const RowShift sh{I.out_p, I.out_q, I.out_rm};
   const int4 r0 = N.rows[b0];
   const int4 r1 = N.rows[b1];
@@ -312,7 +300,6 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, int b
   const bool hout = R::H && B.hess != nullptr;
   double* c = (R::C && B.c) ? B.c + I.co : nullptr;
   double* gradf = (DO_GF && B.gradf) ? B.gradf + I.xo : nullptr;
-  double* u = R::V ? B.u + I.xo : nullptr;
 
   for (int ib = tid; ib < b1 - b0; ib += WG) {
     const int i = b0 + ib;
@@ -321,7 +308,10 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, int b
     int a = ac.x, lo = ac.y;
     if (sh.rm) {
       if (i == sh.p) a -= 1;
-      if (i == sh.q) { a -= 1; lo -= 1; }
+      if (i == sh.q) {
+        a -= 1;
+        lo -= 1;
+      }
     }
     const int oP = sh.jP(ri, i) - jP0, oQ = sh.jQ(ri, i) - jQ0;
     const int oT = sh.hT(ri, i) - hT0, oV = sh.hV(ri, i) - hV0;
@@ -358,13 +348,15 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, int b
           gQv += rec[(R::oJ + 5) * BE + e];
         }
         if constexpr (R::H) {
-          const double t0 = rec[(R::oH + 0) * BE + e], t1 = rec[(R::oH + 1) * BE + e];
-          ha += t0;
-          hb += t1;
-          hvv += rec[(R::oH + 2) * BE + e];
-          ga += t0;
-          gb += t1;
-          gvv += rec[(R::oH + 3) * BE + e];
+          if (hout) {
+            const double t0 = rec[(R::oH + 0) * BE + e], t1 = rec[(R::oH + 1) * BE + e];
+            ha += t0;
+            hb += t1;
+            hvv += rec[(R::oH + 2) * BE + e];
+            ga += t0;
+            gb += t1;
+            gvv += rec[(R::oH + 3) * BE + e];
+          }
         }
         if constexpr (R::V) {
           ut += rec[(R::oV + 0) * BE + e];
@@ -393,9 +385,9 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, int b
     const int g0 = N.gen_ptr[i], g1 = N.gen_ptr[i + 1];
     if (jout) {
       sP[oP + lo] = dP_t;
-      sP[oP + a + lo] = dP_v + 2.0 * bd.z * vi;
+      sP[oP + a + lo] = fma(2.0 * bd.z, vi, dP_v);
       sQ[oQ + lo] = dQ_t;
-      sQ[oQ + a + lo] = dQ_v - 2.0 * bd.w * vi;
+      sQ[oQ + a + lo] = fma(-2.0 * bd.w, vi, dQ_v);
       for (int g = g0; g < g1; ++g) {
         sP[oP + 2 * a + (g - g0)] = -1.0;
         sQ[oQ + 2 * a + (g - g0)] = -1.0;
@@ -405,7 +397,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, int b
       const double* lam = B.lam + I.co;
       sT[oT + lo] = ha;
       sV[oV + lo] = hb;
-      sV[oV + a + lo] = hvv + 2.0 * (lam[i] * bd.z - lam[nb + i] * bd.w);
+      sV[oV + a + lo] = fma(2.0, fma(lam[i], bd.z, -(lam[nb + i] * bd.w)), hvv);
     }
     if (c) {
       double pg = 0, qg = 0;
@@ -414,8 +406,8 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, int b
         pg += x[2 * nb + k];
         qg += x[2 * nb + N.ng + k];
       }
-      c[i] = sPi + bd.z * vi * vi - pg + bd.x;
-      c[nb + i] = sQi - bd.w * vi * vi - qg + bd.y;
+      c[i] = fma(bd.z * vi, vi, sPi) - pg + bd.x;
+      c[nb + i] = fma(-bd.w * vi, vi, sQi) - qg + bd.y;
     }
     if (gradf) {
       gradf[i] = 0.0;
@@ -423,8 +415,9 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, int b
     }
     if constexpr (R::V) {
       const double* w = B.wc + I.co;
+      double* u = B.u + I.xo;
       u[i] = ut;
-      u[nb + i] = uv + 2.0 * (w[i] * bd.z - w[nb + i] * bd.w) * vi;
+      u[nb + i] = fma(2.0 * vi, fma(w[i], bd.z, -(w[nb + i] * bd.w)), uv);
     }
   }
 
@@ -472,7 +465,7 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
       const double pg = x[2 * nb + k];
       const double c2 = N.gen_c2[k], c1 = N.gen_c1[k];
       const double p = Bm * pg;
-      const double grad = 2.0 * c2 * Bm * p + c1 * Bm;
+      const double grad = Bm * fma(2.0 * c2, p, c1);
       if (gradf) {
         gradf[2 * nb + k] = grad;
         gradf[2 * nb + ng + k] = 0.0;
@@ -481,10 +474,10 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
       if constexpr (DO_V) {
         const double* w = B.wc + I.co;
         const int bus = N.gen_bus[k];
-        B.u[I.xo + 2 * nb + k] = wf * grad - w[bus];
+        B.u[I.xo + 2 * nb + k] = fma(wf, grad, -w[bus]);
         B.u[I.xo + 2 * nb + ng + k] = -w[nb + bus];
       }
-      if (fout) term = c2 * p * p + c1 * p + N.gen_c0[k];
+      if (fout) term = fma(fma(c2, p, c1), p, N.gen_c0[k]);
     }
     if (fout) smem[t] = term;
   }
@@ -523,11 +516,8 @@ __global__ __launch_bounds__(WG) void k_eval(Bufs B, const InstOff* __restrict__
     const Tile T = tiles[t];
     const InstOff I = table ? table[T.inst] : one;
     const NetDev& N = *I.net;
-    const int kind = T.kind_aux & 3;
-    if (kind == TILE_BUS) {
-      bus_tile<WHAT, WG, BE, STAGE>(B, I, N, T.a0, T.a1, smem);
-    } else if (kind == TILE_BRANCH) {
-      if constexpr ((WHAT & (W_C | W_J)) != 0) branch_tile<WHAT, WG>(B, I, N, T.a0, T.a1, smem);
+    if ((T.kind_aux & 3) == TILE_BUS) {
+      bus_tile<WHAT, WG, BE, STAGE>(B, I, N, T, smem);
     } else {
       if constexpr ((WHAT & (W_F | W_GRADF | W_H | W_VJP)) != 0)
         gen_tile<WHAT, WG>(B, I, N, T.a0, T.a1, T.kind_aux >> 2, smem);

@@ -1,0 +1,103 @@
+"""Autotuner for the batched schedule.
+
+A schedule is (tile_be, grid_mult, xcd_group): branch ends per bus tile
+(64/128/256, which also fixes the workgroup size and the LDS footprint),
+the persistent grid in workgroups per CU (0 = one workgroup per tile), and
+whether each instance's tiles are pinned to one XCD.  The tuner times every
+candidate on the caller's own batch with HIP events and caches the winner
+in a JSON file keyed by GPU architecture and a size bucket of the batch.
+Every schedule gives bitwise identical results (sums have fixed owners and
+orders independent of the tiling), so the choice affects speed only.
+
+Cache path: $ACOPF_TUNE_CACHE, else tune_cache.json beside this file.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, List, Sequence
+
+DEFAULT = {"tile_be": 128, "grid_mult": 0, "xcd_group": 1, "no_graph": 0}
+CANDIDATES = [{"tile_be": t, "grid_mult": g, "xcd_group": x, "no_graph": 0}
+              for t in (64, 128, 256) for g in (0, 2, 4, 8) for x in (0, 1)]
+
+
+def cache_path() -> str:
+    return os.environ.get("ACOPF_TUNE_CACHE",
+                          os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json"))
+
+
+def _arch() -> str:
+    try:
+        import torch
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def bucket(nets: Sequence) -> str:
+    """Size bucket: instance count and mean buses per instance, both in
+    powers of two."""
+    k = len(nets)
+    buses = sum(int(n.dims.nbus) for n in nets)
+    mean = max(1, buses // max(k, 1))
+    return f"k{int(math.log2(k)) if k else 0}_b{int(math.log2(mean))}"
+
+
+def _load() -> Dict:
+    p = cache_path()
+    if os.path.exists(p):
+        try:
+            with open(p) as fh:
+                return json.load(fh)
+        except Exception:
+            return {}
+    return {}
+
+
+def lookup_or_default(nets: Sequence) -> Dict:
+    ent = _load().get(_arch(), {}).get(bucket(nets))
+    return dict(ent["sched"]) if ent else dict(DEFAULT)
+
+
+def store(nets: Sequence, sched: Dict, timings: List) -> None:
+    doc = _load()
+    doc.setdefault(_arch(), {})[bucket(nets)] = {"sched": sched, "timings_ms": timings}
+    with open(cache_path(), "w") as fh:
+        json.dump(doc, fh, indent=1, sort_keys=True)
+
+
+def autotune(nets: Sequence, x, sigma, lam, outs, what=None, reps: int = 10,
+             candidates: Sequence[Dict] = CANDIDATES, save: bool = True) -> Dict:
+    """Time every candidate schedule on this batch (outputs `outs` =
+    (f, grad_f, c, jac, hess) packed for the batch) and return the fastest."""
+    import torch
+    from . import acopf as A
+    what = A.ACOPF_ALL if what is None else what
+    stream = torch.cuda.current_stream()
+    results = []
+    for cand in candidates:
+        try:
+            b = A.acopf_batch_create(nets, **cand)
+        except A.AcopfError:
+            continue  # a bus exceeds this schedule's tile capacity
+        for _ in range(2):
+            A.acopf_batch_eval(b, x, sigma, lam, *outs, what, stream)
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record(stream)
+        for _ in range(reps):
+            A.acopf_batch_eval(b, x, sigma, lam, *outs, what, stream)
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        results.append((ms, cand))
+        b.close()
+    if not results:
+        raise RuntimeError("no schedule fits this batch")
+    results.sort(key=lambda r: r[0])
+    best = dict(results[0][1])
+    if save:
+        store(nets, best, [[round(ms, 5), c] for ms, c in results])
+    return best

@@ -1,0 +1,245 @@
+"""Batched evaluation on the GPU: parity with the oracle, bitwise identity
+with the one-instance-per-launch path and across every schedule, HIP-graph
+replays, and the two batched workloads at full size (1,000 N-1 outages of a
+2,000-bus grid; 512 uneven scenario grids of 200..25,000 buses)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2203_10587_amd import synth as S
+from tests.parity import assert_close, compare_outputs, log, oracle_all
+
+pytestmark = pytest.mark.gpu
+
+
+def _t():
+    import torch
+    return torch
+
+
+class Packed:
+    """Packed device buffers of a batch, filled from per-instance iterates."""
+
+    def __init__(self, A, batch, iterates, w_f=None, w_c=None):
+        torch = _t()
+        self.A, self.b = A, batch
+        K = batch.count
+        nx, nc = int(batch.x_off[-1]), int(batch.c_off[-1])
+        x = np.empty(nx)
+        lam = np.empty(nc)
+        for k, it in enumerate(iterates):
+            x[batch.x_off[k]:batch.x_off[k + 1]] = it.x
+            lam[batch.c_off[k]:batch.c_off[k + 1]] = it.lam
+        d = lambda a: torch.as_tensor(a, dtype=torch.float64, device="cuda")
+        self.x, self.lam = d(x), d(lam)
+        self.sigma = d([it.sigma for it in iterates])
+        nan = lambda n: torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+        self.f, self.gf, self.c = nan(K), nan(nx), nan(nc)
+        self.jv, self.hv = nan(int(batch.j_off[-1])), nan(int(batch.h_off[-1]))
+        self.u = nan(nx)
+        if w_c is not None:
+            wc = np.empty(nc)
+            for k in range(K):
+                wc[batch.c_off[k]:batch.c_off[k + 1]] = w_c[k]
+            self.wc, self.wf = d(wc), d(w_f)
+
+    def eval(self, what=None, stream=None):
+        A = self.A
+        A.acopf_batch_eval(self.b, self.x, self.sigma, self.lam, self.f, self.gf, self.c,
+                           self.jv, self.hv, A.ACOPF_ALL if what is None else what, stream)
+
+    def vjp(self):
+        self.A.acopf_batch_vjp(self.b, self.x, self.wf, self.wc, self.u)
+
+    def instance(self, k):
+        b = self.b
+        h = lambda t, o: t[int(o[k]):int(o[k + 1])].cpu().numpy()
+        out = {"f": float(self.f[k].cpu()), "grad_f": h(self.gf, b.x_off), "c": h(self.c, b.c_off),
+               "jac_val": h(self.jv, b.j_off), "hess_val": h(self.hv, b.h_off)}
+        if hasattr(self, "wc"):
+            out["u"] = h(self.u, b.x_off)
+        return out
+
+
+def plain(A, net, it, w_f=None, w_c=None):
+    torch = _t()
+    d = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64), device="cuda")
+    z = lambda n: torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+    f, gf, c, jv, hv = z(1), z(net.n), z(net.m), z(net.nnz_jac), z(net.nnz_hess)
+    A.acopf_eval_all(net, d(it.x), it.sigma, d(it.lam), f, gf, c, jv, hv)
+    out = {"f": float(f.cpu()[0]), "grad_f": gf.cpu().numpy(), "c": c.cpu().numpy(),
+           "jac_val": jv.cpu().numpy(), "hess_val": hv.cpu().numpy()}
+    if w_c is not None:
+        u = z(net.n)
+        A.acopf_vjp(net, d(it.x), w_f, d(w_c), u)
+        out["u"] = u.cpu().numpy()
+    return out
+
+
+def same(a, b, tag):
+    for k in a:
+        np.testing.assert_array_equal(np.asarray(a[k]), np.asarray(b[k]), err_msg=f"{tag}:{k}")
+
+
+@pytest.fixture(scope="module")
+def small_n1():
+    os_ = S.config2(0, nb=300, nl=450, count=40)
+    rng = np.random.default_rng(5)
+    w_c = [rng.standard_normal(it.lam.shape) for it in os_.iterates]
+    w_f = rng.standard_normal(len(w_c))
+    return os_, w_f, w_c
+
+
+def _nets(A, os_):
+    base = A.acopf_net_create(os_.base)
+    return base, [A.acopf_net_create_outage(base, int(l)) for l in os_.outages]
+
+
+def test_batch_equals_plain_and_oracle(gpu_lib, small_n1):
+    from paper_2203_10587_amd import acopf as A
+    os_, w_f, w_c = small_n1
+    base, nets = _nets(A, os_)
+    b = A.acopf_batch_create(nets)
+    P = Packed(A, b, os_.iterates, w_f, w_c)
+    P.eval()
+    P.vjp()
+    _t().cuda.synchronize()
+    for k in range(len(nets)):
+        log(f"[batch vs plain] instance {k} outage {int(os_.outages[k])}")
+        got = P.instance(k)
+        ref_plain = plain(A, nets[k], os_.iterates[k], float(w_f[k]), w_c[k])
+        same(got, ref_plain, f"inst{k}")
+        if k % 8 == 0:
+            g2, it = S.config2_instance(os_, k)
+            compare_outputs(f"n1-{k}", got, oracle_all(g2, it, float(w_f[k]), w_c[k]))
+
+
+def test_schedules_bitwise_identical(gpu_lib, small_n1):
+    from paper_2203_10587_amd import acopf as A
+    from paper_2203_10587_amd import tune
+    os_, _, _ = small_n1
+    base, nets = _nets(A, os_)
+    ref = None
+    for cand in tune.CANDIDATES + [dict(tune.DEFAULT, no_graph=1)]:
+        log(f"[schedule] {cand}")
+        b = A.acopf_batch_create(nets, **cand)
+        P = Packed(A, b, os_.iterates)
+        P.eval()
+        _t().cuda.synchronize()
+        outs = [P.instance(k) for k in (0, 17, 39)]
+        if ref is None:
+            ref = outs
+        else:
+            for k, (a, r) in enumerate(zip(outs, ref)):
+                same(a, r, f"{cand}:{k}")
+        b.close()
+
+
+def test_batch_variants_match_full(gpu_lib, small_n1):
+    from paper_2203_10587_amd import acopf as A
+    os_, _, _ = small_n1
+    base, nets = _nets(A, os_)
+    b = A.acopf_batch_create(nets)
+    full = Packed(A, b, os_.iterates)
+    full.eval()
+    _t().cuda.synchronize()
+    ref = [full.instance(k) for k in range(0, 40, 13)]
+    for what, keys in ((A.ACOPF_J, ["jac_val"]), (A.ACOPF_H, ["hess_val"]),
+                       (A.ACOPF_F | A.ACOPF_GRADF | A.ACOPF_C, ["f", "grad_f", "c"]),
+                       (A.ACOPF_C | A.ACOPF_H, ["c", "hess_val"])):
+        P = Packed(A, b, os_.iterates)
+        P.eval(what)
+        _t().cuda.synchronize()
+        for i, k in enumerate(range(0, 40, 13)):
+            got = P.instance(k)
+            for key in keys:
+                np.testing.assert_array_equal(np.asarray(got[key]), np.asarray(ref[i][key]),
+                                              err_msg=f"what={what} {key}")
+
+
+def test_graph_replays_match_eager(gpu_lib, small_n1):
+    """Replay the captured graph several times with eager work and
+    synchronisations in between; every replay equals the eager launch."""
+    from paper_2203_10587_amd import acopf as A
+    torch = _t()
+    os_, _, _ = small_n1
+    base, nets = _nets(A, os_)
+    eager_b = A.acopf_batch_create(nets, no_graph=1)
+    E = Packed(A, eager_b, os_.iterates)
+    E.eval()
+    torch.cuda.synchronize()
+    ref = [E.instance(k) for k in range(40)]
+    gb = A.acopf_batch_create(nets)
+    G = Packed(A, gb, os_.iterates)
+    for rep in range(4):
+        for t in (G.f, G.gf, G.c, G.jv, G.hv):
+            t.fill_(np.nan)
+        G.eval()
+        junk = torch.randn(1 << 20, dtype=torch.float64, device="cuda")
+        _ = (junk * 2.0).sum().item()
+        E.eval()  # eager launch of the same kernel between replays
+        torch.cuda.synchronize()
+        for k in range(40):
+            same(G.instance(k), ref[k], f"replay{rep}:{k}")
+    # a second buffer set goes through its own cached graph
+    G2 = Packed(A, gb, os_.iterates)
+    G2.eval()
+    torch.cuda.synchronize()
+    same(G2.instance(5), ref[5], "second-buffers")
+
+
+def test_config2_full_size(gpu_lib):
+    """1,000 N-1 outages of the 2,000-bus grid in one launch: sampled
+    instances against the oracle and against the plain path; the
+    angle-reference property (theta-columns of every J row sum to zero) on
+    all instances."""
+    from paper_2203_10587_amd import acopf as A
+    os_ = S.config2(0)
+    base, nets = _nets(A, os_)
+    b = A.acopf_batch_create(nets)
+    P = Packed(A, b, os_.iterates)
+    P.eval()
+    _t().cuda.synchronize()
+    for k in (0, 1, 499, 998, 999):
+        log(f"[config2] oracle instance {k}")
+        g2, it = S.config2_instance(os_, k)
+        got = P.instance(k)
+        compare_outputs(f"c2-{k}", got, oracle_all(g2, it))
+        same(got, plain(A, nets[k], it), f"c2 plain {k}")
+    jv = P.jv.cpu().numpy()
+    assert np.all(np.isfinite(jv)) and np.all(np.isfinite(P.hv.cpu().numpy()))
+    for k in range(0, 1000, 37):
+        jp, jc, hp, hc = A.acopf_pattern(nets[k])
+        vals = jv[int(b.j_off[k]):int(b.j_off[k + 1])]
+        nb = os_.base.nbus
+        rows = np.repeat(np.arange(len(jp) - 1), np.diff(jp))
+        th = jc < nb
+        sums = np.bincount(rows[th], weights=vals[th], minlength=len(jp) - 1)
+        scale = np.maximum.reduceat(np.abs(vals), jp[:-1])
+        assert np.all(np.abs(sums) <= 1e-12 * scale * 8), k
+
+
+def test_config3_uneven_subset(gpu_lib):
+    """The uneven scenario workload: a 64-instance draw spanning the size
+    range, batched with VJP; smallest, median and largest instances against
+    the oracle."""
+    from paper_2203_10587_amd import acopf as A
+    sizes = S.config3_sizes(0)
+    order = np.argsort(sizes)
+    pick = sorted(set(order[::8].tolist()) | {int(order[0]), int(order[-1])})
+    inst = S.config3(0, only=pick)
+    nets = [A.acopf_net_create(g) for _, g, _ in inst]
+    rng = np.random.default_rng(9)
+    w_c = [rng.standard_normal(g.m) for _, g, _ in inst]
+    w_f = rng.standard_normal(len(inst))
+    b = A.acopf_batch_create(nets)
+    P = Packed(A, b, [it for _, _, it in inst], w_f, w_c)
+    P.eval()
+    P.vjp()
+    _t().cuda.synchronize()
+    sz = [g.nbus for _, g, _ in inst]
+    chk = {int(np.argmin(sz)), int(np.argmax(sz)), int(np.argsort(sz)[len(sz) // 2])}
+    for i in sorted(chk):
+        k, g, it = inst[i]
+        log(f"[config3] instance {k} nb={g.nbus}")
+        compare_outputs(f"c3-{k}", P.instance(i), oracle_all(g, it, float(w_f[i]), w_c[i]))
