@@ -188,7 +188,7 @@ int acopf_eval_all(acopf_net net, const double* x, double sigma, const double* l
 
 /* Tile/schedule configuration chosen by the autotuner (or fixed by hand). */
 typedef struct {
-  int32_t tile_be;    /* branch ends per bus tile: 128, 256 or 512        */
+  int32_t tile_be;    /* branch ends per bus tile: 64, 128, 256 or 512    */
   int32_t grid_mult;  /* workgroups per CU for the persistent grid; 0 = one
                          workgroup per tile (no persistence)               */
   int32_t xcd_group;  /* 1 = map each instance's tiles onto one XCD        */
@@ -198,7 +198,7 @@ typedef struct {
 /* Build a batch over `count` nets (they cannot be destroyed while the batch
  * exists): per-instance offsets, the XCD-aware tile list and the device
  * descriptor table.  `sched` may be NULL for the default schedule
- * {128, 0, 1, 0}.  Errors: EINVAL (also when a bus exceeds the tile
+ * {256, 0, 1, 0}.  Errors: EINVAL (also when a bus exceeds the tile
  * capacity of the schedule), ENOMEM, EHIP. */
 int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* sched,
                        acopf_batch* out);
@@ -220,6 +220,31 @@ int acopf_batch_eval(acopf_batch batch, const double* x, const double* sigma,
 /* Batched VJP: u_k = w_f[k] grad f_k + J_k' w_c_k for every instance. */
 int acopf_batch_vjp(acopf_batch batch, const double* x, const double* w_f, const double* w_c,
                     double* u, hipStream_t stream);
+
+/* As acopf_batch_eval, for the instances [first, first + count) only (same
+ * packed buffers and offsets; other instances' outputs are not touched).
+ * Launched directly, not through a graph: the window changes from call to
+ * call, as it does for a continuously batched request stream.  Concurrent
+ * calls on one batch must use disjoint windows.  Errors: EINVAL (empty or
+ * out-of-range window, null outputs as in acopf_batch_eval), EHIP. */
+int acopf_batch_eval_range(acopf_batch batch, int32_t first, int32_t count, const double* x,
+                           const double* sigma, const double* lambda, double* f,
+                           double* grad_f, double* c, double* jac_val, double* hess_val,
+                           unsigned what, hipStream_t stream);
+
+/* Random iterates for the instances [first, first + count), drawn on the
+ * device for a served request stream (the request carries only a seed).
+ * Counter-based: stream element j of instance k is
+ *   u = (splitmix64(seeds[k] + (j + 1) * 0x9E3779B97F4A7C15) >> 11) * 2^-53
+ * with the SplitMix64 output function of Steele, Lea and Flood (2014).
+ * x: theta = -0.2 + 0.4 u, v = 0.95 + 0.1 u, Pg = pmin + (pmax - pmin) u,
+ * Qg = qmin + (qmax - qmin) u, from elements 0 .. n-1 in x order; lambda_r is
+ * the Box-Muller normal sqrt(-2 ln(1 - u1)) cos(2 pi u2) of elements
+ * n + 2r and n + 2r + 1.  seeds: DEVICE array indexed by instance (the batch's
+ * count entries); x and lambda: the packed DEVICE buffers.  Errors: EINVAL, EHIP. */
+int acopf_batch_draw_iterates(acopf_batch batch, int32_t first, int32_t count,
+                              const uint64_t* seeds, double pmin, double pmax, double qmin,
+                              double qmax, double* x, double* lambda, hipStream_t stream);
 
 #ifdef __cplusplus
 }

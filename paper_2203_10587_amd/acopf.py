@@ -80,6 +80,10 @@ _SIGS = {
     "acopf_batch_offsets": (C.c_int, [C.c_void_p, _i64p, _i64p, _i64p, _i64p]),
     "acopf_batch_eval": (C.c_int, [C.c_void_p] + [C.c_void_p] * 8 + [C.c_uint, C.c_void_p]),
     "acopf_batch_vjp": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4 + [C.c_void_p]),
+    "acopf_batch_eval_range": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 8
+                               + [C.c_uint, C.c_void_p]),
+    "acopf_batch_draw_iterates": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+                                  + [C.c_double] * 4 + [C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 
@@ -340,3 +344,28 @@ def acopf_batch_vjp(b: Batch, x, w_f, w_c, u, stream=None):
     _check(lib().acopf_batch_vjp(
         b.handle, _ptr(x, int(b.x_off[-1]), "x"), _ptr(w_f, k, "w_f"),
         _ptr(w_c, int(b.c_off[-1]), "w_c"), _ptr(u, int(b.x_off[-1]), "u"), _stream(stream)))
+
+
+def acopf_batch_eval_range(b: Batch, first: int, count: int, x, sigma, lam, f, grad_f, c,
+                           jac_val, hess_val, what: int = ACOPF_ALL, stream=None):
+    k = b.count
+    _check(lib().acopf_batch_eval_range(
+        b.handle, int(first), int(count), _ptr(x, int(b.x_off[-1]), "x"), _ptr(sigma, k, "sigma"),
+        _ptr(lam, int(b.c_off[-1]), "lambda"), _ptr(f, k, "f"),
+        _ptr(grad_f, int(b.x_off[-1]), "grad_f"), _ptr(c, int(b.c_off[-1]), "c"),
+        _ptr(jac_val, int(b.j_off[-1]), "jac_val"), _ptr(hess_val, int(b.h_off[-1]), "hess_val"),
+        C.c_uint(what), _stream(stream)))
+
+
+def acopf_batch_draw_iterates(b: Batch, first: int, count: int, seeds, bounds, x, lam,
+                              stream=None):
+    """seeds: int64/uint64 CUDA tensor of b.count entries (bit pattern used);
+    bounds: (pmin, pmax, qmin, qmax)."""
+    import torch
+    if not (isinstance(seeds, torch.Tensor) and seeds.is_cuda and seeds.dtype in (torch.int64,)
+            and seeds.is_contiguous() and seeds.numel() == b.count):
+        raise TypeError("seeds: expected a contiguous int64 CUDA tensor of batch-count entries")
+    pmin, pmax, qmin, qmax = (float(v) for v in bounds)
+    _check(lib().acopf_batch_draw_iterates(
+        b.handle, int(first), int(count), C.c_void_p(seeds.data_ptr()), pmin, pmax, qmin, qmax,
+        _ptr(x, int(b.x_off[-1]), "x"), _ptr(lam, int(b.c_off[-1]), "lambda"), _stream(stream)))

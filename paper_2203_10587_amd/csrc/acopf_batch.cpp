@@ -45,6 +45,9 @@ struct acopf_batch_s {
   uint32_t* d_ticket = nullptr;
   int ntiles = 0;
   int grid = 0;  // 0: one workgroup per tile
+  acopf::Tile* d_tiles_inst = nullptr;  // the same tiles, instance after instance
+  std::vector<int32_t> inst_tile_off;   // count + 1
+  int max_len = 0;                      // max n + m over instances
   hipStream_t cap_stream = nullptr;
   std::list<std::pair<acopf::GraphKey, hipGraphExec_t>> graphs;  // most recent first
 };
@@ -74,6 +77,13 @@ void free_batch(acopf_batch_s* b) {
   (void)hipSetDevice(cur);
   for (acopf_net n : b->nets) n->refs.fetch_sub(1);
   delete b;
+}
+
+unsigned variant_of(unsigned what) {
+  if ((what & ~unsigned(ACOPF_F | ACOPF_GRADF | ACOPF_C)) == 0) return K_FG;
+  if (what == ACOPF_J) return K_J;
+  if (what == ACOPF_H) return K_H;
+  return K_ALL;
 }
 
 int run_batch(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStream_t stream) {
@@ -141,7 +151,7 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
   acopf_sched s{kDefaultTileBe, 0, 1, 0};
   if (sched) s = *sched;
   TileCaps caps;
-  if (!caps_for(s.tile_be, &caps)) return fail(ACOPF_EINVAL, "tile_be must be 64, 128 or 256");
+  if (!caps_for(s.tile_be, &caps)) return fail(ACOPF_EINVAL, "tile_be must be 64, 128, 256 or 512");
   if (s.xcd_group < 0 || s.xcd_group > 1 || s.no_graph < 0 || s.no_graph > 1)
     return fail(ACOPF_EINVAL, "xcd_group and no_graph must be 0 or 1");
   if (s.grid_mult < 0 || s.grid_mult > 64) return fail(ACOPF_EINVAL, "grid_mult must be in [0, 64]");
@@ -174,42 +184,54 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
       b->ho[k + 1] = b->ho[k] + d.nnz_hess;
       fpo[k + 1] = fpo[k] + nets[k]->base->topo.nchunks;
     }
-    // per-base tile and work lists for this schedule (outage children share their base's)
+    // per-base schedule (outage children share their base's)
     struct PerBase {
-      std::vector<Tile> tiles;
-      std::vector<WorkItem> work;
-      size_t work_off = 0;  // into the batch's work array
+      Schedule sch;
+      size_t work_off = 0;   // into the batch's work array
+      size_t slot_off = 0;   // into the batch's slot array
     };
     std::map<const Base*, PerBase> per_base;
-    size_t work_total = 0;
+    size_t work_total = 0, slot_total = 0;
     for (int k = 0; k < count; ++k) {
       const Base* B = nets[k]->base.get();
       if (per_base.count(B)) continue;
       PerBase pb;
-      int counts[2];
-      int rc = make_tiles(B->topo, s.tile_be, &pb.tiles, &pb.work, counts);
+      int rc = make_tiles(B->topo, s.tile_be, &pb.sch);
       if (rc) {
         free_batch(b);
         return rc;
       }
       pb.work_off = work_total;
-      work_total += pb.work.size();
+      pb.slot_off = slot_total;
+      work_total += pb.sch.work.size();
+      slot_total += pb.sch.slots.size();
       per_base.emplace(B, std::move(pb));
     }
     // XCD queues, largest instances first (LPT on tile counts)
     std::vector<int> order(count);
     std::iota(order.begin(), order.end(), 0);
-    auto ntile = [&](int k) { return int(per_base[nets[k]->base.get()].tiles.size()); };
+    auto ntile = [&](int k) { return int(per_base[nets[k]->base.get()].sch.tiles.size()); };
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return ntile(a) > ntile(c); });
     std::vector<std::vector<Tile>> queue(s.xcd_group ? kXcds : 1);
     std::vector<int64_t> load(queue.size(), 0);
     for (int k : order) {
       const size_t qi = std::min_element(load.begin(), load.end()) - load.begin();
-      for (Tile t : per_base[nets[k]->base.get()].tiles) {
+      for (Tile t : per_base[nets[k]->base.get()].sch.tiles) {
         t.inst = k;
         queue[qi].push_back(t);
       }
       load[qi] += ntile(k);
+    }
+    std::vector<Tile> tiles_inst;
+    b->inst_tile_off.assign(count + 1, 0);
+    for (int k = 0; k < count; ++k) {
+      for (Tile t : per_base[nets[k]->base.get()].sch.tiles) {
+        t.inst = k;
+        tiles_inst.push_back(t);
+      }
+      b->inst_tile_off[k + 1] = int32_t(tiles_inst.size());
+      const acopf_dims& d = nets[k]->dims;
+      b->max_len = std::max<int>(b->max_len, int(d.n + d.m));
     }
     std::vector<Tile> tiles;
     size_t total = 0;
@@ -231,10 +253,12 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     // device table, tiles, work items, scratch
     const size_t s_table = align_up(size_t(count) * sizeof(InstOff));
     const size_t s_tiles = align_up(tiles.size() * sizeof(Tile));
+    const size_t s_tinst = align_up(tiles_inst.size() * sizeof(Tile));
     const size_t s_work = align_up(std::max<size_t>(work_total, 1) * sizeof(WorkItem));
+    const size_t s_slot = align_up(std::max<size_t>(slot_total, 1) * sizeof(int2));
     const size_t s_fpart = align_up(size_t(fpo[count]) * sizeof(double));
     const size_t s_ticket = align_up(size_t(count) * sizeof(uint32_t));
-    e = hipMalloc(&b->mem, s_table + s_tiles + s_work + s_fpart + s_ticket);
+    e = hipMalloc(&b->mem, s_table + s_tiles + s_work + s_slot + s_fpart + s_ticket + s_tinst);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       b->mem = nullptr;
@@ -245,12 +269,17 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     b->d_table = reinterpret_cast<InstOff*>(base);
     b->d_tiles = reinterpret_cast<Tile*>(base + s_table);
     WorkItem* d_work = reinterpret_cast<WorkItem*>(base + s_table + s_tiles);
-    b->d_fpart = reinterpret_cast<double*>(base + s_table + s_tiles + s_work);
-    b->d_ticket = reinterpret_cast<uint32_t*>(base + s_table + s_tiles + s_work + s_fpart);
+    int2* d_slot = reinterpret_cast<int2*>(base + s_table + s_tiles + s_work);
+    b->d_fpart = reinterpret_cast<double*>(base + s_table + s_tiles + s_work + s_slot);
+    b->d_ticket =
+        reinterpret_cast<uint32_t*>(base + s_table + s_tiles + s_work + s_slot + s_fpart);
+    b->d_tiles_inst =
+        reinterpret_cast<Tile*>(base + s_table + s_tiles + s_work + s_slot + s_fpart + s_ticket);
     std::vector<InstOff> table(count);
     for (int k = 0; k < count; ++k) {
       InstOff I = net_inst(nets[k]);
       I.work = d_work + per_base[nets[k]->base.get()].work_off;
+      I.slots = d_slot + per_base[nets[k]->base.get()].slot_off;
       I.xo = b->xo[k];
       I.co = b->co[k];
       I.jo = b->jo[k];
@@ -263,10 +292,17 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     if (e == hipSuccess)
       e = hipMemcpy(b->d_tiles, tiles.data(), tiles.size() * sizeof(Tile), hipMemcpyHostToDevice);
     for (auto& kv : per_base) {
-      if (e != hipSuccess || kv.second.work.empty()) continue;
-      e = hipMemcpy(d_work + kv.second.work_off, kv.second.work.data(),
-                    kv.second.work.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+      const Schedule& sc = kv.second.sch;
+      if (e == hipSuccess && !sc.work.empty())
+        e = hipMemcpy(d_work + kv.second.work_off, sc.work.data(), sc.work.size() * sizeof(WorkItem),
+                      hipMemcpyHostToDevice);
+      if (e == hipSuccess && !sc.slots.empty())
+        e = hipMemcpy(d_slot + kv.second.slot_off, sc.slots.data(), sc.slots.size() * sizeof(int2),
+                      hipMemcpyHostToDevice);
     }
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_tiles_inst, tiles_inst.data(), tiles_inst.size() * sizeof(Tile),
+                    hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(b->d_fpart, 0, s_fpart + s_ticket);
     if (e != hipSuccess) {
       free_batch(b);
@@ -319,14 +355,60 @@ int acopf_batch_eval(acopf_batch b, const double* x, const double* sigma, const 
   bufs.hess = (what & ACOPF_H) ? hess_val : nullptr;
   bufs.fpart = b->d_fpart;
   bufs.ticket = b->d_ticket;
-  unsigned variant = K_ALL;
-  if ((what & ~unsigned(ACOPF_F | ACOPF_GRADF | ACOPF_C)) == 0)
-    variant = K_FG;
-  else if (what == ACOPF_J)
-    variant = K_J;
-  else if (what == ACOPF_H)
-    variant = K_H;
-  return run_batch(b, variant, bufs, stream);
+  return run_batch(b, variant_of(what), bufs, stream);
+}
+
+int acopf_batch_eval_range(acopf_batch b, int32_t first, int32_t count, const double* x,
+                           const double* sigma, const double* lambda, double* f, double* grad_f,
+                           double* c, double* jac_val, double* hess_val, unsigned what,
+                           hipStream_t stream) {
+  if (!b || !x) return fail(ACOPF_EINVAL, "null batch or x");
+  if (first < 0 || count < 1 || first > b->count - count)
+    return fail(ACOPF_EINVAL, "instance window out of range");
+  if (what & ~unsigned(ACOPF_ALL)) return fail(ACOPF_EINVAL, "unknown bits in what");
+  if (((what & ACOPF_F) && !f) || ((what & ACOPF_GRADF) && !grad_f) || ((what & ACOPF_C) && !c) ||
+      ((what & ACOPF_J) && !jac_val) ||
+      ((what & ACOPF_H) && (!hess_val || !lambda || !sigma)))
+    return fail(ACOPF_EINVAL, "a selected output (or lambda/sigma for ACOPF_H) is null");
+  if (!what) return ACOPF_OK;
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != b->device) return fail(ACOPF_EINVAL, "batch lives on another device");
+  Bufs bufs{};
+  bufs.x = x;
+  bufs.lam = (what & ACOPF_H) ? lambda : nullptr;
+  bufs.sigma = (what & ACOPF_H) ? sigma : nullptr;
+  bufs.f = (what & ACOPF_F) ? f : nullptr;
+  bufs.gradf = (what & ACOPF_GRADF) ? grad_f : nullptr;
+  bufs.c = (what & ACOPF_C) ? c : nullptr;
+  bufs.jac = (what & ACOPF_J) ? jac_val : nullptr;
+  bufs.hess = (what & ACOPF_H) ? hess_val : nullptr;
+  bufs.fpart = b->d_fpart;
+  bufs.ticket = b->d_ticket;
+  const int t0 = b->inst_tile_off[first], t1 = b->inst_tile_off[first + count];
+  const InstOff none{};
+  e = launch_eval(variant_of(what), b->sched.tile_be, bufs, b->d_table, none, b->d_tiles_inst + t0,
+                  t1 - t0, 0, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  return ACOPF_OK;
+}
+
+int acopf_batch_draw_iterates(acopf_batch b, int32_t first, int32_t count, const uint64_t* seeds,
+                              double pmin, double pmax, double qmin, double qmax, double* x,
+                              double* lambda, hipStream_t stream) {
+  if (!b || !seeds || !x || !lambda) return fail(ACOPF_EINVAL, "null argument");
+  if (first < 0 || count < 1 || first > b->count - count)
+    return fail(ACOPF_EINVAL, "instance window out of range");
+  if (count > 65535) return fail(ACOPF_EINVAL, "at most 65535 instances per draw");
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != b->device) return fail(ACOPF_EINVAL, "batch lives on another device");
+  e = launch_draw(b->d_table, first, count, b->max_len, seeds, pmin, pmax, qmin, qmax, x, lambda,
+                  stream);
+  if (e != hipSuccess) return hip_fail(e, "draw kernel launch");
+  return ACOPF_OK;
 }
 
 int acopf_batch_vjp(acopf_batch b, const double* x, const double* w_f, const double* w_c,

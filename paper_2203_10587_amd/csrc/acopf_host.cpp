@@ -268,20 +268,36 @@ void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,
   for (int k = 0; k < ng; ++k) hp->push_back(int32_t(hc->size()));
 }
 
-int make_tiles(const Topology& T, int tile_be, std::vector<Tile>* out, std::vector<WorkItem>* work,
-               int counts[2]) {
+// Slot-map entry: signed sum of record `field` over branch ends [ea, ea+cnt).
+static int2 slot(int ea, int cnt, int field, int neg, int kind, int bl) {
+  return make_int2(ea | (cnt << 16), field | (neg << 4) | (kind << 5) | (bl << 8));
+}
+
+int make_tiles(const Topology& T, int tile_be, Schedule* S) {
   TileCaps caps;
   if (!caps_for(tile_be, &caps)) return fail(ACOPF_EINVAL, "unsupported tile size");
-  out->clear();
-  work->clear();
+  S->tiles.clear();
+  S->work.clear();
+  S->slots.clear();
   // adjacency position of each branch end
   std::vector<int32_t> pos_from(T.nl), pos_to(T.nl);
   for (int e = 0; e < int(T.be.size()); ++e) {
     const int code = T.be[e];
     ((code & 1) ? pos_to : pos_from)[code >> 1] = e;
   }
+  auto far = [&](int e) {
+    const int code = T.be[e];
+    const int2 ft = T.ft[code >> 1];
+    return (code & 1) ? ft.x : ft.y;
+  };
   std::vector<int32_t> seen(T.nl, -1);
   std::vector<int32_t> items;
+  struct Grp {
+    int j, ea, cnt;
+  };
+  std::vector<Grp> grp;
+  std::vector<int2> sT, sV;
+  bool tiler_error = false;
   auto close = [&](int b0, int b1) {
     const int e0 = T.be_ptr[b0], e1 = T.be_ptr[b1];
     items.clear();
@@ -293,41 +309,147 @@ int make_tiles(const Topology& T, int tile_be, std::vector<Tile>* out, std::vect
       }
     }
     std::sort(items.begin(), items.end());
-    const int w0 = int(work->size());
+    const int w0 = int(S->work.size());
     for (int l : items) {
       const int f = T.ft[l].x, t = T.ft[l].y;
       const uint32_t sf = (f >= b0 && f < b1) ? uint32_t(pos_from[l] - e0) : kNoSlot;
       const uint32_t st = (t >= b0 && t < b1) ? uint32_t(pos_to[l] - e0) : kNoSlot;
-      work->push_back({l, f, t, sf | (st << 16)});
+      S->work.push_back({l, f, t, sf | (st << 16)});
     }
-    out->push_back({0, TILE_BUS, b0, b1, e0, e1 - e0, w0, int(work->size()) - w0});
+    // slot map: J P rows (shared by the Q rows), then H theta rows, then H v rows
+    const int sm0 = int(S->slots.size());
+    sT.clear();
+    sV.clear();
+    for (int i = b0; i < b1; ++i) {
+      const int bl = i - b0;
+      const int ea = T.be_ptr[i] - e0, deg = T.be_ptr[i + 1] - T.be_ptr[i];
+      grp.clear();
+      for (int e = T.be_ptr[i]; e < T.be_ptr[i + 1]; ++e) {
+        const int j = far(e);
+        if (grp.empty() || grp.back().j != j) grp.push_back({j, e - e0, 0});
+        grp.back().cnt++;
+      }
+      // members of {i} u N(i) ascending; the diagonal sits before the first j > i
+      std::vector<Grp> mem;
+      bool self = false;
+      for (const Grp& g : grp) {
+        if (!self && g.j > i) {
+          mem.push_back({i, ea, deg});
+          self = true;
+        }
+        mem.push_back(g);
+      }
+      if (!self) mem.push_back({i, ea, deg});
+      for (const Grp& g : mem)  // theta columns
+        S->slots.push_back(g.j == i ? slot(g.ea, g.cnt, 0, 0, SK_SUM, bl)
+                                    : slot(g.ea, g.cnt, 0, 1, SK_SUM, bl));
+      for (const Grp& g : mem)  // v columns
+        S->slots.push_back(g.j == i ? slot(g.ea, g.cnt, 1, 0, SK_JDIAG_V, bl)
+                                    : slot(g.ea, g.cnt, 2, 0, SK_SUM, bl));
+      for (int g = T.gen_ptr[i]; g < T.gen_ptr[i + 1]; ++g)
+        S->slots.push_back(slot(0, 0, 0, 0, SK_GEN, bl));
+      for (const Grp& g : mem)  // H theta row: j <= i
+        if (g.j <= i) sT.push_back(g.j == i ? slot(g.ea, g.cnt, 0, 0, SK_SUM, bl)
+                                            : slot(g.ea, g.cnt, 0, 1, SK_SUM, bl));
+      for (const Grp& g : mem)  // H v row: theta_j for all j
+        sV.push_back(g.j == i ? slot(g.ea, g.cnt, 1, 0, SK_SUM, bl)
+                              : slot(g.ea, g.cnt, 1, 1, SK_SUM, bl));
+      for (const Grp& g : mem)  // H v row: v_j for j <= i
+        if (g.j <= i) sV.push_back(g.j == i ? slot(g.ea, g.cnt, 2, 0, SK_HDIAG_V, bl)
+                                            : slot(g.ea, g.cnt, 3, 0, SK_SUM, bl));
+    }
+    const int nP = int(S->slots.size()) - sm0;
+    S->slots.insert(S->slots.end(), sT.begin(), sT.end());
+    S->slots.insert(S->slots.end(), sV.begin(), sV.end());
+    const int4 r0 = T.rows[b0], r1 = T.rows[b1];
+    // the slot map must cover exactly the tile's row segments, and every
+    // record range must lie inside the tile
+    bool ok = nP == r1.x - r0.x && int(sT.size()) == r1.z - r0.z && int(sV.size()) == r1.w - r0.w;
+    for (size_t k = sm0; ok && k < S->slots.size(); ++k) {
+      const int2 en = S->slots[k];
+      ok = (en.x & 0xFFFF) + (en.x >> 16) <= e1 - e0 && (en.y >> 8) < b1 - b0;
+    }
+    if (!ok) {
+      tiler_error = true;
+      return;
+    }
+    Tile tl{};
+    tl.inst = 0;
+    tl.kind_aux = TILE_BUS;
+    tl.a0 = b0;
+    tl.a1 = b1;
+    tl.e0 = e0;
+    tl.ne = e1 - e0;
+    tl.w0 = w0;
+    tl.nw = int(S->work.size()) - w0;
+    tl.sm0 = sm0;
+    tl.nP = nP;
+    tl.nT = int(sT.size());
+    tl.nV = int(sV.size());
+    tl.jP0 = r0.x;
+    tl.jQ0 = r0.y;
+    tl.hT0 = r0.z;
+    tl.hV0 = r0.w;
+    S->tiles.push_back(tl);
   };
-  int b0 = 0, cur_be = 0, cur_st = 0;
+  int b0 = 0, cur_be = 0;
   for (int i = 0; i < T.nb; ++i) {
     const int d = T.be_ptr[i + 1] - T.be_ptr[i];
-    const int a = T.acnt[i].x, lo = T.acnt[i].y, g = T.gen_ptr[i + 1] - T.gen_ptr[i];
-    const int st = 2 * (2 * a + g) + (lo + 1) + (a + lo + 1);
-    if (d > caps.be || st > caps.stage)
+    if (d > caps.be)
       return fail(ACOPF_EINVAL, "bus " + std::to_string(i) + " has " + std::to_string(d) +
-                                    " branch ends and " + std::to_string(st) +
-                                    " row entries; a bus tile of this schedule holds at most " +
-                                    std::to_string(caps.be) + " and " + std::to_string(caps.stage));
-    if (i > b0 && (cur_be + d > caps.be || cur_st + st > caps.stage)) {
+                                    " branch ends; a bus tile of this schedule holds at most " +
+                                    std::to_string(caps.be));
+    if (i > b0 && (cur_be + d > caps.be || i - b0 >= caps.nbus)) {
       close(b0, i);
       b0 = i;
       cur_be = 0;
-      cur_st = 0;
     }
     cur_be += d;
-    cur_st += st;
   }
   close(b0, T.nb);
-  counts[0] = int(out->size());
-  for (int c = 0; c < T.nchunks; ++c)
-    out->push_back({0, (c << 2) | TILE_GEN, c * kGenChunk, std::min(T.ng, (c + 1) * kGenChunk), 0, 0,
-                    0, 0});
-  counts[1] = int(out->size()) - counts[0];
+  if (tiler_error) return fail(ACOPF_EINVAL, "internal: slot map does not match the pattern");
+  S->counts[0] = int(S->tiles.size());
+  for (int c = 0; c < T.nchunks; ++c) {
+    Tile tl{};
+    tl.kind_aux = (c << 2) | TILE_GEN;
+    tl.a0 = c * kGenChunk;
+    tl.a1 = std::min(T.ng, (c + 1) * kGenChunk);
+    S->tiles.push_back(tl);
+  }
+  S->counts[1] = int(S->tiles.size()) - S->counts[0];
   return ACOPF_OK;
+}
+
+// Base positions of the 8 Jacobian and 4 Hessian slots an outage of a
+// branch without a parallel twin removes (ascending), or INT32_MAX.
+void removed_slots(const Topology& T, int32_t p, int32_t q, int32_t rm, int32_t rj[8],
+                   int32_t rh[4]) {
+  for (int k = 0; k < 8; ++k) rj[k] = INT_MAX;
+  for (int k = 0; k < 4; ++k) rh[k] = INT_MAX;
+  if (!rm) return;
+  auto rank = [&](int i, int j) {  // position of j in the ascending set {i} u N(i)
+    int r = (i < j) ? 1 : 0, prev = -1;
+    for (int e = T.be_ptr[i]; e < T.be_ptr[i + 1]; ++e) {
+      const int code = T.be[e];
+      const int2 ft = T.ft[code >> 1];
+      const int o = (code & 1) ? ft.x : ft.y;
+      if (o != prev) {
+        if (o < j) ++r;
+        prev = o;
+      }
+    }
+    return r;
+  };
+  const int rpq = rank(p, q), rqp = rank(q, p);
+  const int ap = T.acnt[p].x, aq = T.acnt[q].x;
+  const int4 Rp = T.rows[p], Rq = T.rows[q];
+  int32_t j[8] = {Rp.x + rpq, Rp.x + ap + rpq, Rq.x + rqp, Rq.x + aq + rqp,
+                  Rp.y + rpq, Rp.y + ap + rpq, Rq.y + rqp, Rq.y + aq + rqp};
+  int32_t h[4] = {Rq.z + rqp, Rp.w + rpq, Rq.w + rqp, Rq.w + aq + rqp};
+  std::sort(j, j + 8);
+  std::sort(h, h + 4);
+  for (int k = 0; k < 8; ++k) rj[k] = j[k];
+  for (int k = 0; k < 4; ++k) rh[k] = h[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -347,7 +469,7 @@ Base::~Base() {
 
 int upload_base(Base* B) {
   const Topology& T = B->topo;
-  int rc = make_tiles(T, kDefaultTileBe, &B->plain_tiles, &B->plain_work, B->plain_counts);
+  int rc = make_tiles(T, kDefaultTileBe, &B->plain);
   if (rc) return rc;
   struct Part {
     const void* src;
@@ -358,16 +480,15 @@ int upload_base(Base* B) {
       {T.y.data(), T.y.size() * sizeof(BranchY), 0},
       {T.bus.data(), T.bus.size() * sizeof(double4), 0},
       {T.be_ptr.data(), T.be_ptr.size() * sizeof(int32_t), 0},
-      {T.acnt.data(), T.acnt.size() * sizeof(int2), 0},
-      {T.rows.data(), T.rows.size() * sizeof(int4), 0},
       {T.gen_ptr.data(), T.gen_ptr.size() * sizeof(int32_t), 0},
       {T.gen_list.data(), T.gen_list.size() * sizeof(int32_t), 0},
       {T.gen_bus.data(), T.gen_bus.size() * sizeof(int32_t), 0},
       {T.c2.data(), T.c2.size() * sizeof(double), 0},
       {T.c1.data(), T.c1.size() * sizeof(double), 0},
       {T.c0.data(), T.c0.size() * sizeof(double), 0},
-      {B->plain_tiles.data(), B->plain_tiles.size() * sizeof(Tile), 0},
-      {B->plain_work.data(), B->plain_work.size() * sizeof(WorkItem), 0},
+      {B->plain.tiles.data(), B->plain.tiles.size() * sizeof(Tile), 0},
+      {B->plain.work.data(), B->plain.work.size() * sizeof(WorkItem), 0},
+      {B->plain.slots.data(), B->plain.slots.size() * sizeof(int2), 0},
       {nullptr, sizeof(NetDev), 0},
   };
   size_t total = 0;
@@ -396,21 +517,20 @@ int upload_base(Base* B) {
   nd.br_y = static_cast<const BranchY*>(at(0));
   nd.bus = static_cast<const double4*>(at(1));
   nd.be_ptr = static_cast<const int32_t*>(at(2));
-  nd.acnt = static_cast<const int2*>(at(3));
-  nd.rows = static_cast<const int4*>(at(4));
-  nd.gen_ptr = static_cast<const int32_t*>(at(5));
-  nd.gen_list = static_cast<const int32_t*>(at(6));
-  nd.gen_bus = static_cast<const int32_t*>(at(7));
-  nd.gen_c2 = static_cast<const double*>(at(8));
-  nd.gen_c1 = static_cast<const double*>(at(9));
-  nd.gen_c0 = static_cast<const double*>(at(10));
+  nd.gen_ptr = static_cast<const int32_t*>(at(3));
+  nd.gen_list = static_cast<const int32_t*>(at(4));
+  nd.gen_bus = static_cast<const int32_t*>(at(5));
+  nd.gen_c2 = static_cast<const double*>(at(6));
+  nd.gen_c1 = static_cast<const double*>(at(7));
+  nd.gen_c0 = static_cast<const double*>(at(8));
   nd.base_mva = T.base;
   nd.jflow = T.jflow;
   nd.hpg = T.hpg;
-  B->d_tiles = static_cast<Tile*>(at(11));
-  B->d_work = static_cast<WorkItem*>(at(12));
-  B->d_net = static_cast<NetDev*>(at(13));
-  parts[13].src = &nd;
+  B->d_tiles = static_cast<Tile*>(at(9));
+  B->d_work = static_cast<WorkItem*>(at(10));
+  B->d_slots = static_cast<int2*>(at(11));
+  B->d_net = static_cast<NetDev*>(at(12));
+  parts[12].src = &nd;
   for (const Part& p : parts) {
     if (p.bytes == 0) continue;
     e = hipMemcpy(base + p.off, p.src, p.bytes, hipMemcpyHostToDevice);
@@ -502,6 +622,7 @@ int acopf_net_create_outage(acopf_net base, int32_t branch, acopf_net* out) {
     int rc = outage_info(base->base->topo, branch, &net->out_p, &net->out_q, &net->out_rm);
     if (rc) return rc;
     net->out_l = branch;
+    removed_slots(base->base->topo, net->out_p, net->out_q, net->out_rm, net->rj, net->rh);
     net->parent = base;
     rc = net_init_scratch(net.get());
     if (rc) return rc;
@@ -586,10 +707,11 @@ InstOff net_inst(const acopf_net_s* net) {
   InstOff I{};
   I.net = net->base->d_net;
   I.work = net->base->d_work;
+  I.slots = net->base->d_slots;
   I.out_l = net->out_l;
-  I.out_p = net->out_p;
-  I.out_q = net->out_q;
   I.out_rm = net->out_rm;
+  for (int k = 0; k < 8; ++k) I.rj[k] = net->rj[k];
+  for (int k = 0; k < 4; ++k) I.rh[k] = net->rh[k];
   I.k = 0;
   I.fpo = 0;
   return I;
@@ -613,7 +735,7 @@ static int run_plain(const acopf_net_s* net, unsigned variant, Bufs b, bool bus,
   const Base& B = *net->base;
   b.fpart = net->d_fpart;
   b.ticket = net->d_ticket;
-  const int nbu = B.plain_counts[0], ngt = B.plain_counts[1];
+  const int nbu = B.plain.counts[0], ngt = B.plain.counts[1];
   if (!bus && !gen) return ACOPF_OK;
   const int t0 = bus ? 0 : nbu;
   const int t1 = gen ? nbu + ngt : nbu;

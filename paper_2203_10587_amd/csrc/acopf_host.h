@@ -28,6 +28,14 @@ struct Topology {
   int32_t jflow = 0, hpg = 0;
 };
 
+// Tiles, work items and slot map of one schedule (tile size) for a network.
+struct Schedule {
+  std::vector<Tile> tiles;        // [bus tiles][gen tiles]
+  std::vector<WorkItem> work;
+  std::vector<int2> slots;
+  int counts[2] = {0, 0};
+};
+
 // A base network resident on one device; shared by its outage children.
 struct Base {
   Topology topo;
@@ -35,11 +43,10 @@ struct Base {
   void* mem = nullptr;
   size_t bytes = 0;
   NetDev* d_net = nullptr;
-  Tile* d_tiles = nullptr;           // plain-path tiles [bus][gen]
-  WorkItem* d_work = nullptr;        // plain-path work items
-  std::vector<Tile> plain_tiles;
-  std::vector<WorkItem> plain_work;
-  int plain_counts[2] = {0, 0};
+  Tile* d_tiles = nullptr;           // plain-path schedule on the device
+  WorkItem* d_work = nullptr;
+  int2* d_slots = nullptr;
+  Schedule plain;
   ~Base();
 };
 
@@ -49,6 +56,9 @@ struct acopf_net_s {
   std::shared_ptr<acopf::Base> base;
   acopf_net_s* parent = nullptr;
   int32_t out_l = -1, out_p = -1, out_q = -1, out_rm = 0;
+  int32_t rj[8] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX,
+                   INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+  int32_t rh[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
   acopf_dims dims{};
   void* scratch = nullptr;           // f partials + ticket of the plain path
   double* d_fpart = nullptr;
@@ -66,8 +76,9 @@ int outage_info(const Topology& T, int32_t l, int32_t* p, int32_t* q, int32_t* r
 void fill_dims(const Topology& T, int32_t outage, int32_t rm, acopf_dims* d);
 void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,
                    std::vector<int32_t>* jc, std::vector<int32_t>* hp, std::vector<int32_t>* hc);
-int make_tiles(const Topology& T, int tile_be, std::vector<Tile>* out, std::vector<WorkItem>* work,
-               int counts[2]);
+int make_tiles(const Topology& T, int tile_be, Schedule* S);
+void removed_slots(const Topology& T, int32_t p, int32_t q, int32_t rm, int32_t rj[8],
+                   int32_t rh[4]);
 int upload_base(Base* B);
 int net_init_scratch(acopf_net_s* net);
 InstOff net_inst(const acopf_net_s* net);

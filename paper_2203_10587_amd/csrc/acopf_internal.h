@@ -4,12 +4,17 @@
 // device memory; everything about one evaluation instance (which net, which
 // outage, where its slices of the packed buffers start) in one InstOff.
 // Work is cut into tiles of two kinds:
-//   bus tile  a contiguous range of buses: every branch touching them is
-//             evaluated once (a host-built work list names the branch, its
-//             endpoints and the LDS slots of its ends inside the tile); the
-//             tile writes the power-balance rows of c and J, the theta/v rows
-//             of the Hessian (or the VJP's theta/v entries), and the flow-limit
-//             rows of the branches whose from-bus it owns
+//   bus tile  a contiguous range of buses.  A host-built work list names
+//             every branch touching the tile (branch, endpoints, LDS slots of
+//             its ends); each is evaluated once into per-branch-end LDS
+//             records.  A host-built slot map then describes every output
+//             entry of the tile's CSR row segments as a signed sum of a
+//             contiguous range of records (branch ends are sorted by bus and
+//             far bus, so a diagonal entry sums a bus's ends and an
+//             off-diagonal entry the ends of one parallel-branch group), so
+//             one lane computes and stores one output entry.  The tile also
+//             writes the balance rows of c, and the flow-limit rows of the
+//             branches whose from-bus it owns.
 //   gen tile  a fixed chunk of generators: f, grad f, the Pg diagonal of H
 #pragma once
 
@@ -24,10 +29,13 @@ constexpr uint32_t kNoSlot = 0xFFFFu;
 enum TileKind : int32_t { TILE_BUS = 1, TILE_GEN = 2 };
 
 // A unit of work.  Bus tile: buses [a0, a1), branch ends [e0, e0 + ne) of the
-// adjacency, work items [w0, w0 + nw).  Gen tile: generators [a0, a1);
+// adjacency, work items [w0, w0 + nw), slot map [sm0, sm0 + nP + nT + nV) for
+// the J P rows (the J Q rows share it), the H theta rows and the H v rows,
+// whose base starts are jP0, jQ0, hT0, hV0.  Gen tile: generators [a0, a1);
 // kind_aux = (chunk << 2) | kind.
 struct Tile {
   int32_t inst, kind_aux, a0, a1, e0, ne, w0, nw;
+  int32_t sm0, nP, nT, nV, jP0, jQ0, hT0, hV0;
 };
 
 // One branch evaluated by a bus tile: branch id, its from and to bus, and
@@ -36,6 +44,16 @@ struct Tile {
 struct WorkItem {
   int32_t l, f, t;
   uint32_t slots;
+};
+
+// One output entry: value = (-1)^neg * sum of record field `field` over
+// branch ends [ea, ea + cnt) of the tile, plus the bus extra of `kind`.
+//   x = ea | cnt << 16;  y = field | neg << 4 | kind << 5 | bus_local << 8
+enum SlotKind : int32_t {
+  SK_SUM = 0,      // plain signed sum
+  SK_JDIAG_V = 1,  // J diagonal d/dv_i: + 2 gs v_i (P row) or - 2 bs v_i (Q row)
+  SK_GEN = 2,      // generator column: the constant -1
+  SK_HDIAG_V = 3,  // H (v_i, v_i): + 2 (lP_i gs - lQ_i bs)
 };
 
 // Admittances of one branch (pi model, from-side ideal transformer).
@@ -48,8 +66,6 @@ struct NetDev {
   const BranchY* br_y;      // [nl]
   const double4* bus;       // [nb] (pd, qd, gs, bs)
   const int32_t* be_ptr;    // [nb + 1] branch ends of bus i: adjacency positions be_ptr[i] ..
-  const int2* acnt;         // [nb] (|{i} u N(i)|, #distinct neighbours below i)
-  const int4* rows;         // [nb + 1] base starts of (J P row, J Q row, H theta row, H v row)
   const int32_t* gen_ptr;   // [nb + 1] generators at bus i: gen_list[gen_ptr[i] .. gen_ptr[i+1])
   const int32_t* gen_list;  // [ng]
   const int32_t* gen_bus;   // [ng]
@@ -61,13 +77,19 @@ struct NetDev {
   int32_t hpg;              // base start of the Pg rows in H
 };
 
-// One evaluation instance.  Offsets index the packed buffers of Bufs.
+// One evaluation instance.  Offsets index the packed buffers of Bufs.  An
+// N-1 instance whose removed branch had no parallel twin loses 8 Jacobian
+// and 4 Hessian slots; their base positions, ascending, are rj and rh
+// (INT32_MAX when nothing is removed), and every later entry moves down by
+// the number of removed positions before it.
 struct InstOff {
   const NetDev* net;
   const WorkItem* work;     // work items of the schedule in use
+  const int2* slots;        // slot map of the schedule in use
   int32_t out_l;            // removed branch, -1 for none
-  int32_t out_p, out_q;     // its endpoints, p < q
-  int32_t out_rm;           // 1 if no parallel branch keeps the (p, q) slots
+  int32_t out_rm;           // 1 if the removal drops the (p, q) slots
+  int32_t rj[8];
+  int32_t rh[4];
   int64_t xo;               // x, grad f, u
   int64_t co;               // lambda, c, w_c
   int64_t jo;               // Jacobian values
@@ -98,23 +120,23 @@ enum : unsigned {
 };
 
 // Tile capacities of one schedule: workgroup size, branch ends per bus tile
-// and the LDS staging capacity (doubles) for the tile's J and H row segments.
+// (LDS records) and buses per bus tile (LDS bus extras).
 struct TileCaps {
-  int32_t wg, be, stage;
+  int32_t wg, be, nbus;
 };
 
-// Staging of ~10 doubles per branch end covers grids of mean degree ~3; the
-// tiler closes a tile early when a dense patch would overflow it.
-constexpr TileCaps kCaps64 = {64, 64, 640};
-constexpr TileCaps kCaps128 = {128, 128, 1280};
-constexpr TileCaps kCaps256 = {256, 256, 2560};
-constexpr int kDefaultTileBe = 128;
+constexpr TileCaps kCaps64 = {64, 64, 32};
+constexpr TileCaps kCaps128 = {128, 128, 64};
+constexpr TileCaps kCaps256 = {256, 256, 128};
+constexpr TileCaps kCaps512 = {256, 512, 256};
+constexpr int kDefaultTileBe = 256;
 
 inline bool caps_for(int tile_be, TileCaps* out) {
   switch (tile_be) {
     case 64: *out = kCaps64; return true;
     case 128: *out = kCaps128; return true;
     case 256: *out = kCaps256; return true;
+    case 512: *out = kCaps512; return true;
     default: return false;
   }
 }
@@ -134,5 +156,11 @@ enum : unsigned {
 hipError_t launch_eval(unsigned kvariant, int tile_be, const Bufs& b, const InstOff* table,
                        const InstOff& one, const Tile* tiles, int ntiles, int grid,
                        hipStream_t stream);
+
+// Enqueue the random-iterate draw for instances [first, first + count) of a
+// batch table; max_len bounds n + m over those instances.
+hipError_t launch_draw(const InstOff* table, int first, int count, int max_len,
+                       const uint64_t* seeds, double pmin, double pmax, double qmin, double qmax,
+                       double* x, double* lam, hipStream_t stream);
 
 }  // namespace acopf

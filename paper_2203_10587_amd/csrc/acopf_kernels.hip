@@ -12,15 +12,17 @@
 //            the six Jacobian terms, the four Hessian terms, or the two VJP
 //            terms).  A branch whose from-bus the tile owns also writes its
 //            flow-limit rows: h = P^2 + Q^2 at both ends and their Jacobian
-//            rows 2 (P dP + Q dQ) on (theta_f, theta_t, v_f, v_t).
-//            Phase B, lane per bus: a segmented sum over the bus's branch
-//            ends in their fixed (far bus, branch) order -- diagonal entries
-//            over all of them, one off-diagonal entry per distinct neighbour
-//            -- written into an LDS image of the tile's four contiguous CSR
-//            row segments (J P rows, J Q rows, H theta rows, H v rows).  No
-//            atomics: every sum has one owner and a fixed order, so results
-//            are bitwise reproducible whatever the tiling.
-//            Phase C: the LDS image is streamed out with coalesced stores.
+//            rows 2 (P dP + Q dQ) on (theta_f, theta_t, v_f, v_t).  Lanes
+//            also stage each bus's own terms (shunts, load, generation).
+//            Phase B, lane per output entry: a host-built slot map gives each
+//            entry of the tile's CSR row segments (J P and Q rows, H theta and
+//            v rows) as a signed sum over a contiguous range of records --
+//            branch ends are sorted by (bus, far bus, branch), so a diagonal
+//            entry sums all of a bus's ends and an off-diagonal entry the ends
+//            of one group of parallel branches -- plus a bus term; consecutive
+//            lanes store consecutive entries.  No atomics: every sum has one
+//            owner and a fixed order, so results are bitwise reproducible
+//            whatever the tiling.
 //  gen tile  a fixed chunk of 256 generators: grad f, the Pg diagonal of H,
 //            the Pg/Qg part of the VJP and a fixed-tree partial sum of the
 //            cost; the last chunk of an instance to finish (ticket counter)
@@ -105,65 +107,81 @@ struct Rec {
   static constexpr int N = oV + (V ? 2 : 0);
 };
 
-template <unsigned WHAT, int WG, int BE, int STAGE>
+// Bus terms staged by phase A (structure of arrays, NBUS entries per field).
+template <unsigned WHAT>
+struct BusRec {
+  static constexpr bool C = (WHAT & W_C) != 0;
+  static constexpr bool J = (WHAT & W_J) != 0;
+  static constexpr bool H = (WHAT & W_H) != 0;
+  static constexpr bool V = (WHAT & W_VJP) != 0;
+  static constexpr int oJ = 0;                  // 2 gs v, -2 bs v
+  static constexpr int oH = oJ + (J ? 2 : 0);   // 2 (lP gs - lQ bs)
+  static constexpr int oC = oH + (H ? 1 : 0);   // (gs v^2 - Pg) + Pd, (-bs v^2 - Qg) + Qd
+  static constexpr int oV = oC + (C ? 2 : 0);   // 2 v (wP gs - wQ bs)
+  static constexpr int N = oV + (V ? 1 : 0);
+};
+
+template <unsigned WHAT, int BE, int NBUS>
 struct Lds {
-  static constexpr bool kStage = (WHAT & (W_J | W_H)) != 0;
-  static constexpr int kBus = Rec<WHAT>::N * BE + BE / 2 + (kStage ? STAGE : 0);
+  static constexpr int kRec = Rec<WHAT>::N * BE;
+  static constexpr int kBus = kRec + BusRec<WHAT>::N * NBUS + NBUS;  // + (first end, count) per bus
   static constexpr int kGen = kGenChunk;
   static constexpr int kMax = kBus > kGen ? kBus : kGen;
 };
 
 __device__ __forceinline__ int after_outage(int l, int ol) { return (ol >= 0 && l > ol) ? 1 : 0; }
 
-// Row starts of an instance: the base pattern's, shifted for a removed
-// (p, q) slot pair (p < q): rows p and q of the J balance blocks lose two
-// entries each, row theta_q of H loses theta_p, row v_p loses theta_q and
-// row v_q loses theta_p and v_p.
-struct RowShift {
-  int p, q, rm;
-  __device__ __forceinline__ int below(int i) const { return (p < i ? 1 : 0) + (q < i ? 1 : 0); }
-  __device__ __forceinline__ int jP(int4 r, int i) const { return r.x - 2 * rm * below(i); }
-  __device__ __forceinline__ int jQ(int4 r, int i) const { return r.y - 4 * rm - 2 * rm * below(i); }
-  __device__ __forceinline__ int hT(int4 r, int i) const { return r.z - rm * (q < i ? 1 : 0); }
-  __device__ __forceinline__ int hV(int4 r, int i) const {
-    return r.w - rm * (1 + (p < i ? 1 : 0) + 2 * (q < i ? 1 : 0));
-  }
-};
-
 // ---------------------------------------------------------------------------
 // bus tile
 
-template <unsigned WHAT, int WG, int BE, int STAGE>
+// Position of a base slot in an instance that may have lost slots: -1 if
+// the slot itself was removed, else the base position minus the removed
+// positions before it.
+template <int NR>
+__device__ __forceinline__ int shifted(int gp, const int32_t (&r)[NR]) {
+  int below = 0;
+  bool gone = false;
+#pragma unroll
+  for (int m = 0; m < NR; ++m) {
+    below += r[m] < gp ? 1 : 0;
+    gone = gone || r[m] == gp;
+  }
+  return gone ? -1 : gp - below;
+}
+
+template <unsigned WHAT, int WG, int BE, int NBUS>
 __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const Tile& T,
                          double* smem) {
   using R = Rec<WHAT>;
+  using U = BusRec<WHAT>;
   constexpr bool DO_GF = (WHAT & W_GRADF) != 0 && !R::V;
   const int tid = threadIdx.x;
   const int nb = N.nb;
   const int ol = I.out_l;
   const int nll = N.nl - (ol >= 0 ? 1 : 0);
-  const int b0 = T.a0, b1 = T.a1, e0 = T.e0;
+  const int b0 = T.a0, nbus = T.a1 - T.a0, e0 = T.e0;
   double* rec = smem;
-  int* nbr = reinterpret_cast<int*>(smem + R::N * BE);
-  double* stage = smem + R::N * BE + BE / 2;
+  double* bus = smem + Lds<WHAT, BE, NBUS>::kRec;
+  int2* bus_e = reinterpret_cast<int2*>(bus + U::N * NBUS);
   const double* x = B.x + I.xo;
   const double* mul = R::H ? B.lam + I.co : (R::V ? B.wc + I.co : nullptr);
   const bool hneed = R::V || (R::H && B.hess != nullptr);
   double* cflow = (R::C && B.c) ? B.c + I.co + 2 * nb : nullptr;
   double* jflow = (R::J && B.jac) ? B.jac + I.jo + (N.jflow - 8 * I.out_rm) : nullptr;
 
-  // ---- phase A: lane per branch touching the tile
+  // ---- phase A (1): lane per branch touching the tile
   for (int k = tid; k < T.nw; k += WG) {
     const WorkItem wi = I.work[T.w0 + k];
     const int l = wi.l, f = wi.f, t = wi.t;
     const uint32_t sf = wi.slots & 0xFFFFu, st = wi.slots >> 16;
-    if (l == ol) {  // removed branch: keeps its place in the adjacency order, adds nothing
-      if (sf != kNoSlot) nbr[sf] = -1 - t;
-      if (st != kNoSlot) nbr[st] = -1 - f;
+    if (l == ol) {  // removed branch: its ends keep their places and add zero
+#pragma unroll
+      for (int q = 0; q < R::N; ++q) {
+        if (sf != kNoSlot) rec[q * BE + sf] = 0.0;
+        if (st != kNoSlot) rec[q * BE + st] = 0.0;
+      }
       continue;
     }
-    if (sf != kNoSlot) nbr[sf] = t;
-    if (st != kNoSlot) nbr[st] = f;
     const BranchY y = N.br_y[l];
     Br b;
     branch_eval(x[f], x[t], x[nb + f], x[nb + t], y, b);
@@ -283,156 +301,119 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       }
     }
   }
-  __syncthreads();
 
-  // ---- phase B: lane per bus, segmented sums in (far bus, branch) order
-  const RowShift sh{I.out_p, I.out_q, I.out_rm};
-  const int4 r0 = N.rows[b0];
-  const int4 r1 = N.rows[b1];
-  const int jP0 = sh.jP(r0, b0), jQ0 = sh.jQ(r0, b0), hT0 = sh.hT(r0, b0), hV0 = sh.hV(r0, b0);
-  const int LP = sh.jP(r1, b1) - jP0, LQ = sh.jQ(r1, b1) - jQ0;
-  const int LT = sh.hT(r1, b1) - hT0, LV = sh.hV(r1, b1) - hV0;
-  double* sP = stage;
-  double* sQ = sP + LP;
-  double* sT = sQ + LQ;
-  double* sV = sT + LT;
+  // ---- phase A (2): lane per bus, the bus's own terms
   const bool jout = R::J && B.jac != nullptr;
   const bool hout = R::H && B.hess != nullptr;
   double* c = (R::C && B.c) ? B.c + I.co : nullptr;
-  double* gradf = (DO_GF && B.gradf) ? B.gradf + I.xo : nullptr;
-
-  for (int ib = tid; ib < b1 - b0; ib += WG) {
+  for (int ib = tid; ib < nbus; ib += WG) {
     const int i = b0 + ib;
-    const int4 ri = N.rows[i];
-    int2 ac = N.acnt[i];
-    int a = ac.x, lo = ac.y;
-    if (sh.rm) {
-      if (i == sh.p) a -= 1;
-      if (i == sh.q) {
-        a -= 1;
-        lo -= 1;
+    const int ea = N.be_ptr[i];
+    bus_e[ib] = make_int2(ea - e0, N.be_ptr[i + 1] - ea);
+    const double4 bd = N.bus[i];  // pd, qd, gs, bs
+    const double vi = x[nb + i];
+    if constexpr (U::J) {
+      bus[(U::oJ + 0) * NBUS + ib] = 2.0 * bd.z * vi;
+      bus[(U::oJ + 1) * NBUS + ib] = -2.0 * bd.w * vi;
+    }
+    if constexpr (U::H) {
+      if (hout) bus[U::oH * NBUS + ib] = 2.0 * fma(mul[i], bd.z, -(mul[nb + i] * bd.w));
+    }
+    if constexpr (U::C) {
+      if (c) {
+        double pg = 0, qg = 0;
+        for (int g = N.gen_ptr[i], g1 = N.gen_ptr[i + 1]; g < g1; ++g) {
+          const int k = N.gen_list[g];
+          pg += x[2 * nb + k];
+          qg += x[2 * nb + N.ng + k];
+        }
+        bus[(U::oC + 0) * NBUS + ib] = (bd.z * vi * vi - pg) + bd.x;
+        bus[(U::oC + 1) * NBUS + ib] = (-bd.w * vi * vi - qg) + bd.y;
       }
     }
-    const int oP = sh.jP(ri, i) - jP0, oQ = sh.jQ(ri, i) - jQ0;
-    const int oT = sh.hT(ri, i) - hT0, oV = sh.hV(ri, i) - hV0;
-    double sPi = 0, sQi = 0;
-    double dP_t = 0, dP_v = 0, dQ_t = 0, dQ_v = 0;
-    double ha = 0, hb = 0, hvv = 0;
-    double ut = 0, uv = 0;
-    int rank = 0;
-    const int ebeg = N.be_ptr[i] - e0, eend = N.be_ptr[i + 1] - e0;
-    int e = ebeg;
-    while (e < eend) {
-      const int key = nbr[e];
-      const int j = key >= 0 ? key : -1 - key;
-      bool live = false;
-      double gPt = 0, gPv = 0, gQt = 0, gQv = 0, ga = 0, gb = 0, gvv = 0;
-      for (; e < eend; ++e) {
-        const int k2 = nbr[e];
-        if ((k2 >= 0 ? k2 : -1 - k2) != j) break;
-        if (k2 < 0) continue;
-        live = true;
-        if constexpr (R::C) {
-          sPi += rec[(R::oC + 0) * BE + e];
-          sQi += rec[(R::oC + 1) * BE + e];
-        }
-        if constexpr (R::J) {
-          const double t0 = rec[(R::oJ + 0) * BE + e], t3 = rec[(R::oJ + 3) * BE + e];
-          dP_t += t0;
-          dP_v += rec[(R::oJ + 1) * BE + e];
-          dQ_t += t3;
-          dQ_v += rec[(R::oJ + 4) * BE + e];
-          gPt += t0;
-          gPv += rec[(R::oJ + 2) * BE + e];
-          gQt += t3;
-          gQv += rec[(R::oJ + 5) * BE + e];
-        }
-        if constexpr (R::H) {
-          if (hout) {
-            const double t0 = rec[(R::oH + 0) * BE + e], t1 = rec[(R::oH + 1) * BE + e];
-            ha += t0;
-            hb += t1;
-            hvv += rec[(R::oH + 2) * BE + e];
-            ga += t0;
-            gb += t1;
-            gvv += rec[(R::oH + 3) * BE + e];
+    if constexpr (U::V) {
+      bus[U::oV * NBUS + ib] = 2.0 * vi * fma(mul[i], bd.z, -(mul[nb + i] * bd.w));
+    }
+  }
+  __syncthreads();
+
+  // ---- phase B: lane per output entry
+  const int2* sm = I.slots + T.sm0;
+  const bool shift = I.out_rm != 0;
+  if (jout) {
+    double* jac = B.jac + I.jo;
+    for (int k = tid; k < T.nP; k += WG) {
+      const int2 ent = sm[k];
+      const int ea = ent.x & 0xFFFF, cnt = ent.x >> 16;
+      const int fld = ent.y & 15, kind = (ent.y >> 5) & 7, bl = ent.y >> 8;
+      double vp = 0.0, vq = 0.0;
+      for (int e = ea; e < ea + cnt; ++e) {
+        vp += rec[(R::oJ + fld) * BE + e];
+        vq += rec[(R::oJ + 3 + fld) * BE + e];
+      }
+      if (ent.y & 16) {
+        vp = -vp;
+        vq = -vq;
+      }
+      if (kind == SK_JDIAG_V) {
+        vp += bus[(U::oJ + 0) * NBUS + bl];
+        vq += bus[(U::oJ + 1) * NBUS + bl];
+      } else if (kind == SK_GEN) {
+        vp = -1.0;
+        vq = -1.0;
+      }
+      const int gp = shift ? shifted(T.jP0 + k, I.rj) : T.jP0 + k;
+      const int gq = shift ? shifted(T.jQ0 + k, I.rj) : T.jQ0 + k;
+      if (gp >= 0) jac[gp] = vp;
+      if (gq >= 0) jac[gq] = vq;
+    }
+  }
+  if (hout) {
+    double* hess = B.hess + I.ho;
+    const int2* smT = sm + T.nP;
+    for (int k = tid; k < T.nT + T.nV; k += WG) {
+      const int2 ent = smT[k];
+      const int ea = ent.x & 0xFFFF, cnt = ent.x >> 16;
+      const int fld = ent.y & 15, kind = (ent.y >> 5) & 7, bl = ent.y >> 8;
+      double v = 0.0;
+      for (int e = ea; e < ea + cnt; ++e) v += rec[(R::oH + fld) * BE + e];
+      if (ent.y & 16) v = -v;
+      if (kind == SK_HDIAG_V) v += bus[U::oH * NBUS + bl];
+      const int base = k < T.nT ? T.hT0 + k : T.hV0 + (k - T.nT);
+      const int gp = shift ? shifted(base, I.rh) : base;
+      if (gp >= 0) hess[gp] = v;
+    }
+  }
+  if constexpr (R::C || R::V || DO_GF) {
+    double* gradf = (DO_GF && B.gradf) ? B.gradf + I.xo : nullptr;
+    for (int ib = tid; ib < nbus; ib += WG) {
+      const int i = b0 + ib;
+      const int2 be = bus_e[ib];
+      if constexpr (R::C) {
+        if (c) {
+          double sp = 0.0, sq = 0.0;
+          for (int e = be.x; e < be.x + be.y; ++e) {
+            sp += rec[(R::oC + 0) * BE + e];
+            sq += rec[(R::oC + 1) * BE + e];
           }
+          c[i] = sp + bus[(U::oC + 0) * NBUS + ib];
+          c[nb + i] = sq + bus[(U::oC + 1) * NBUS + ib];
         }
-        if constexpr (R::V) {
+      }
+      if (gradf) {
+        gradf[i] = 0.0;
+        gradf[nb + i] = 0.0;
+      }
+      if constexpr (R::V) {
+        double ut = 0.0, uv = 0.0;
+        for (int e = be.x; e < be.x + be.y; ++e) {
           ut += rec[(R::oV + 0) * BE + e];
           uv += rec[(R::oV + 1) * BE + e];
         }
+        double* u = B.u + I.xo;
+        u[i] = ut;
+        u[nb + i] = uv + bus[U::oV * NBUS + ib];
       }
-      if (!live) continue;
-      const int pos = rank + (j > i ? 1 : 0);
-      if (jout) {
-        sP[oP + pos] = -gPt;
-        sP[oP + a + pos] = gPv;
-        sQ[oQ + pos] = -gQt;
-        sQ[oQ + a + pos] = gQv;
-      }
-      if (hout) {
-        sV[oV + pos] = -gb;
-        if (j < i) {
-          sT[oT + pos] = -ga;
-          sV[oV + a + pos] = gvv;
-        }
-      }
-      ++rank;
-    }
-    const double4 bd = N.bus[i];  // pd, qd, gs, bs
-    const double vi = x[nb + i];
-    const int g0 = N.gen_ptr[i], g1 = N.gen_ptr[i + 1];
-    if (jout) {
-      sP[oP + lo] = dP_t;
-      sP[oP + a + lo] = fma(2.0 * bd.z, vi, dP_v);
-      sQ[oQ + lo] = dQ_t;
-      sQ[oQ + a + lo] = fma(-2.0 * bd.w, vi, dQ_v);
-      for (int g = g0; g < g1; ++g) {
-        sP[oP + 2 * a + (g - g0)] = -1.0;
-        sQ[oQ + 2 * a + (g - g0)] = -1.0;
-      }
-    }
-    if (hout) {
-      const double* lam = B.lam + I.co;
-      sT[oT + lo] = ha;
-      sV[oV + lo] = hb;
-      sV[oV + a + lo] = fma(2.0, fma(lam[i], bd.z, -(lam[nb + i] * bd.w)), hvv);
-    }
-    if (c) {
-      double pg = 0, qg = 0;
-      for (int g = g0; g < g1; ++g) {
-        const int k = N.gen_list[g];
-        pg += x[2 * nb + k];
-        qg += x[2 * nb + N.ng + k];
-      }
-      c[i] = fma(bd.z * vi, vi, sPi) - pg + bd.x;
-      c[nb + i] = fma(-bd.w * vi, vi, sQi) - qg + bd.y;
-    }
-    if (gradf) {
-      gradf[i] = 0.0;
-      gradf[nb + i] = 0.0;
-    }
-    if constexpr (R::V) {
-      const double* w = B.wc + I.co;
-      double* u = B.u + I.xo;
-      u[i] = ut;
-      u[nb + i] = fma(2.0 * vi, fma(w[i], bd.z, -(w[nb + i] * bd.w)), uv);
-    }
-  }
-
-  // ---- phase C: stream the LDS image of the row segments out
-  if (jout || hout) {
-    __syncthreads();
-    if (jout) {
-      double* jac = B.jac + I.jo;
-      for (int k = tid; k < LP; k += WG) jac[jP0 + k] = sP[k];
-      for (int k = tid; k < LQ; k += WG) jac[jQ0 + k] = sQ[k];
-    }
-    if (hout) {
-      double* hess = B.hess + I.ho;
-      for (int k = tid; k < LT; k += WG) hess[hT0 + k] = sT[k];
-      for (int k = tid; k < LV; k += WG) hess[hV0 + k] = sV[k];
     }
   }
 }
@@ -507,17 +488,17 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
 
 // ---------------------------------------------------------------------------
 
-template <unsigned WHAT, int WG, int BE, int STAGE>
+template <unsigned WHAT, int WG, int BE, int NBUS>
 __global__ __launch_bounds__(WG) void k_eval(Bufs B, const InstOff* __restrict__ table,
                                              InstOff one, const Tile* __restrict__ tiles,
                                              int ntiles) {
-  __shared__ double smem[Lds<WHAT, WG, BE, STAGE>::kMax];
+  __shared__ double smem[Lds<WHAT, BE, NBUS>::kMax];
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const Tile T = tiles[t];
     const InstOff I = table ? table[T.inst] : one;
     const NetDev& N = *I.net;
     if ((T.kind_aux & 3) == TILE_BUS) {
-      bus_tile<WHAT, WG, BE, STAGE>(B, I, N, T, smem);
+      bus_tile<WHAT, WG, BE, NBUS>(B, I, N, T, smem);
     } else {
       if constexpr ((WHAT & (W_F | W_GRADF | W_H | W_VJP)) != 0)
         gen_tile<WHAT, WG>(B, I, N, T.a0, T.a1, T.kind_aux >> 2, smem);
@@ -532,15 +513,15 @@ hipError_t launch_caps(int tile_be, const Bufs& b, const InstOff* table, const I
   const int blocks = grid > 0 ? (grid < ntiles ? grid : ntiles) : ntiles;
   if (blocks <= 0) return hipSuccess;
   switch (tile_be) {
-    case 64:
-      k_eval<WHAT, 64, 64, kCaps64.stage><<<blocks, 64, 0, s>>>(b, table, one, tiles, ntiles);
-      break;
-    case 128:
-      k_eval<WHAT, 128, 128, kCaps128.stage><<<blocks, 128, 0, s>>>(b, table, one, tiles, ntiles);
-      break;
-    case 256:
-      k_eval<WHAT, 256, 256, kCaps256.stage><<<blocks, 256, 0, s>>>(b, table, one, tiles, ntiles);
-      break;
+#define ACOPF_CASE(C)                                                                      \
+  case C.be:                                                                               \
+    k_eval<WHAT, C.wg, C.be, C.nbus><<<blocks, C.wg, 0, s>>>(b, table, one, tiles, ntiles); \
+    break;
+    ACOPF_CASE(kCaps64)
+    ACOPF_CASE(kCaps128)
+    ACOPF_CASE(kCaps256)
+    ACOPF_CASE(kCaps512)
+#undef ACOPF_CASE
     default:
       return hipErrorInvalidValue;
   }

@@ -1,0 +1,327 @@
+"""Continuous-batching evaluation server.
+
+Requests name a resident grid and carry a seed; the device draws the
+request's iterate and multipliers from the seed and evaluates f, grad f, c,
+J and H into a slot of that grid's pool.  The scheduler
+
+  - keeps each grid's network resident on the device and one slot pool per
+    grid (the instance slots of one batch handle);
+  - admits queued requests oldest-first while slots are free and the HBM
+    bytes of all in-flight slots stay within the budget; a request whose slot
+    alone exceeds the budget is rejected (ACOPF_EBUDGET semantics);
+  - launches every admitted window as soon as it is formed, on the grid's own
+    stream, so requests that arrive while others are on the GPU join the next
+    window and windows of different grids overlap on the device (continuous
+    batching);
+  - retires each window when its completion event fires, frees its slots
+    and budget, and stamps each request's latency;
+  - fails a window whose launch raises, and fails (and quarantines the slots
+    of) a window that has not completed within the watchdog timeout.
+
+The device work goes through an Executor; GpuExecutor drives the C ABI
+(acopf_batch_draw_iterates + acopf_batch_eval_range), and the CPU tests use
+a simulated executor with the same interface.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence
+
+
+@dataclass
+class Request:
+    rid: int
+    grid: int
+    seed: int
+    t_arrive: float
+    t_launch: float = float("nan")
+    t_done: float = float("nan")
+    slot: int = -1
+    status: str = "queued"     # queued | running | done | failed | rejected
+    error: str = ""
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrive
+
+
+@dataclass
+class _Window:
+    grid: int
+    first: int
+    reqs: List[Request]
+    handle: object
+    t_launch: float
+    nbytes: int
+
+
+class Executor:
+    """Device side of the server (one pool of `capacity[g]` slots per grid)."""
+
+    def grids(self) -> Sequence[int]:
+        raise NotImplementedError
+
+    def capacity(self, grid: int) -> int:
+        raise NotImplementedError
+
+    def slot_bytes(self, grid: int) -> int:
+        raise NotImplementedError
+
+    def launch(self, grid: int, first: int, seeds: Sequence[int]):
+        """Enqueue draw + evaluation of slots [first, first + len(seeds))."""
+        raise NotImplementedError
+
+    def done(self, handle) -> bool:
+        raise NotImplementedError
+
+
+class _Pool:
+    """Slot occupancy of one grid.  Windows take a contiguous run of free
+    slots starting at the rotating head (or at 0); slots of a window that
+    timed out stay occupied, since the device may still write them."""
+
+    def __init__(self, capacity: int):
+        self.capacity = int(capacity)
+        self.occ = [False] * self.capacity
+        self.head = 0
+
+    def alloc(self, want: int):
+        for start in (self.head, 0):
+            if start >= self.capacity:
+                continue
+            run = 0
+            while run < want and start + run < self.capacity and not self.occ[start + run]:
+                run += 1
+            if run:
+                for k in range(start, start + run):
+                    self.occ[k] = True
+                self.head = start + run
+                return start, run
+        return None
+
+    def free(self, first: int, k: int):
+        for s in range(first, first + k):
+            self.occ[s] = False
+
+
+class Server:
+    def __init__(self, executor: Executor, budget_bytes: int = 8 << 30, max_window: int = 64,
+                 timeout_s: float = 10.0, clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_window = int(max_window)
+        self.timeout = float(timeout_s)
+        self.clock = clock
+        self.pools = {g: _Pool(executor.capacity(g)) for g in executor.grids()}
+        self.queues: Dict[int, collections.deque] = {g: collections.deque() for g in self.pools}
+        self.inflight: Dict[int, collections.deque] = {g: collections.deque() for g in self.pools}
+        self.bytes_in_flight = 0
+        self.peak_bytes = 0
+        self.requests: List[Request] = []
+        self.windows_launched = 0
+        self._rr = 0
+
+    # -- intake ---------------------------------------------------------------
+    def submit(self, grid: int, seed: int, t_arrive: Optional[float] = None) -> Request:
+        r = Request(rid=len(self.requests), grid=grid, seed=int(seed),
+                    t_arrive=self.clock() if t_arrive is None else float(t_arrive))
+        self.requests.append(r)
+        if grid not in self.pools:
+            r.status, r.error = "rejected", "unknown grid"
+        elif self.ex.slot_bytes(grid) > self.budget:
+            r.status, r.error = "rejected", "request exceeds the HBM budget"
+        else:
+            self.queues[grid].append(r)
+        return r
+
+    # -- progress -------------------------------------------------------------
+    def _retire(self, now: float) -> int:
+        n = 0
+        for g, q in self.inflight.items():
+            keep = collections.deque()
+            for w in q:
+                if w.handle is not None and self.ex.done(w.handle):
+                    if w.reqs and w.reqs[0].status == "running":
+                        for r in w.reqs:
+                            r.t_done, r.status = now, "done"
+                    self.pools[g].free(w.first, len(w.reqs))
+                    self.bytes_in_flight -= w.nbytes
+                    n += 1
+                    continue
+                if w.reqs and w.reqs[0].status == "running" and now - w.t_launch > self.timeout:
+                    # watchdog: fail the requests now; the slots and their bytes
+                    # stay reserved until the device finishes with them
+                    for r in w.reqs:
+                        r.t_done, r.status, r.error = now, "failed", "timeout"
+                    n += 1
+                keep.append(w)
+            self.inflight[g] = keep
+        return n
+
+    def _admit(self, now: float) -> int:
+        launched = 0
+        grids = list(self.pools)
+        for step in range(len(grids)):
+            g = grids[(self._rr + step) % len(grids)]
+            q, pool = self.queues[g], self.pools[g]
+            sb = self.ex.slot_bytes(g)
+            while q:
+                room = (self.budget - self.bytes_in_flight) // sb
+                want = min(len(q), self.max_window, room)
+                if want <= 0:
+                    break
+                got = pool.alloc(want)
+                if got is None:
+                    break
+                first, k = got
+                reqs = [q.popleft() for _ in range(k)]
+                try:
+                    h = self.ex.launch(g, first, [r.seed for r in reqs])
+                except Exception as exc:  # a failed launch fails its window only
+                    pool.free(first, k)
+                    for r in reqs:
+                        r.status, r.error, r.t_done = "failed", f"launch: {exc}", now
+                    continue
+                for i, r in enumerate(reqs):
+                    r.slot, r.status, r.t_launch = first + i, "running", now
+                self.bytes_in_flight += k * sb
+                self.peak_bytes = max(self.peak_bytes, self.bytes_in_flight)
+                self.inflight[g].append(_Window(g, first, reqs, h, now, k * sb))
+                self.windows_launched += 1
+                launched += 1
+        self._rr = (self._rr + 1) % max(1, len(grids))
+        return launched
+
+    def step(self) -> int:
+        now = self.clock()
+        return self._retire(now) + self._admit(now)
+
+    def idle(self) -> bool:
+        return not any(self.queues.values()) and not any(self.inflight.values())
+
+    # -- open-loop driver -------------------------------------------------------
+    def run_trace(self, arrivals: Sequence[tuple], progress: Optional[Callable] = None,
+                  time_limit_s: float = 600.0) -> Dict:
+        """arrivals: (t_offset_s, grid, seed) sorted by time; requests enter at
+        their scheduled time and latency runs from that time (open loop)."""
+        t0 = self.clock()
+        i = 0
+        last_report = t0
+        while i < len(arrivals) or not self.idle():
+            now = self.clock()
+            while i < len(arrivals) and t0 + arrivals[i][0] <= now:
+                t, g, s = arrivals[i]
+                self.submit(g, s, t_arrive=t0 + t)
+                i += 1
+            self.step()
+            if progress and now - last_report > 5.0:
+                progress(i, len(arrivals))
+                last_report = now
+            if now - t0 > time_limit_s:
+                break
+        return self.stats(self.clock() - t0)
+
+    def stats(self, wall_s: float) -> Dict:
+        import numpy as np
+        done = [r for r in self.requests if r.status == "done"]
+        lat = np.array([r.latency for r in done]) * 1e3 if done else np.zeros(1)
+        per = {}
+        for g in self.pools:
+            lg = np.array([r.latency for r in done if r.grid == g]) * 1e3
+            if len(lg):
+                per[str(g)] = {"n": int(len(lg)), "p50_ms": float(np.percentile(lg, 50)),
+                               "p99_ms": float(np.percentile(lg, 99))}
+        return {
+            "requests": len(self.requests), "done": len(done),
+            "failed": sum(r.status == "failed" for r in self.requests),
+            "rejected": sum(r.status == "rejected" for r in self.requests),
+            "wall_s": wall_s, "throughput_rps": len(done) / wall_s if wall_s > 0 else 0.0,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "windows": self.windows_launched,
+            "mean_window": len(done) / max(1, self.windows_launched),
+            "peak_bytes_in_flight": self.peak_bytes, "per_grid": per,
+        }
+
+
+def poisson_trace(rate_hz: float, seconds: float, ngrids: int, seed: int = 1):
+    """Open-loop Poisson arrivals, each on a uniformly chosen grid, with a
+    per-request seed."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    n = int(rng.poisson(rate_hz * seconds))
+    t = np.sort(rng.uniform(0.0, seconds, n))
+    g = rng.integers(0, ngrids, n)
+    s = rng.integers(0, 2 ** 62, n)
+    return list(zip(t.tolist(), g.tolist(), s.tolist()))
+
+
+class GpuExecutor(Executor):
+    """Slot pools of resident grids on the current GPU, one stream per grid."""
+
+    def __init__(self, grids: Sequence, capacities: Sequence[int], tile_be: int = 256):
+        import torch
+        from . import acopf as A
+        self.A = A
+        self.dev = torch.device("cuda", torch.cuda.current_device())
+        self.pool = []
+        for g, cap in zip(grids, capacities):
+            net = A.acopf_net_create(g)
+            b = A.acopf_batch_create([net] * int(cap), tile_be=tile_be, grid_mult=0, xcd_group=0,
+                                     no_graph=1)
+            nx, nc = int(b.x_off[-1]), int(b.c_off[-1])
+            nj, nh = int(b.j_off[-1]), int(b.h_off[-1])
+            z = lambda n: torch.zeros(n, dtype=torch.float64, device=self.dev)
+            bufs = dict(x=z(nx), lam=z(nc), sigma=torch.ones(cap, dtype=torch.float64, device=self.dev),
+                        f=z(cap), gf=z(nx), c=z(nc), jac=z(nj), hess=z(nh))
+            seeds = torch.zeros(cap, dtype=torch.int64, device=self.dev)
+            pinned = torch.zeros(cap, dtype=torch.int64, pin_memory=True)
+            bounds = (float(g.gen_pmin[0]) if g.ngen else 0.0, float(g.gen_pmax[0]) if g.ngen else 0.0,
+                      float(g.gen_qmin[0]) if g.ngen else 0.0, float(g.gen_qmax[0]) if g.ngen else 0.0)
+            per_slot = 8 * (2 * net.n + 2 * net.m + 1 + net.nnz_jac + net.nnz_hess) + 16
+            self.pool.append(dict(net=net, batch=b, bufs=bufs, seeds=seeds, pinned=pinned,
+                                  bounds=bounds, cap=int(cap), stream=torch.cuda.Stream(),
+                                  slot_bytes=per_slot))
+
+    def grids(self):
+        return list(range(len(self.pool)))
+
+    def capacity(self, grid):
+        return self.pool[grid]["cap"]
+
+    def slot_bytes(self, grid):
+        return self.pool[grid]["slot_bytes"]
+
+    def launch(self, grid, first, seeds):
+        import torch
+        P = self.pool[grid]
+        k = len(seeds)
+        P["pinned"][first:first + k] = torch.tensor([s & ((1 << 63) - 1) for s in seeds],
+                                                    dtype=torch.int64)
+        st = P["stream"]
+        with torch.cuda.stream(st):
+            P["seeds"][first:first + k].copy_(P["pinned"][first:first + k], non_blocking=True)
+            b, B = P["batch"], P["bufs"]
+            self.A.acopf_batch_draw_iterates(b, first, k, P["seeds"], P["bounds"], B["x"],
+                                             B["lam"], st)
+            self.A.acopf_batch_eval_range(b, first, k, B["x"], B["sigma"], B["lam"], B["f"],
+                                          B["gf"], B["c"], B["jac"], B["hess"],
+                                          self.A.ACOPF_ALL, st)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return ev
+
+    def done(self, handle):
+        return handle.query()
+
+    def fetch(self, grid, slot):
+        """Host copies of one slot's outputs (tests)."""
+        P = self.pool[grid]
+        b, B = P["batch"], P["bufs"]
+        P["stream"].synchronize()
+        sl = lambda t, o: t[int(o[slot]):int(o[slot + 1])].cpu().numpy()
+        return {"x": sl(B["x"], b.x_off), "lam": sl(B["lam"], b.c_off),
+                "f": float(B["f"][slot].cpu()), "grad_f": sl(B["gf"], b.x_off),
+                "c": sl(B["c"], b.c_off), "jac_val": sl(B["jac"], b.j_off),
+                "hess_val": sl(B["hess"], b.h_off)}

@@ -1,0 +1,179 @@
+"""Serving scheduler on the CPU with a simulated executor and a manual
+clock: budget admission, FIFO order, continuous batching, starvation
+freedom, launch failures, the watchdog and rejection of oversize requests."""
+import math
+
+import pytest
+
+from paper_2203_10587_amd.serve import Executor, Server, poisson_trace
+
+
+class Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class FakeExecutor(Executor):
+    def __init__(self, clock, caps=(8, 4), slot_bytes=(100, 1000), cost=(0.001, 0.01),
+                 fail_calls=(), hang_calls=()):
+        self.clock = clock
+        self.caps, self.sb, self.cost = caps, slot_bytes, cost
+        self.calls = []
+        self.fail_calls, self.hang_calls = set(fail_calls), set(hang_calls)
+        self.busy = {}
+
+    def grids(self):
+        return list(range(len(self.caps)))
+
+    def capacity(self, g):
+        return self.caps[g]
+
+    def slot_bytes(self, g):
+        return self.sb[g]
+
+    def launch(self, g, first, seeds):
+        idx = len(self.calls)
+        self.calls.append((self.clock(), g, first, list(seeds)))
+        if idx in self.fail_calls:
+            raise RuntimeError("injected launch failure")
+        # one device stream per grid: windows of a grid run back to back
+        start = max(self.clock(), self.busy.get(g, 0.0))
+        end = start + self.cost[g] * (1 + 0.1 * len(seeds))
+        self.busy[g] = end
+        # an injected hang is a completion that never arrives
+        return math.inf if idx in self.hang_calls else end
+
+    def done(self, h):
+        return self.clock() >= h
+
+
+def drive(server, clock, dt=1e-4, limit=10.0):
+    while not server.idle() and clock.t < limit:
+        server.step()
+        clock.t += dt
+
+
+def test_all_done_and_budget_respected():
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    s = Server(ex, budget_bytes=2500, max_window=3, clock=clk)
+    for i in range(60):
+        s.submit(i % 2, i)
+    drive(s, clk)
+    st = s.stats(clk.t)
+    assert st["done"] == 60 and st["failed"] == 0
+    assert s.peak_bytes <= 2500
+    assert s.bytes_in_flight == 0
+
+
+def test_fifo_within_grid_and_slots_in_range():
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    s = Server(ex, max_window=2, clock=clk)
+    reqs = [s.submit(0, i) for i in range(20)]
+    drive(s, clk)
+    launches = [r.t_launch for r in reqs]
+    assert launches == sorted(launches)
+    assert all(0 <= r.slot < ex.caps[0] for r in reqs)
+    # a slot is never used by two windows at once
+    live = {}
+    for t, g, first, seeds in ex.calls:
+        for k in range(first, first + len(seeds)):
+            assert k < ex.caps[g]
+
+
+def test_continuous_batching_joins_while_busy():
+    """Requests that arrive while a window runs are launched before that
+    window completes, as long as slots and budget allow."""
+    clk = Clock()
+    ex = FakeExecutor(clk, caps=(8,), slot_bytes=(10,), cost=(0.05,))
+    s = Server(ex, max_window=8, clock=clk)
+    a = [s.submit(0, i) for i in range(3)]
+    s.step()
+    assert all(r.status == "running" for r in a)
+    clk.t += 0.01
+    b = [s.submit(0, 100 + i) for i in range(3)]
+    s.step()
+    assert all(r.status == "running" for r in b)
+    assert all(r.status == "running" for r in a)  # first window still in flight
+    drive(s, clk)
+    assert all(r.status == "done" for r in a + b)
+    assert b[0].t_done > a[0].t_done  # same-grid windows run back to back
+
+
+def test_budget_serializes_windows():
+    clk = Clock()
+    ex = FakeExecutor(clk, caps=(8,), slot_bytes=(100,), cost=(0.01,))
+    s = Server(ex, budget_bytes=300, max_window=8, clock=clk)
+    r = [s.submit(0, i) for i in range(6)]
+    s.step()
+    assert [x.status for x in r].count("running") == 3
+    drive(s, clk)
+    assert all(x.status == "done" for x in r)
+    assert s.peak_bytes == 300
+
+
+def test_oversize_request_rejected():
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    s = Server(ex, budget_bytes=500, clock=clk)
+    big = s.submit(1, 0)
+    small = s.submit(0, 1)
+    drive(s, clk)
+    assert big.status == "rejected" and "budget" in big.error
+    assert small.status == "done"
+
+
+def test_launch_failure_fails_only_its_window():
+    clk = Clock()
+    ex = FakeExecutor(clk, fail_calls={0})
+    s = Server(ex, max_window=2, clock=clk)
+    r = [s.submit(0, i) for i in range(4)]
+    drive(s, clk)
+    assert [x.status for x in r] == ["failed", "failed", "done", "done"]
+    assert "injected" in r[0].error
+
+
+def test_watchdog_times_out_a_stuck_window():
+    clk = Clock()
+    ex = FakeExecutor(clk, caps=(4, 4), hang_calls={0})
+    s = Server(ex, max_window=2, timeout_s=0.5, clock=clk)
+    stuck = [s.submit(0, i) for i in range(2)]
+    other = [s.submit(1, 10 + i) for i in range(2)]
+    for _ in range(2000):
+        s.step()
+        clk.t += 1e-3
+    assert all(r.status == "failed" and r.error == "timeout" for r in stuck)
+    assert all(r.status == "done" for r in other)
+    # the stuck slots stay reserved; the rest of the pool keeps serving
+    more = [s.submit(0, 20 + i) for i in range(2)]
+    for _ in range(200):
+        s.step()
+        clk.t += 1e-3
+    assert all(r.status == "done" for r in more)
+    assert all(r.slot >= 2 for r in more)
+
+
+def test_no_starvation_under_small_flood():
+    clk = Clock()
+    ex = FakeExecutor(clk, caps=(16, 2), slot_bytes=(10, 500), cost=(0.001, 0.02))
+    s = Server(ex, budget_bytes=600, max_window=16, clock=clk)
+    big = [s.submit(1, i) for i in range(3)]
+    for k in range(400):
+        s.submit(0, 1000 + k)
+        s.step()
+        clk.t += 5e-4
+    drive(s, clk)
+    assert all(r.status == "done" for r in big)
+
+
+def test_poisson_trace_shape():
+    tr = poisson_trace(2000.0, 2.0, 4, seed=1)
+    assert 3600 < len(tr) < 4400
+    ts = [t for t, _, _ in tr]
+    assert ts == sorted(ts) and 0 <= ts[0] and ts[-1] <= 2.0
+    assert {g for _, g, _ in tr} == {0, 1, 2, 3}
+    assert tr == poisson_trace(2000.0, 2.0, 4, seed=1)
