@@ -168,6 +168,17 @@ int acopf_eval_hess(acopf_net net, const double* x, double sigma, const double* 
 int acopf_vjp(acopf_net net, const double* x, double w_f, const double* w_c, double* u,
               hipStream_t stream);
 
+/* Hessian-vector product of the Lagrangian without forming H:
+ * out = (sigma grad^2 f + sum_r lambda_r grad^2 c_r) d, all n entries (the full
+ * symmetric H, not only its lower triangle).  DEVICE pointers: x, d, out (n),
+ * lambda (m).  Lets Newton-Krylov solvers skip storing H. */
+int acopf_hvp(acopf_net net, const double* x, double sigma, const double* lambda,
+              const double* d, double* out, hipStream_t stream);
+
+/* Jacobian-vector product without forming J: out = J(x) d (m entries);
+ * DEVICE pointers x, d (n), out (m). */
+int acopf_jvp(acopf_net net, const double* x, const double* d, double* out, hipStream_t stream);
+
 /* Everything at once in a single launch: the outputs selected by `what`
  * (ACOPF_* bits; the matching pointer must be non-NULL).  lambda is needed
  * only for ACOPF_H. */
@@ -220,6 +231,14 @@ int acopf_batch_eval(acopf_batch batch, const double* x, const double* sigma,
 /* Batched VJP: u_k = w_f[k] grad f_k + J_k' w_c_k for every instance. */
 int acopf_batch_vjp(acopf_batch batch, const double* x, const double* w_f, const double* w_c,
                     double* u, hipStream_t stream);
+
+/* Batched Hessian- and Jacobian-vector products: per instance, out_k =
+ * H_k d_k (packed like x; sigma is a DEVICE array of count) and
+ * out_k = J_k d_k (packed like c). */
+int acopf_batch_hvp(acopf_batch batch, const double* x, const double* sigma,
+                    const double* lambda, const double* d, double* out, hipStream_t stream);
+int acopf_batch_jvp(acopf_batch batch, const double* x, const double* d, double* out,
+                    hipStream_t stream);
 
 /* As acopf_batch_eval, for the instances [first, first + count) only (same
  * packed buffers and offsets; other instances' outputs are not touched).

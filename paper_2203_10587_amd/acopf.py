@@ -71,6 +71,11 @@ _SIGS = {
                                   C.c_void_p]),
     "acopf_vjp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
                             C.c_void_p]),
+    "acopf_hvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_void_p]),
+    "acopf_jvp": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "acopf_batch_hvp": (C.c_int, [C.c_void_p] + [C.c_void_p] * 5 + [C.c_void_p]),
+    "acopf_batch_jvp": (C.c_int, [C.c_void_p] + [C.c_void_p] * 3 + [C.c_void_p]),
     "acopf_eval_all": (C.c_int, [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint,
                                  C.c_void_p]),
@@ -268,6 +273,16 @@ def acopf_vjp(net: Net, x, w_f: float, w_c, u, stream=None):
                            _ptr(u, net.n, "u"), _stream(stream)))
 
 
+def acopf_hvp(net: Net, x, sigma: float, lam, d, out, stream=None):
+    _check(lib().acopf_hvp(net.handle, _ptr(x, net.n, "x"), float(sigma), _ptr(lam, net.m, "lambda"),
+                           _ptr(d, net.n, "d"), _ptr(out, net.n, "out"), _stream(stream)))
+
+
+def acopf_jvp(net: Net, x, d, out, stream=None):
+    _check(lib().acopf_jvp(net.handle, _ptr(x, net.n, "x"), _ptr(d, net.n, "d"),
+                           _ptr(out, net.m, "out"), _stream(stream)))
+
+
 def acopf_eval_all(net: Net, x, sigma: float, lam, f, grad_f, c, jac_val, hess_val,
                    what: int = ACOPF_ALL, stream=None):
     _check(lib().acopf_eval_all(
@@ -369,3 +384,16 @@ def acopf_batch_draw_iterates(b: Batch, first: int, count: int, seeds, bounds, x
     _check(lib().acopf_batch_draw_iterates(
         b.handle, int(first), int(count), C.c_void_p(seeds.data_ptr()), pmin, pmax, qmin, qmax,
         _ptr(x, int(b.x_off[-1]), "x"), _ptr(lam, int(b.c_off[-1]), "lambda"), _stream(stream)))
+
+
+def acopf_batch_hvp(b: Batch, x, sigma, lam, d, out, stream=None):
+    nx, nc = int(b.x_off[-1]), int(b.c_off[-1])
+    _check(lib().acopf_batch_hvp(b.handle, _ptr(x, nx, "x"), _ptr(sigma, b.count, "sigma"),
+                                 _ptr(lam, nc, "lambda"), _ptr(d, nx, "d"), _ptr(out, nx, "out"),
+                                 _stream(stream)))
+
+
+def acopf_batch_jvp(b: Batch, x, d, out, stream=None):
+    nx, nc = int(b.x_off[-1]), int(b.c_off[-1])
+    _check(lib().acopf_batch_jvp(b.handle, _ptr(x, nx, "x"), _ptr(d, nx, "d"), _ptr(out, nc, "out"),
+                                 _stream(stream)))

@@ -1,13 +1,17 @@
-"""torch.autograd.Function wrappers whose backward pass is the library's
-hand-written adjoint (VJP) kernel.
+"""torch.autograd.Function wrappers whose backward passes are the library's
+hand-written adjoint kernels.
 
 AcopfEval.apply(x, net)        -> (f [1], c [m])
 AcopfBatchEval.apply(x, batch) -> (f [K], c [sum m_k])  (packed layout)
 
-backward(g_f, g_c) returns u = g_f grad f + J' g_c, computed without
-forming J (acopf_batch_vjp; a single net uses a cached one-instance batch
-so that g_f stays on the device).  Forward values come from
-acopf_eval_f_g / acopf_batch_eval.  Second derivatives are not provided.
+backward(g_f, g_c) returns u = g_f grad f + J' g_c, computed without forming
+J (acopf_batch_vjp; a single net uses a cached one-instance batch so that g_f
+stays on the device).  That backward is itself differentiable, so double
+backward works:
+  d/dx    of u along a direction dx = (g_f grad^2 f + sum g_c,r grad^2 c_r) dx
+          (Hessian-vector product kernel, H never formed);
+  d/dg_c  = J dx (Jacobian-vector product kernel);
+  d/dg_f  = grad f . dx.
 """
 from __future__ import annotations
 
@@ -22,6 +26,43 @@ def _one_batch(net):
         b = A.acopf_batch_create([net], tile_be=256, grid_mult=0, xcd_group=0, no_graph=1)
         net._vjp_batch = b
     return b
+
+
+def _zeros(n, like):
+    return torch.zeros(n, dtype=torch.float64, device=like.device)
+
+
+class _BatchVjp(torch.autograd.Function):
+    """u = w_f grad f + J' w_c for every instance of a batch; differentiable."""
+
+    @staticmethod
+    def forward(ctx, x, w_f, w_c, batch):
+        x, w_f, w_c = x.contiguous(), w_f.contiguous(), w_c.contiguous()
+        u = torch.empty_like(x)
+        A.acopf_batch_vjp(batch, x, w_f, w_c, u)
+        ctx.save_for_backward(x, w_f, w_c)
+        ctx.batch = batch
+        return u
+
+    @staticmethod
+    def backward(ctx, gu):
+        x, w_f, w_c = ctx.saved_tensors
+        b = ctx.batch
+        gu = gu.contiguous()
+        gx = gwf = gwc = None
+        if ctx.needs_input_grad[0]:
+            gx = torch.empty_like(x)
+            A.acopf_batch_hvp(b, x, w_f, w_c, gu, gx)
+        if ctx.needs_input_grad[2]:
+            gwc = torch.empty_like(w_c)
+            A.acopf_batch_jvp(b, x, gu, gwc)
+        if ctx.needs_input_grad[1]:
+            gf = torch.empty_like(x)
+            A.acopf_batch_eval(b, x, None, None, None, gf, None, None, None, A.ACOPF_GRADF)
+            prod = gf * gu
+            gwf = torch.stack([prod[int(b.x_off[k]):int(b.x_off[k + 1])].sum()
+                               for k in range(b.count)])
+        return gx, gwf, gwc, None
 
 
 class AcopfEval(torch.autograd.Function):
@@ -39,13 +80,9 @@ class AcopfEval(torch.autograd.Function):
     def backward(ctx, gf, gc):
         (x,) = ctx.saved_tensors
         net = ctx.net
-        if gf is None:
-            gf = torch.zeros(1, dtype=torch.float64, device=x.device)
-        if gc is None:
-            gc = torch.zeros(net.m, dtype=torch.float64, device=x.device)
-        u = torch.empty_like(x)
-        A.acopf_batch_vjp(_one_batch(net), x, gf.contiguous(), gc.contiguous(), u)
-        return u, None
+        gf = _zeros(1, x) if gf is None else gf
+        gc = _zeros(net.m, x) if gc is None else gc
+        return _BatchVjp.apply(x, gf, gc, _one_batch(net)), None
 
 
 class AcopfBatchEval(torch.autograd.Function):
@@ -64,10 +101,6 @@ class AcopfBatchEval(torch.autograd.Function):
     def backward(ctx, gf, gc):
         (x,) = ctx.saved_tensors
         b = ctx.batch
-        if gf is None:
-            gf = torch.zeros(b.count, dtype=torch.float64, device=x.device)
-        if gc is None:
-            gc = torch.zeros(int(b.c_off[-1]), dtype=torch.float64, device=x.device)
-        u = torch.empty_like(x)
-        A.acopf_batch_vjp(b, x, gf.contiguous(), gc.contiguous(), u)
-        return u, None
+        gf = _zeros(b.count, x) if gf is None else gf
+        gc = _zeros(int(b.c_off[-1]), x) if gc is None else gc
+        return _BatchVjp.apply(x, gf, gc, b), None

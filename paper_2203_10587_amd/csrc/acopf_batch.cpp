@@ -26,7 +26,7 @@ constexpr size_t kGraphCache = 8;
 
 struct GraphKey {
   unsigned variant;
-  std::array<const void*, 11> ptrs;
+  std::array<const void*, 13> ptrs;
   bool operator==(const GraphKey& o) const { return variant == o.variant && ptrs == o.ptrs; }
 };
 
@@ -42,7 +42,6 @@ struct acopf_batch_s {
   acopf::InstOff* d_table = nullptr;
   acopf::Tile* d_tiles = nullptr;
   double* d_fpart = nullptr;
-  uint32_t* d_ticket = nullptr;
   int ntiles = 0;
   int grid = 0;  // 0: one workgroup per tile
   acopf::Tile* d_tiles_inst = nullptr;  // the same tiles, instance after instance
@@ -86,21 +85,28 @@ unsigned variant_of(unsigned what) {
   return K_ALL;
 }
 
+// The evaluation kernel, then (if f is wanted) the f reduction.
+hipError_t enqueue(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStream_t s) {
+  const InstOff none{};
+  hipError_t e = launch_eval(variant, b->sched.tile_be, bufs, b->d_table, none, b->d_tiles,
+                             b->ntiles, b->grid, s);
+  if (e == hipSuccess && bufs.f) e = launch_fsum(b->d_table, none, 0, b->count, bufs.fpart, bufs.f, s);
+  return e;
+}
+
 int run_batch(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStream_t stream) {
   int cur = 0;
   hipError_t e = hipGetDevice(&cur);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (cur != b->device) return fail(ACOPF_EINVAL, "batch lives on another device");
-  const int tile_be = b->sched.tile_be;
-  const InstOff none{};
   if (b->sched.no_graph) {
-    e = launch_eval(variant, tile_be, bufs, b->d_table, none, b->d_tiles, b->ntiles, b->grid, stream);
+    e = enqueue(b, variant, bufs, stream);
     if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
     return ACOPF_OK;
   }
   GraphKey key{variant,
                {bufs.x, bufs.lam, bufs.wc, bufs.sigma, bufs.wf, bufs.f, bufs.gradf, bufs.c,
-                bufs.jac, bufs.hess, bufs.u}};
+                bufs.jac, bufs.hess, bufs.u, bufs.dir, bufs.out}};
   hipGraphExec_t exec = nullptr;
   for (auto it = b->graphs.begin(); it != b->graphs.end(); ++it) {
     if (it->first == key) {
@@ -116,8 +122,7 @@ int run_batch(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStream_t 
     }
     e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t le =
-        launch_eval(variant, tile_be, bufs, b->d_table, none, b->d_tiles, b->ntiles, b->grid, b->cap_stream);
+    hipError_t le = enqueue(b, variant, bufs, b->cap_stream);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(b->cap_stream, &graph);
     if (le != hipSuccess) {
@@ -255,10 +260,9 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     const size_t s_tiles = align_up(tiles.size() * sizeof(Tile));
     const size_t s_tinst = align_up(tiles_inst.size() * sizeof(Tile));
     const size_t s_work = align_up(std::max<size_t>(work_total, 1) * sizeof(WorkItem));
-    const size_t s_slot = align_up(std::max<size_t>(slot_total, 1) * sizeof(int2));
+    const size_t s_slot = align_up(std::max<size_t>(slot_total, 1) * sizeof(uint32_t));
     const size_t s_fpart = align_up(size_t(fpo[count]) * sizeof(double));
-    const size_t s_ticket = align_up(size_t(count) * sizeof(uint32_t));
-    e = hipMalloc(&b->mem, s_table + s_tiles + s_work + s_slot + s_fpart + s_ticket + s_tinst);
+    e = hipMalloc(&b->mem, s_table + s_tiles + s_work + s_slot + s_fpart + s_tinst);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       b->mem = nullptr;
@@ -269,12 +273,9 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     b->d_table = reinterpret_cast<InstOff*>(base);
     b->d_tiles = reinterpret_cast<Tile*>(base + s_table);
     WorkItem* d_work = reinterpret_cast<WorkItem*>(base + s_table + s_tiles);
-    int2* d_slot = reinterpret_cast<int2*>(base + s_table + s_tiles + s_work);
+    uint32_t* d_slot = reinterpret_cast<uint32_t*>(base + s_table + s_tiles + s_work);
     b->d_fpart = reinterpret_cast<double*>(base + s_table + s_tiles + s_work + s_slot);
-    b->d_ticket =
-        reinterpret_cast<uint32_t*>(base + s_table + s_tiles + s_work + s_slot + s_fpart);
-    b->d_tiles_inst =
-        reinterpret_cast<Tile*>(base + s_table + s_tiles + s_work + s_slot + s_fpart + s_ticket);
+    b->d_tiles_inst = reinterpret_cast<Tile*>(base + s_table + s_tiles + s_work + s_slot + s_fpart);
     std::vector<InstOff> table(count);
     for (int k = 0; k < count; ++k) {
       InstOff I = net_inst(nets[k]);
@@ -297,13 +298,13 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
         e = hipMemcpy(d_work + kv.second.work_off, sc.work.data(), sc.work.size() * sizeof(WorkItem),
                       hipMemcpyHostToDevice);
       if (e == hipSuccess && !sc.slots.empty())
-        e = hipMemcpy(d_slot + kv.second.slot_off, sc.slots.data(), sc.slots.size() * sizeof(int2),
-                      hipMemcpyHostToDevice);
+        e = hipMemcpy(d_slot + kv.second.slot_off, sc.slots.data(),
+                      sc.slots.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess)
       e = hipMemcpy(b->d_tiles_inst, tiles_inst.data(), tiles_inst.size() * sizeof(Tile),
                     hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(b->d_fpart, 0, s_fpart + s_ticket);
+    if (e == hipSuccess) e = hipMemset(b->d_fpart, 0, s_fpart);
     if (e != hipSuccess) {
       free_batch(b);
       return hip_fail(e, "batch table upload");
@@ -354,8 +355,31 @@ int acopf_batch_eval(acopf_batch b, const double* x, const double* sigma, const 
   bufs.jac = (what & ACOPF_J) ? jac_val : nullptr;
   bufs.hess = (what & ACOPF_H) ? hess_val : nullptr;
   bufs.fpart = b->d_fpart;
-  bufs.ticket = b->d_ticket;
   return run_batch(b, variant_of(what), bufs, stream);
+}
+
+int acopf_batch_hvp(acopf_batch b, const double* x, const double* sigma, const double* lambda,
+                    const double* d, double* out, hipStream_t stream) {
+  if (!b || !x || !sigma || !lambda || !d || !out) return fail(ACOPF_EINVAL, "null argument");
+  Bufs bufs{};
+  bufs.x = x;
+  bufs.sigma = sigma;
+  bufs.lam = lambda;
+  bufs.dir = d;
+  bufs.out = out;
+  bufs.fpart = b->d_fpart;
+  return run_batch(b, K_HVP, bufs, stream);
+}
+
+int acopf_batch_jvp(acopf_batch b, const double* x, const double* d, double* out,
+                    hipStream_t stream) {
+  if (!b || !x || !d || !out) return fail(ACOPF_EINVAL, "null argument");
+  Bufs bufs{};
+  bufs.x = x;
+  bufs.dir = d;
+  bufs.out = out;
+  bufs.fpart = b->d_fpart;
+  return run_batch(b, K_JVP, bufs, stream);
 }
 
 int acopf_batch_eval_range(acopf_batch b, int32_t first, int32_t count, const double* x,
@@ -385,11 +409,11 @@ int acopf_batch_eval_range(acopf_batch b, int32_t first, int32_t count, const do
   bufs.jac = (what & ACOPF_J) ? jac_val : nullptr;
   bufs.hess = (what & ACOPF_H) ? hess_val : nullptr;
   bufs.fpart = b->d_fpart;
-  bufs.ticket = b->d_ticket;
   const int t0 = b->inst_tile_off[first], t1 = b->inst_tile_off[first + count];
   const InstOff none{};
   e = launch_eval(variant_of(what), b->sched.tile_be, bufs, b->d_table, none, b->d_tiles_inst + t0,
                   t1 - t0, 0, stream);
+  if (e == hipSuccess && bufs.f) e = launch_fsum(b->d_table, none, first, count, bufs.fpart, bufs.f, stream);
   if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
   return ACOPF_OK;
 }
@@ -420,7 +444,6 @@ int acopf_batch_vjp(acopf_batch b, const double* x, const double* w_f, const dou
   bufs.wc = w_c;
   bufs.u = u;
   bufs.fpart = b->d_fpart;
-  bufs.ticket = b->d_ticket;
   return run_batch(b, K_VJP, bufs, stream);
 }
 

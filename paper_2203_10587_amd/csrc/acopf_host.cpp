@@ -268,9 +268,11 @@ void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,
   for (int k = 0; k < ng; ++k) hp->push_back(int32_t(hc->size()));
 }
 
-// Slot-map entry: signed sum of record `field` over branch ends [ea, ea+cnt).
-static int2 slot(int ea, int cnt, int field, int neg, int kind, int bl) {
-  return make_int2(ea | (cnt << 16), field | (neg << 4) | (kind << 5) | (bl << 8));
+// Slot-map entry: signed sum of record `field` over branch ends [ea, ea+cnt);
+// the caps keep ea < 512, cnt <= 512 and bl < 256 (checked when the tile closes).
+static uint32_t slot(int ea, int cnt, int field, int neg, int kind, int bl) {
+  return uint32_t(ea) | (uint32_t(cnt) << 9) | (uint32_t(field) << 19) | (uint32_t(neg) << 21) |
+         (uint32_t(kind) << 22) | (uint32_t(bl) << 24);
 }
 
 int make_tiles(const Topology& T, int tile_be, Schedule* S) {
@@ -296,7 +298,7 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
     int j, ea, cnt;
   };
   std::vector<Grp> grp;
-  std::vector<int2> sT, sV;
+  std::vector<uint32_t> sT, sV;
   bool tiler_error = false;
   auto close = [&](int b0, int b1) {
     const int e0 = T.be_ptr[b0], e1 = T.be_ptr[b1];
@@ -365,9 +367,10 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
     // the slot map must cover exactly the tile's row segments, and every
     // record range must lie inside the tile
     bool ok = nP == r1.x - r0.x && int(sT.size()) == r1.z - r0.z && int(sV.size()) == r1.w - r0.w;
+    ok = ok && e1 - e0 <= 512 && b1 - b0 <= 256 && int(S->slots.size()) - sm0 <= caps.spl * caps.wg;
     for (size_t k = sm0; ok && k < S->slots.size(); ++k) {
-      const int2 en = S->slots[k];
-      ok = (en.x & 0xFFFF) + (en.x >> 16) <= e1 - e0 && (en.y >> 8) < b1 - b0;
+      const uint32_t en = S->slots[k];
+      ok = int(en & 511u) + int((en >> 9) & 1023u) <= e1 - e0 && int(en >> 24) < b1 - b0;
     }
     if (!ok) {
       tiler_error = true;
@@ -392,19 +395,25 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
     tl.hV0 = r0.w;
     S->tiles.push_back(tl);
   };
-  int b0 = 0, cur_be = 0;
+  const int slotcap = caps.spl * caps.wg;
+  int b0 = 0, cur_be = 0, cur_sl = 0;
   for (int i = 0; i < T.nb; ++i) {
     const int d = T.be_ptr[i + 1] - T.be_ptr[i];
-    if (d > caps.be)
+    const int a = T.acnt[i].x, lo = T.acnt[i].y, g = T.gen_ptr[i + 1] - T.gen_ptr[i];
+    const int sl = (2 * a + g) + (lo + 1) + (a + lo + 1);  // J P row, H theta row, H v row
+    if (d > caps.be || sl > slotcap)
       return fail(ACOPF_EINVAL, "bus " + std::to_string(i) + " has " + std::to_string(d) +
-                                    " branch ends; a bus tile of this schedule holds at most " +
-                                    std::to_string(caps.be));
-    if (i > b0 && (cur_be + d > caps.be || i - b0 >= caps.nbus)) {
+                                    " branch ends and " + std::to_string(sl) +
+                                    " row entries; a bus tile of this schedule holds at most " +
+                                    std::to_string(caps.be) + " and " + std::to_string(slotcap));
+    if (i > b0 && (cur_be + d > caps.be || cur_sl + sl > slotcap || i - b0 >= caps.nbus)) {
       close(b0, i);
       b0 = i;
       cur_be = 0;
+      cur_sl = 0;
     }
     cur_be += d;
+    cur_sl += sl;
   }
   close(b0, T.nb);
   if (tiler_error) return fail(ACOPF_EINVAL, "internal: slot map does not match the pattern");
@@ -488,7 +497,7 @@ int upload_base(Base* B) {
       {T.c0.data(), T.c0.size() * sizeof(double), 0},
       {B->plain.tiles.data(), B->plain.tiles.size() * sizeof(Tile), 0},
       {B->plain.work.data(), B->plain.work.size() * sizeof(WorkItem), 0},
-      {B->plain.slots.data(), B->plain.slots.size() * sizeof(int2), 0},
+      {B->plain.slots.data(), B->plain.slots.size() * sizeof(uint32_t), 0},
       {nullptr, sizeof(NetDev), 0},
   };
   size_t total = 0;
@@ -528,7 +537,7 @@ int upload_base(Base* B) {
   nd.hpg = T.hpg;
   B->d_tiles = static_cast<Tile*>(at(9));
   B->d_work = static_cast<WorkItem*>(at(10));
-  B->d_slots = static_cast<int2*>(at(11));
+  B->d_slots = static_cast<uint32_t*>(at(11));
   B->d_net = static_cast<NetDev*>(at(12));
   parts[12].src = &nd;
   for (const Part& p : parts) {
@@ -681,7 +690,7 @@ namespace acopf {
 
 int net_init_scratch(acopf_net_s* net) {
   const int nch = net->base->topo.nchunks;
-  const size_t bytes = align_up(nch * sizeof(double)) + 256;
+  const size_t bytes = align_up(nch * sizeof(double));
   int cur = 0;
   hipError_t e = hipGetDevice(&cur);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -699,7 +708,6 @@ int net_init_scratch(acopf_net_s* net) {
   }
   net->scratch = p;
   net->d_fpart = static_cast<double*>(p);
-  net->d_ticket = reinterpret_cast<uint32_t*>(static_cast<char*>(p) + align_up(nch * sizeof(double)));
   return ACOPF_OK;
 }
 
@@ -734,13 +742,13 @@ static int run_plain(const acopf_net_s* net, unsigned variant, Bufs b, bool bus,
   if (rc) return rc;
   const Base& B = *net->base;
   b.fpart = net->d_fpart;
-  b.ticket = net->d_ticket;
   const int nbu = B.plain.counts[0], ngt = B.plain.counts[1];
   if (!bus && !gen) return ACOPF_OK;
   const int t0 = bus ? 0 : nbu;
   const int t1 = gen ? nbu + ngt : nbu;
   const InstOff one = net_inst(net);
   hipError_t e = launch_eval(variant, kDefaultTileBe, b, nullptr, one, B.d_tiles + t0, t1 - t0, 0, s);
+  if (e == hipSuccess && b.f) e = launch_fsum(nullptr, one, 0, 1, b.fpart, b.f, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return ACOPF_OK;
 }
@@ -789,6 +797,27 @@ int acopf_vjp(acopf_net net, const double* x, double w_f, const double* w_c, dou
   b.wf_v = w_f;
   b.u = u;
   return run_plain(net, K_VJP, b, true, true, stream);
+}
+
+int acopf_hvp(acopf_net net, const double* x, double sigma, const double* lambda, const double* d,
+              double* out, hipStream_t stream) {
+  if (!net || !x || !lambda || !d || !out) return fail(ACOPF_EINVAL, "null argument");
+  Bufs b{};
+  b.x = x;
+  b.lam = lambda;
+  b.sigma_v = sigma;
+  b.dir = d;
+  b.out = out;
+  return run_plain(net, K_HVP, b, true, true, stream);
+}
+
+int acopf_jvp(acopf_net net, const double* x, const double* d, double* out, hipStream_t stream) {
+  if (!net || !x || !d || !out) return fail(ACOPF_EINVAL, "null argument");
+  Bufs b{};
+  b.x = x;
+  b.dir = d;
+  b.out = out;
+  return run_plain(net, K_JVP, b, true, false, stream);
 }
 
 int acopf_eval_all(acopf_net net, const double* x, double sigma, const double* lambda, double* f,

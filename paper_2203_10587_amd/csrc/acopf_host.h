@@ -32,7 +32,7 @@ struct Topology {
 struct Schedule {
   std::vector<Tile> tiles;        // [bus tiles][gen tiles]
   std::vector<WorkItem> work;
-  std::vector<int2> slots;
+  std::vector<uint32_t> slots;
   int counts[2] = {0, 0};
 };
 
@@ -45,7 +45,7 @@ struct Base {
   NetDev* d_net = nullptr;
   Tile* d_tiles = nullptr;           // plain-path schedule on the device
   WorkItem* d_work = nullptr;
-  int2* d_slots = nullptr;
+  uint32_t* d_slots = nullptr;
   Schedule plain;
   ~Base();
 };
@@ -60,9 +60,8 @@ struct acopf_net_s {
                    INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
   int32_t rh[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
   acopf_dims dims{};
-  void* scratch = nullptr;           // f partials + ticket of the plain path
+  void* scratch = nullptr;           // f partials of the plain path
   double* d_fpart = nullptr;
-  uint32_t* d_ticket = nullptr;
   std::atomic<int> refs{0};          // outage children and batches using this net
 };
 

@@ -46,9 +46,10 @@ struct WorkItem {
   uint32_t slots;
 };
 
-// One output entry: value = (-1)^neg * sum of record field `field` over
-// branch ends [ea, ea + cnt) of the tile, plus the bus extra of `kind`.
-//   x = ea | cnt << 16;  y = field | neg << 4 | kind << 5 | bus_local << 8
+// One output entry, packed in 32 bits: value = (-1)^neg * sum of record
+// field `field` over branch ends [ea, ea + cnt) of the tile, plus the bus
+// extra of `kind` for tile-local bus `bl`:
+//   ea (9 bits) | cnt << 9 (10) | field << 19 (2) | neg << 21 | kind << 22 (2) | bl << 24 (8)
 enum SlotKind : int32_t {
   SK_SUM = 0,      // plain signed sum
   SK_JDIAG_V = 1,  // J diagonal d/dv_i: + 2 gs v_i (P row) or - 2 bs v_i (Q row)
@@ -85,7 +86,7 @@ struct NetDev {
 struct InstOff {
   const NetDev* net;
   const WorkItem* work;     // work items of the schedule in use
-  const int2* slots;        // slot map of the schedule in use
+  const uint32_t* slots;    // slot map of the schedule in use
   int32_t out_l;            // removed branch, -1 for none
   int32_t out_rm;           // 1 if the removal drops the (p, q) slots
   int32_t rj[8];
@@ -94,7 +95,7 @@ struct InstOff {
   int64_t co;               // lambda, c, w_c
   int64_t jo;               // Jacobian values
   int64_t ho;               // Hessian values
-  int32_t k;                // instance index: f, sigma, w_f, ticket
+  int32_t k;                // instance index: f, sigma, w_f
   int32_t fpo;              // first f partial of this instance
 };
 
@@ -111,24 +112,26 @@ struct Bufs {
   double* jac;
   double* hess;
   double* u;
+  const double* dir;        // direction of a Hessian- or Jacobian-vector product
+  double* out;              // H dir (length n) or J dir (length m)
   double* fpart;            // f partial sums, one per generator chunk
-  uint32_t* ticket;         // per instance: gen chunks finished in this launch
 };
 
 enum : unsigned {
-  W_F = 1u, W_GRADF = 2u, W_C = 4u, W_J = 8u, W_H = 16u, W_VJP = 32u,
+  W_F = 1u, W_GRADF = 2u, W_C = 4u, W_J = 8u, W_H = 16u, W_VJP = 32u, W_HVP = 64u, W_JVP = 128u,
 };
 
 // Tile capacities of one schedule: workgroup size, branch ends per bus tile
-// (LDS records) and buses per bus tile (LDS bus extras).
+// (LDS records), buses per bus tile (LDS bus terms) and slot-map entries per
+// lane (prefetched into registers at the start of the tile).
 struct TileCaps {
-  int32_t wg, be, nbus;
+  int32_t wg, be, nbus, spl;
 };
 
-constexpr TileCaps kCaps64 = {64, 64, 32};
-constexpr TileCaps kCaps128 = {128, 128, 64};
-constexpr TileCaps kCaps256 = {256, 256, 128};
-constexpr TileCaps kCaps512 = {256, 512, 256};
+constexpr TileCaps kCaps64 = {64, 64, 32, 8};
+constexpr TileCaps kCaps128 = {128, 128, 64, 8};
+constexpr TileCaps kCaps256 = {256, 256, 128, 8};
+constexpr TileCaps kCaps512 = {256, 512, 256, 12};
 constexpr int kDefaultTileBe = 256;
 
 inline bool caps_for(int tile_be, TileCaps* out) {
@@ -148,7 +151,14 @@ enum : unsigned {
   K_H = W_H,
   K_ALL = W_F | W_GRADF | W_C | W_J | W_H,
   K_VJP = W_VJP,
+  K_HVP = W_HVP,
+  K_JVP = W_JVP,
 };
+
+// Enqueue the f reduction for instances [first, first + count) (table) or
+// the one instance `one` (table == nullptr, first = 0, count = 1).
+hipError_t launch_fsum(const InstOff* table, const InstOff& one, int first, int count,
+                       const double* fpart, double* f, hipStream_t stream);
 
 // Enqueue one evaluation kernel over `ntiles` tiles.  grid = 0 launches one
 // workgroup per tile; otherwise a persistent grid of `grid` workgroups

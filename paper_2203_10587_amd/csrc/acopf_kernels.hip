@@ -25,8 +25,9 @@
 //            whatever the tiling.
 //  gen tile  a fixed chunk of 256 generators: grad f, the Pg diagonal of H,
 //            the Pg/Qg part of the VJP and a fixed-tree partial sum of the
-//            cost; the last chunk of an instance to finish (ticket counter)
-//            adds the partials in chunk order into f and re-arms the counter.
+//            cost; a second small kernel adds each instance's partials in
+//            chunk order into f (a kernel boundary instead of fences: an
+//            agent-scope release fence per chunk writes back the whole L2).
 //
 // The model (paper: OPFLOW section, power-balance-polar representation; the
 // formulation itself is the standard polar pi-model one the paper refers to):
@@ -48,14 +49,27 @@ namespace acopf {
 namespace {
 
 // ---------------------------------------------------------------------------
-// one branch: both end flows and first derivatives with respect to
-// (theta_f, v_f, v_t)
+// one branch: both end flows; first derivatives with respect to
+// (theta_f, v_f, v_t) are formed where they are used (members below)
 
 struct Br {
   double vf, vt, w, cP, cQ, cPt, cQt;
+  double gff, bff, gtt, btt;
   double Pf, Qf, Pt, Qt;
-  double Pf_a, Pf_f, Pf_t, Qf_a, Qf_f, Qf_t;  // d/dtheta_f, d/dv_f, d/dv_t of the from flow
-  double Pt_a, Pt_f, Pt_t, Qt_a, Qt_f, Qt_t;  // ... of the to flow
+  // d/dtheta_f (a), d/dv_f (f), d/dv_t (t) of the from flow ...
+  __device__ __forceinline__ double Pf_a() const { return -(w * cQ); }
+  __device__ __forceinline__ double Pf_f() const { return fma(2.0 * gff, vf, vt * cP); }
+  __device__ __forceinline__ double Pf_t() const { return vf * cP; }
+  __device__ __forceinline__ double Qf_a() const { return w * cP; }
+  __device__ __forceinline__ double Qf_f() const { return fma(-2.0 * bff, vf, vt * cQ); }
+  __device__ __forceinline__ double Qf_t() const { return vf * cQ; }
+  // ... and of the to flow
+  __device__ __forceinline__ double Pt_a() const { return w * cQt; }
+  __device__ __forceinline__ double Pt_f() const { return vt * cPt; }
+  __device__ __forceinline__ double Pt_t() const { return fma(2.0 * gtt, vt, vf * cPt); }
+  __device__ __forceinline__ double Qt_a() const { return -(w * cPt); }
+  __device__ __forceinline__ double Qt_f() const { return vt * cQt; }
+  __device__ __forceinline__ double Qt_t() const { return fma(-2.0 * btt, vt, vf * cQt); }
 };
 
 __device__ __forceinline__ void branch_eval(double thf, double tht, double vf, double vt,
@@ -63,34 +77,21 @@ __device__ __forceinline__ void branch_eval(double thf, double tht, double vf, d
   double sn, cs;
   sincos(thf - tht, &sn, &cs);
   const double w = vf * vt;
-  const double cP = fma(y.gft, cs, y.bft * sn);
-  const double cQ = fma(y.gft, sn, -(y.bft * cs));
-  const double cPt = fma(y.gtf, cs, -(y.btf * sn));
-  const double cQt = -fma(y.gtf, sn, y.btf * cs);
   o.vf = vf;
   o.vt = vt;
   o.w = w;
-  o.cP = cP;
-  o.cQ = cQ;
-  o.cPt = cPt;
-  o.cQt = cQt;
-  const double vf2 = vf * vf, vt2 = vt * vt;
-  o.Pf = fma(y.gff, vf2, w * cP);
-  o.Qf = fma(-y.bff, vf2, w * cQ);
-  o.Pt = fma(y.gtt, vt2, w * cPt);
-  o.Qt = fma(-y.btt, vt2, w * cQt);
-  o.Pf_a = -(w * cQ);
-  o.Pf_f = fma(2.0 * y.gff, vf, vt * cP);
-  o.Pf_t = vf * cP;
-  o.Qf_a = w * cP;
-  o.Qf_f = fma(-2.0 * y.bff, vf, vt * cQ);
-  o.Qf_t = vf * cQ;
-  o.Pt_a = w * cQt;
-  o.Pt_f = vt * cPt;
-  o.Pt_t = fma(2.0 * y.gtt, vt, vf * cPt);
-  o.Qt_a = -(w * cPt);
-  o.Qt_f = vt * cQt;
-  o.Qt_t = fma(-2.0 * y.btt, vt, vf * cQt);
+  o.cP = fma(y.gft, cs, y.bft * sn);
+  o.cQ = fma(y.gft, sn, -(y.bft * cs));
+  o.cPt = fma(y.gtf, cs, -(y.btf * sn));
+  o.cQt = -fma(y.gtf, sn, y.btf * cs);
+  o.gff = y.gff;
+  o.bff = y.bff;
+  o.gtt = y.gtt;
+  o.btt = y.btt;
+  o.Pf = fma(y.gff, vf * vf, w * o.cP);
+  o.Qf = fma(-y.bff, vf * vf, w * o.cQ);
+  o.Pt = fma(y.gtt, vt * vt, w * o.cPt);
+  o.Qt = fma(-y.btt, vt * vt, w * o.cQt);
 }
 
 // Record layout of phase A (structure of arrays in LDS, BE entries per field).
@@ -100,11 +101,15 @@ struct Rec {
   static constexpr bool J = (WHAT & W_J) != 0;
   static constexpr bool H = (WHAT & W_H) != 0;
   static constexpr bool V = (WHAT & W_VJP) != 0;
+  static constexpr bool HV = (WHAT & W_HVP) != 0;
+  static constexpr bool JV = (WHAT & W_JVP) != 0;
   static constexpr int oC = 0;                  // P_e, Q_e
   static constexpr int oJ = oC + (C ? 2 : 0);   // dP/dth_e, dP/dv_e, dP/dv_o, dQ/... (o = far end)
   static constexpr int oH = oJ + (J ? 6 : 0);   // d2/dth_e2, d2/dv_e dth_e, d2/dv_e2, d2/dv_e dv_o
   static constexpr int oV = oH + (H ? 4 : 0);   // u_th_e, u_v_e
-  static constexpr int N = oV + (V ? 2 : 0);
+  static constexpr int oHV = oV + (V ? 2 : 0);  // (H d)_th_e, (H d)_v_e
+  static constexpr int oJV = oHV + (HV ? 2 : 0); // (J d) of P_e, of Q_e
+  static constexpr int N = oJV + (JV ? 2 : 0);
 };
 
 // Bus terms staged by phase A (structure of arrays, NBUS entries per field).
@@ -114,11 +119,15 @@ struct BusRec {
   static constexpr bool J = (WHAT & W_J) != 0;
   static constexpr bool H = (WHAT & W_H) != 0;
   static constexpr bool V = (WHAT & W_VJP) != 0;
+  static constexpr bool HV = (WHAT & W_HVP) != 0;
+  static constexpr bool JV = (WHAT & W_JVP) != 0;
   static constexpr int oJ = 0;                  // 2 gs v, -2 bs v
   static constexpr int oH = oJ + (J ? 2 : 0);   // 2 (lP gs - lQ bs)
   static constexpr int oC = oH + (H ? 1 : 0);   // (gs v^2 - Pg) + Pd, (-bs v^2 - Qg) + Qd
   static constexpr int oV = oC + (C ? 2 : 0);   // 2 v (wP gs - wQ bs)
-  static constexpr int N = oV + (V ? 1 : 0);
+  static constexpr int oHV = oV + (V ? 1 : 0);  // 2 (lP gs - lQ bs) d_v
+  static constexpr int oJV = oHV + (HV ? 1 : 0); // 2 gs v d_v - sum d_Pg, -2 bs v d_v - sum d_Qg
+  static constexpr int N = oJV + (JV ? 2 : 0);
 };
 
 template <unsigned WHAT, int BE, int NBUS>
@@ -149,11 +158,34 @@ __device__ __forceinline__ int shifted(int gp, const int32_t (&r)[NR]) {
   return gone ? -1 : gp - below;
 }
 
-template <unsigned WHAT, int WG, int BE, int NBUS>
+// The same for a whole segment [s0, s0 + n) of base positions: when no
+// removed position falls inside it, every entry moves by one constant.
+struct SegShift {
+  int below;
+  bool inside;
+  template <int NR>
+  __device__ __forceinline__ SegShift(int s0, int n, const int32_t (&r)[NR]) : below(0), inside(false) {
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      below += r[m] < s0 ? 1 : 0;
+      inside = inside || (r[m] >= s0 && r[m] < s0 + n);
+    }
+  }
+};
+
+template <int NR>
+__device__ __forceinline__ int place(int gp, const SegShift& sg, const int32_t (&r)[NR]) {
+  return sg.inside ? shifted(gp, r) : gp - sg.below;
+}
+
+template <unsigned WHAT, int WG, int BE, int NBUS, int SPL>
 __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const Tile& T,
                          double* smem) {
   using R = Rec<WHAT>;
   using U = BusRec<WHAT>;
+  constexpr bool SLOTS = R::J || R::H;
+  const int nS = T.nP + T.nT + T.nV;
+  uint32_t pre[SPL];
   constexpr bool DO_GF = (WHAT & W_GRADF) != 0 && !R::V;
   const int tid = threadIdx.x;
   const int nb = N.nb;
@@ -164,8 +196,9 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   double* bus = smem + Lds<WHAT, BE, NBUS>::kRec;
   int2* bus_e = reinterpret_cast<int2*>(bus + U::N * NBUS);
   const double* x = B.x + I.xo;
-  const double* mul = R::H ? B.lam + I.co : (R::V ? B.wc + I.co : nullptr);
-  const bool hneed = R::V || (R::H && B.hess != nullptr);
+  const double* mul = (R::H || R::HV) ? B.lam + I.co : (R::V ? B.wc + I.co : nullptr);
+  const bool hneed = R::V || R::HV || (R::H && B.hess != nullptr);
+  const double* dir = (R::HV || R::JV) ? B.dir + I.xo : nullptr;
   double* cflow = (R::C && B.c) ? B.c + I.co + 2 * nb : nullptr;
   double* jflow = (R::J && B.jac) ? B.jac + I.jo + (N.jflow - 8 * I.out_rm) : nullptr;
 
@@ -198,20 +231,38 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
     }
     if constexpr (R::J) {
       if (sf != kNoSlot) {
-        rec[(R::oJ + 0) * BE + sf] = b.Pf_a;
-        rec[(R::oJ + 1) * BE + sf] = b.Pf_f;
-        rec[(R::oJ + 2) * BE + sf] = b.Pf_t;
-        rec[(R::oJ + 3) * BE + sf] = b.Qf_a;
-        rec[(R::oJ + 4) * BE + sf] = b.Qf_f;
-        rec[(R::oJ + 5) * BE + sf] = b.Qf_t;
+        rec[(R::oJ + 0) * BE + sf] = b.Pf_a();
+        rec[(R::oJ + 1) * BE + sf] = b.Pf_f();
+        rec[(R::oJ + 2) * BE + sf] = b.Pf_t();
+        rec[(R::oJ + 3) * BE + sf] = b.Qf_a();
+        rec[(R::oJ + 4) * BE + sf] = b.Qf_f();
+        rec[(R::oJ + 5) * BE + sf] = b.Qf_t();
       }
       if (st != kNoSlot) {  // to end: d/dtheta_t = -d/dtheta_f
-        rec[(R::oJ + 0) * BE + st] = -b.Pt_a;
-        rec[(R::oJ + 1) * BE + st] = b.Pt_t;
-        rec[(R::oJ + 2) * BE + st] = b.Pt_f;
-        rec[(R::oJ + 3) * BE + st] = -b.Qt_a;
-        rec[(R::oJ + 4) * BE + st] = b.Qt_t;
-        rec[(R::oJ + 5) * BE + st] = b.Qt_f;
+        rec[(R::oJ + 0) * BE + st] = -b.Pt_a();
+        rec[(R::oJ + 1) * BE + st] = b.Pt_t();
+        rec[(R::oJ + 2) * BE + st] = b.Pt_f();
+        rec[(R::oJ + 3) * BE + st] = -b.Qt_a();
+        rec[(R::oJ + 4) * BE + st] = b.Qt_t();
+        rec[(R::oJ + 5) * BE + st] = b.Qt_f();
+      }
+    }
+    if constexpr (R::JV) {  // J d: first derivatives along the direction
+      const double da = dir[f] - dir[t], dvf = dir[nb + f], dvt = dir[nb + t];
+      const double jPf = fma(b.Pf_a(), da, fma(b.Pf_f(), dvf, b.Pf_t() * dvt));
+      const double jQf = fma(b.Qf_a(), da, fma(b.Qf_f(), dvf, b.Qf_t() * dvt));
+      const double jPt = fma(b.Pt_a(), da, fma(b.Pt_f(), dvf, b.Pt_t() * dvt));
+      const double jQt = fma(b.Qt_a(), da, fma(b.Qt_f(), dvf, b.Qt_t() * dvt));
+      if (sf != kNoSlot) {
+        rec[(R::oJV + 0) * BE + sf] = jPf;
+        rec[(R::oJV + 1) * BE + sf] = jQf;
+        double* o = B.out + I.co + 2 * nb;
+        o[lp] = 2.0 * fma(b.Pf, jPf, b.Qf * jQf);
+        o[nll + lp] = 2.0 * fma(b.Pt, jPt, b.Qt * jQt);
+      }
+      if (st != kNoSlot) {
+        rec[(R::oJV + 0) * BE + st] = jPt;
+        rec[(R::oJV + 1) * BE + st] = jQt;
       }
     }
     if (sf != kNoSlot) {  // the from-bus owner writes the flow-limit rows
@@ -220,12 +271,12 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
         cflow[nll + lp] = fma(b.Pt, b.Pt, b.Qt * b.Qt);
       }
       if (jflow) {
-        const double hf_a = 2.0 * fma(b.Pf, b.Pf_a, b.Qf * b.Qf_a);
-        const double hf_f = 2.0 * fma(b.Pf, b.Pf_f, b.Qf * b.Qf_f);
-        const double hf_t = 2.0 * fma(b.Pf, b.Pf_t, b.Qf * b.Qf_t);
-        const double ht_a = 2.0 * fma(b.Pt, b.Pt_a, b.Qt * b.Qt_a);
-        const double ht_f = 2.0 * fma(b.Pt, b.Pt_f, b.Qt * b.Qt_f);
-        const double ht_t = 2.0 * fma(b.Pt, b.Pt_t, b.Qt * b.Qt_t);
+        const double hf_a = 2.0 * fma(b.Pf, b.Pf_a(), b.Qf * b.Qf_a());
+        const double hf_f = 2.0 * fma(b.Pf, b.Pf_f(), b.Qf * b.Qf_f());
+        const double hf_t = 2.0 * fma(b.Pf, b.Pf_t(), b.Qf * b.Qf_t());
+        const double ht_a = 2.0 * fma(b.Pt, b.Pt_a(), b.Qt * b.Qt_a());
+        const double ht_f = 2.0 * fma(b.Pt, b.Pt_f(), b.Qt * b.Qt_f());
+        const double ht_t = 2.0 * fma(b.Pt, b.Pt_t(), b.Qt * b.Qt_t());
         const bool asc = f < t;  // columns ascend: theta_lo, theta_hi, v_lo, v_hi
         double* rf = jflow + 4 * lp;
         double* rt = jflow + 4 * nll + 4 * lp;
@@ -239,7 +290,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
         rt[3] = asc ? ht_t : ht_f;
       }
     }
-    if constexpr (R::H || R::V) {
+    if constexpr (R::H || R::V || R::HV) {
       if (!hneed) continue;  // the full variant reads multipliers only when H is wanted
       const double mf = mul[2 * nb + lp];
       const double mt = mul[2 * nb + nll + lp];
@@ -248,57 +299,83 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       const double oQf = fma(2.0 * mf, b.Qf, mul[nb + f]);
       const double oPt = fma(2.0 * mt, b.Pt, mul[t]);
       const double oQt = fma(2.0 * mt, b.Qt, mul[nb + t]);
-      if constexpr (R::H) {
-        // s: the weighted transfer terms; d2L/dv_f dv_t starts with s and
-        // d2L/dtheta_f^2 with -w s
-        const double s = fma(oPf, b.cP, fma(oQf, b.cQ, fma(oPt, b.cPt, oQt * b.cQt)));
-        const double m2f = 2.0 * mf, m2t = 2.0 * mt;
-        const double a = fma(-b.w, s,
-                             fma(m2f, fma(b.Pf_a, b.Pf_a, b.Qf_a * b.Qf_a),
-                                 m2t * fma(b.Pt_a, b.Pt_a, b.Qt_a * b.Qt_a)));
-        // d2L/dv_f dtheta_f
-        const double r = fma(oQf, b.cP, fma(-oPf, b.cQ, fma(oPt, b.cQt, -(oQt * b.cPt))));
-        const double beta_f = fma(b.vt, r,
-                                  fma(m2f, fma(b.Pf_f, b.Pf_a, b.Qf_f * b.Qf_a),
-                                      m2t * fma(b.Pt_f, b.Pt_a, b.Qt_f * b.Qt_a)));
-        // d2L/dv_t dtheta_t = -d2L/dv_t dtheta_f
-        const double beta_t = -fma(b.vf, r,
-                                   fma(m2f, fma(b.Pf_t, b.Pf_a, b.Qf_t * b.Qf_a),
-                                       m2t * fma(b.Pt_t, b.Pt_a, b.Qt_t * b.Qt_a)));
-        const double vv_ff = fma(2.0, fma(oPf, y.gff, -(oQf * y.bff)),
-                                 fma(m2f, fma(b.Pf_f, b.Pf_f, b.Qf_f * b.Qf_f),
-                                     m2t * fma(b.Pt_f, b.Pt_f, b.Qt_f * b.Qt_f)));
-        const double vv_tt = fma(2.0, fma(oPt, y.gtt, -(oQt * y.btt)),
-                                 fma(m2f, fma(b.Pf_t, b.Pf_t, b.Qf_t * b.Qf_t),
-                                     m2t * fma(b.Pt_t, b.Pt_t, b.Qt_t * b.Qt_t)));
-        const double vv_ft = s + fma(m2f, fma(b.Pf_f, b.Pf_t, b.Qf_f * b.Qf_t),
-                                     m2t * fma(b.Pt_f, b.Pt_t, b.Qt_f * b.Qt_t));
-        if (sf != kNoSlot) {
-          rec[(R::oH + 0) * BE + sf] = a;
-          rec[(R::oH + 1) * BE + sf] = beta_f;
-          rec[(R::oH + 2) * BE + sf] = vv_ff;
-          rec[(R::oH + 3) * BE + sf] = vv_ft;
-        }
-        if (st != kNoSlot) {
-          rec[(R::oH + 0) * BE + st] = a;
-          rec[(R::oH + 1) * BE + st] = beta_t;
-          rec[(R::oH + 2) * BE + st] = vv_tt;
-          rec[(R::oH + 3) * BE + st] = vv_ft;
-        }
-      }
+      // s, r: the weighted transfer terms; every second derivative and the
+      // VJP are short expressions in them (the Gauss-Newton cross terms
+      // Pt_f Pt_a + Qt_f Qt_a and Pf_t Pf_a + Qf_t Qf_a vanish identically)
+      const double s = fma(oPf, b.cP, fma(oQf, b.cQ, fma(oPt, b.cPt, oQt * b.cQt)));
+      const double r = fma(oQf, b.cP, fma(-oPf, b.cQ, fma(oPt, b.cQt, -(oQt * b.cPt))));
       if constexpr (R::V) {
-        const double u_a = fma(oPf, b.Pf_a, fma(oQf, b.Qf_a, fma(oPt, b.Pt_a, oQt * b.Qt_a)));
+        const double u_a = b.w * r;  // d/dtheta_f; d/dtheta_t = -u_a
+        const double u_f = fma(2.0 * b.vf, fma(oPf, b.gff, -(oQf * b.bff)), b.vt * s);
+        const double u_t = fma(2.0 * b.vt, fma(oPt, b.gtt, -(oQt * b.btt)), b.vf * s);
         if (sf != kNoSlot) {
           rec[(R::oV + 0) * BE + sf] = u_a;
-          rec[(R::oV + 1) * BE + sf] =
-              fma(oPf, b.Pf_f, fma(oQf, b.Qf_f, fma(oPt, b.Pt_f, oQt * b.Qt_f)));
+          rec[(R::oV + 1) * BE + sf] = u_f;
         }
         if (st != kNoSlot) {
           rec[(R::oV + 0) * BE + st] = -u_a;
-          rec[(R::oV + 1) * BE + st] =
-              fma(oPf, b.Pf_t, fma(oQf, b.Qf_t, fma(oPt, b.Pt_t, oQt * b.Qt_t)));
+          rec[(R::oV + 1) * BE + st] = u_t;
         }
       }
+      if constexpr (R::H || R::HV) {
+        const double m2f = 2.0 * mf, m2t = 2.0 * mt;
+        const double ccf = fma(b.cP, b.cP, b.cQ * b.cQ), cct = fma(b.cPt, b.cPt, b.cQt * b.cQt);
+        // d2L/dtheta_f^2
+        const double a = fma(-b.w, s, (b.w * b.w) * fma(m2f, ccf, m2t * cct));
+        // d2L/dv_f dtheta_f and d2L/dv_t dtheta_t
+        const double beta_f =
+            fma(b.vt, r, -(2.0 * m2f) * (b.vf * b.w) * fma(b.gff, b.cQ, b.bff * b.cP));
+        const double beta_t =
+            -fma(b.vf, r, (2.0 * m2t) * (b.vt * b.w) * fma(b.gtt, b.cQt, b.btt * b.cPt));
+        const double pff = b.Pf_f(), qff = b.Qf_f(), ptt = b.Pt_t(), qtt = b.Qt_t();
+        const double vv_ff = fma(2.0, fma(oPf, b.gff, -(oQf * b.bff)),
+                                 fma(m2f, fma(pff, pff, qff * qff), m2t * (b.vt * b.vt) * cct));
+        const double vv_tt = fma(2.0, fma(oPt, b.gtt, -(oQt * b.btt)),
+                                 fma(m2f * (b.vf * b.vf), ccf, m2t * fma(ptt, ptt, qtt * qtt)));
+        const double vv_ft =
+            s + fma(m2f * b.vf, fma(2.0 * b.vf, fma(b.gff, b.cP, -(b.bff * b.cQ)), b.vt * ccf),
+                    m2t * b.vt * fma(2.0 * b.vt, fma(b.gtt, b.cPt, -(b.btt * b.cQt)), b.vf * cct));
+        if constexpr (R::H) {
+          if (sf != kNoSlot) {
+            rec[(R::oH + 0) * BE + sf] = a;
+            rec[(R::oH + 1) * BE + sf] = beta_f;
+            rec[(R::oH + 2) * BE + sf] = vv_ff;
+            rec[(R::oH + 3) * BE + sf] = vv_ft;
+          }
+          if (st != kNoSlot) {
+            rec[(R::oH + 0) * BE + st] = a;
+            rec[(R::oH + 1) * BE + st] = beta_t;
+            rec[(R::oH + 2) * BE + st] = vv_tt;
+            rec[(R::oH + 3) * BE + st] = vv_ft;
+          }
+        }
+        if constexpr (R::HV) {
+          // the branch's 4x4 block on (theta_f, theta_t, v_f, v_t) times d:
+          // theta rows +-(a da + beta_f d_vf - beta_t d_vt), v rows below
+          const double da = dir[f] - dir[t], dvf = dir[nb + f], dvt = dir[nb + t];
+          const double h_a = fma(a, da, fma(beta_f, dvf, -(beta_t * dvt)));
+          if (sf != kNoSlot) {
+            rec[(R::oHV + 0) * BE + sf] = h_a;
+            rec[(R::oHV + 1) * BE + sf] = fma(beta_f, da, fma(vv_ff, dvf, vv_ft * dvt));
+          }
+          if (st != kNoSlot) {
+            rec[(R::oHV + 0) * BE + st] = -h_a;
+            rec[(R::oHV + 1) * BE + st] = fma(-beta_t, da, fma(vv_ft, dvf, vv_tt * dvt));
+          }
+        }
+      }
+    }
+  }
+
+  // slot-map entries of this lane, fetched here so that their latency
+  // overlaps the bus pass and the barrier (not live across the branch pass,
+  // the register peak)
+  if constexpr (SLOTS) {
+    const uint32_t* smg = I.slots + T.sm0;
+#pragma unroll
+    for (int r = 0; r < SPL; ++r) {
+      const int k = threadIdx.x + r * WG;
+      pre[r] = k < nS ? smg[k] : 0u;
     }
   }
 
@@ -334,57 +411,73 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
     if constexpr (U::V) {
       bus[U::oV * NBUS + ib] = 2.0 * vi * fma(mul[i], bd.z, -(mul[nb + i] * bd.w));
     }
+    if constexpr (U::HV) {
+      bus[U::oHV * NBUS + ib] = 2.0 * fma(mul[i], bd.z, -(mul[nb + i] * bd.w)) * dir[nb + i];
+    }
+    if constexpr (U::JV) {
+      double dpg = 0, dqg = 0;
+      for (int g = N.gen_ptr[i], g1 = N.gen_ptr[i + 1]; g < g1; ++g) {
+        const int k = N.gen_list[g];
+        dpg += dir[2 * nb + k];
+        dqg += dir[2 * nb + N.ng + k];
+      }
+      bus[(U::oJV + 0) * NBUS + ib] = 2.0 * bd.z * vi * dir[nb + i] - dpg;
+      bus[(U::oJV + 1) * NBUS + ib] = -2.0 * bd.w * vi * dir[nb + i] - dqg;
+    }
   }
   __syncthreads();
 
-  // ---- phase B: lane per output entry
-  const int2* sm = I.slots + T.sm0;
-  const bool shift = I.out_rm != 0;
-  if (jout) {
-    double* jac = B.jac + I.jo;
-    for (int k = tid; k < T.nP; k += WG) {
-      const int2 ent = sm[k];
-      const int ea = ent.x & 0xFFFF, cnt = ent.x >> 16;
-      const int fld = ent.y & 15, kind = (ent.y >> 5) & 7, bl = ent.y >> 8;
-      double vp = 0.0, vq = 0.0;
-      for (int e = ea; e < ea + cnt; ++e) {
-        vp += rec[(R::oJ + fld) * BE + e];
-        vq += rec[(R::oJ + 3 + fld) * BE + e];
+  // ---- phase B: lane per output entry, from the prefetched slot map
+  if constexpr (SLOTS) {
+    const bool rm = I.out_rm != 0;
+    const SegShift shP(T.jP0, T.nP, I.rj), shQ(T.jQ0, T.nP, I.rj);
+    const SegShift shT(T.hT0, T.nT, I.rh), shV(T.hV0, T.nV, I.rh);
+    double* jac = jout ? B.jac + I.jo : nullptr;
+    double* hess = hout ? B.hess + I.ho : nullptr;
+#pragma unroll
+    for (int r = 0; r < SPL; ++r) {
+      const int k = tid + r * WG;
+      if (k >= nS) continue;
+      const uint32_t ent = pre[r];
+      const int ea = ent & 511u, cnt = (ent >> 9) & 1023u, fld = (ent >> 19) & 3u;
+      const bool neg = (ent >> 21) & 1u;
+      const int kind = (ent >> 22) & 3u, bl = ent >> 24;
+      if (k < T.nP) {
+        if (!jout) continue;
+        double vp = 0.0, vq = 0.0;
+        for (int e = ea; e < ea + cnt; ++e) {
+          vp += rec[(R::oJ + fld) * BE + e];
+          vq += rec[(R::oJ + 3 + fld) * BE + e];
+        }
+        if (neg) {
+          vp = -vp;
+          vq = -vq;
+        }
+        if (kind == SK_JDIAG_V) {
+          vp += bus[(U::oJ + 0) * NBUS + bl];
+          vq += bus[(U::oJ + 1) * NBUS + bl];
+        } else if (kind == SK_GEN) {
+          vp = -1.0;
+          vq = -1.0;
+        }
+        const int gp = rm ? place(T.jP0 + k, shP, I.rj) : T.jP0 + k;
+        const int gq = rm ? place(T.jQ0 + k, shQ, I.rj) : T.jQ0 + k;
+        if (gp >= 0) jac[gp] = vp;
+        if (gq >= 0) jac[gq] = vq;
+      } else {
+        if (!hout) continue;
+        double v = 0.0;
+        for (int e = ea; e < ea + cnt; ++e) v += rec[(R::oH + fld) * BE + e];
+        if (neg) v = -v;
+        if (kind == SK_HDIAG_V) v += bus[U::oH * NBUS + bl];
+        const bool th = k < T.nP + T.nT;
+        const int base = th ? T.hT0 + (k - T.nP) : T.hV0 + (k - T.nP - T.nT);
+        const int gp = rm ? place(base, th ? shT : shV, I.rh) : base;
+        if (gp >= 0) hess[gp] = v;
       }
-      if (ent.y & 16) {
-        vp = -vp;
-        vq = -vq;
-      }
-      if (kind == SK_JDIAG_V) {
-        vp += bus[(U::oJ + 0) * NBUS + bl];
-        vq += bus[(U::oJ + 1) * NBUS + bl];
-      } else if (kind == SK_GEN) {
-        vp = -1.0;
-        vq = -1.0;
-      }
-      const int gp = shift ? shifted(T.jP0 + k, I.rj) : T.jP0 + k;
-      const int gq = shift ? shifted(T.jQ0 + k, I.rj) : T.jQ0 + k;
-      if (gp >= 0) jac[gp] = vp;
-      if (gq >= 0) jac[gq] = vq;
     }
   }
-  if (hout) {
-    double* hess = B.hess + I.ho;
-    const int2* smT = sm + T.nP;
-    for (int k = tid; k < T.nT + T.nV; k += WG) {
-      const int2 ent = smT[k];
-      const int ea = ent.x & 0xFFFF, cnt = ent.x >> 16;
-      const int fld = ent.y & 15, kind = (ent.y >> 5) & 7, bl = ent.y >> 8;
-      double v = 0.0;
-      for (int e = ea; e < ea + cnt; ++e) v += rec[(R::oH + fld) * BE + e];
-      if (ent.y & 16) v = -v;
-      if (kind == SK_HDIAG_V) v += bus[U::oH * NBUS + bl];
-      const int base = k < T.nT ? T.hT0 + k : T.hV0 + (k - T.nT);
-      const int gp = shift ? shifted(base, I.rh) : base;
-      if (gp >= 0) hess[gp] = v;
-    }
-  }
-  if constexpr (R::C || R::V || DO_GF) {
+  if constexpr (R::C || R::V || R::HV || R::JV || DO_GF) {
     double* gradf = (DO_GF && B.gradf) ? B.gradf + I.xo : nullptr;
     for (int ib = tid; ib < nbus; ib += WG) {
       const int i = b0 + ib;
@@ -414,13 +507,33 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
         u[i] = ut;
         u[nb + i] = uv + bus[U::oV * NBUS + ib];
       }
+      if constexpr (R::HV) {
+        double ht = 0.0, hv = 0.0;
+        for (int e = be.x; e < be.x + be.y; ++e) {
+          ht += rec[(R::oHV + 0) * BE + e];
+          hv += rec[(R::oHV + 1) * BE + e];
+        }
+        double* o = B.out + I.xo;
+        o[i] = ht;
+        o[nb + i] = hv + bus[U::oHV * NBUS + ib];
+      }
+      if constexpr (R::JV) {
+        double jp = 0.0, jq = 0.0;
+        for (int e = be.x; e < be.x + be.y; ++e) {
+          jp += rec[(R::oJV + 0) * BE + e];
+          jq += rec[(R::oJV + 1) * BE + e];
+        }
+        double* o = B.out + I.co;
+        o[i] = jp + bus[(U::oJV + 0) * NBUS + ib];
+        o[nb + i] = jq + bus[(U::oJV + 1) * NBUS + ib];
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // gen tile: objective, its gradient, the Pg diagonal of H, the Pg/Qg part of
-// the VJP
+// the VJP, and this chunk's fixed-tree partial sum of the cost
 
 template <unsigned WHAT, int WG>
 __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k0, int k1,
@@ -429,6 +542,7 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
   constexpr bool DO_GF = (WHAT & W_GRADF) != 0;
   constexpr bool DO_H = (WHAT & W_H) != 0;
   constexpr bool DO_V = (WHAT & W_VJP) != 0;
+  constexpr bool DO_HV = (WHAT & W_HVP) != 0;
   const int tid = threadIdx.x;
   const int nb = N.nb, ng = N.ng;
   const double Bm = N.base_mva;
@@ -458,6 +572,11 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
         B.u[I.xo + 2 * nb + k] = fma(wf, grad, -w[bus]);
         B.u[I.xo + 2 * nb + ng + k] = -w[nb + bus];
       }
+      if constexpr (DO_HV) {
+        double* o = B.out + I.xo;
+        o[2 * nb + k] = sigma * (2.0 * c2 * Bm * Bm) * B.dir[I.xo + 2 * nb + k];
+        o[2 * nb + ng + k] = 0.0;
+      }
       if (fout) term = fma(fma(c2, p, c1), p, N.gen_c0[k]);
     }
     if (fout) smem[t] = term;
@@ -469,26 +588,27 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
     for (int t = tid; t < s; t += WG) smem[t] = smem[t] + smem[t + s];
     __syncthreads();
   }
-  if (tid == 0) {
-    double* fpart = B.fpart + I.fpo;
-    __hip_atomic_store(&fpart[chunk], smem[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const uint32_t prev =
-        __hip_atomic_fetch_add(&B.ticket[I.k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == static_cast<uint32_t>(N.nchunks - 1)) {
-      __threadfence();
-      double f = 0.0;
-      for (int ch = 0; ch < N.nchunks; ++ch)
-        f += __hip_atomic_load(&fpart[ch], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      B.f[I.k] = f;
-      __hip_atomic_store(&B.ticket[I.k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  if (tid == 0) B.fpart[I.fpo + chunk] = smem[0];
+}
+
+// f of each instance: its chunk partials added in chunk order.  A kernel of
+// its own, enqueued after the evaluation on the same stream, so the
+// partials are visible without fences.
+__global__ __launch_bounds__(256) void k_fsum(const InstOff* __restrict__ table, InstOff one,
+                                              int first, int count, const double* __restrict__ fpart,
+                                              double* __restrict__ f) {
+  const int k = first + static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (k >= first + count) return;
+  const InstOff I = table ? table[k] : one;
+  const int nch = I.net->nchunks;
+  double s = 0.0;
+  for (int ch = 0; ch < nch; ++ch) s += fpart[I.fpo + ch];
+  f[I.k] = s;
 }
 
 // ---------------------------------------------------------------------------
 
-template <unsigned WHAT, int WG, int BE, int NBUS>
+template <unsigned WHAT, int WG, int BE, int NBUS, int SPL>
 __global__ __launch_bounds__(WG) void k_eval(Bufs B, const InstOff* __restrict__ table,
                                              InstOff one, const Tile* __restrict__ tiles,
                                              int ntiles) {
@@ -498,9 +618,9 @@ __global__ __launch_bounds__(WG) void k_eval(Bufs B, const InstOff* __restrict__
     const InstOff I = table ? table[T.inst] : one;
     const NetDev& N = *I.net;
     if ((T.kind_aux & 3) == TILE_BUS) {
-      bus_tile<WHAT, WG, BE, NBUS>(B, I, N, T, smem);
+      bus_tile<WHAT, WG, BE, NBUS, SPL>(B, I, N, T, smem);
     } else {
-      if constexpr ((WHAT & (W_F | W_GRADF | W_H | W_VJP)) != 0)
+      if constexpr ((WHAT & (W_F | W_GRADF | W_H | W_VJP | W_HVP)) != 0)
         gen_tile<WHAT, WG>(B, I, N, T.a0, T.a1, T.kind_aux >> 2, smem);
     }
     __syncthreads();
@@ -515,7 +635,7 @@ hipError_t launch_caps(int tile_be, const Bufs& b, const InstOff* table, const I
   switch (tile_be) {
 #define ACOPF_CASE(C)                                                                      \
   case C.be:                                                                               \
-    k_eval<WHAT, C.wg, C.be, C.nbus><<<blocks, C.wg, 0, s>>>(b, table, one, tiles, ntiles); \
+    k_eval<WHAT, C.wg, C.be, C.nbus, C.spl><<<blocks, C.wg, 0, s>>>(b, table, one, tiles, ntiles); \
     break;
     ACOPF_CASE(kCaps64)
     ACOPF_CASE(kCaps128)
@@ -530,6 +650,13 @@ hipError_t launch_caps(int tile_be, const Bufs& b, const InstOff* table, const I
 
 }  // namespace
 
+hipError_t launch_fsum(const InstOff* table, const InstOff& one, int first, int count,
+                       const double* fpart, double* f, hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  k_fsum<<<(count + 255) / 256, 256, 0, stream>>>(table, one, first, count, fpart, f);
+  return hipGetLastError();
+}
+
 hipError_t launch_eval(unsigned kvariant, int tile_be, const Bufs& b, const InstOff* table,
                        const InstOff& one, const Tile* tiles, int ntiles, int grid,
                        hipStream_t stream) {
@@ -539,6 +666,8 @@ hipError_t launch_eval(unsigned kvariant, int tile_be, const Bufs& b, const Inst
     case K_H: return launch_caps<K_H>(tile_be, b, table, one, tiles, ntiles, grid, stream);
     case K_ALL: return launch_caps<K_ALL>(tile_be, b, table, one, tiles, ntiles, grid, stream);
     case K_VJP: return launch_caps<K_VJP>(tile_be, b, table, one, tiles, ntiles, grid, stream);
+    case K_HVP: return launch_caps<K_HVP>(tile_be, b, table, one, tiles, ntiles, grid, stream);
+    case K_JVP: return launch_caps<K_JVP>(tile_be, b, table, one, tiles, ntiles, grid, stream);
     default: return hipErrorInvalidValue;
   }
 }

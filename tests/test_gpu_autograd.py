@@ -75,3 +75,50 @@ def test_batched_directional_fd(gpu_lib):
         scale = float((u[xs].abs() * v[xs].abs()).sum())
         log(f"[batched fd] inst {k} nb={nets[k].dims.nbus} fd={fd:.6e} an={an:.6e}")
         assert abs(fd - an) <= 1e-6 * scale
+
+
+def test_hvp_and_jvp_match_oracle(gpu_lib):
+    """H d (full symmetric H) and J d against the oracle's matrices, on a
+    grid with shunts, parallel branches and phase shifters, and on an N-1
+    child."""
+    import torch
+    from paper_2203_10587_amd import acopf as A
+    from tests.parity import assert_close
+    g = S.random_grid(60, 95, 20, seed=5, parallel=3)
+    base = A.acopf_net_create(g)
+    for net, grid in ((base, g), (A.acopf_net_create_outage(base, 7), S.remove_branch(g, 7))):
+        it = S.draw_iterate(grid, np.random.default_rng(3), sigma=0.7)
+        d = np.random.default_rng(4).standard_normal(grid.n)
+        T = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64), device="cuda")
+        hv = torch.empty(net.n, dtype=torch.float64, device="cuda")
+        jv = torch.empty(net.m, dtype=torch.float64, device="cuda")
+        A.acopf_hvp(net, T(it.x), it.sigma, T(it.lam), T(d), hv)
+        A.acopf_jvp(net, T(it.x), T(d), jv)
+        mdl = O.prepare(grid)
+        H = O.hessian_matrix(mdl, it.x, it.sigma, it.lam)
+        J = O.jacobian_matrix(mdl, it.x)
+        out = O.evaluate(mdl, it.x, it.sigma, it.lam)
+        sj = O.jacobian_row_scales(mdl, it.x, out["jac_val"])
+        rows = np.repeat(np.arange(mdl.m), np.diff(mdl.jac_rowptr))
+        jscale = np.bincount(rows, weights=sj * np.abs(d[mdl.jac_col]), minlength=mdl.m)
+        assert_close("jvp", jv.cpu().numpy(), J @ d, jscale)
+        # each H entry sums per-branch terms that may cancel: bound the
+        # rounding by the row's largest entry times the sum of |d| it touches
+        Habs = abs(H).tocsr()
+        rowmax = Habs.max(axis=1).toarray().ravel()
+        hscale = rowmax * ((Habs > 0).astype(float) @ np.abs(d))
+        assert_close("hvp", hv.cpu().numpy(), H @ d, hscale)
+
+
+def test_double_backward(gpu_lib):
+    """gradgradcheck: the VJP's own derivatives (HVP, JVP) against finite
+    differences of the VJP."""
+    import torch
+    from paper_2203_10587_amd import acopf as A
+    from paper_2203_10587_amd.autograd import AcopfEval
+    g = S.random_grid(12, 18, 4, seed=2, parallel=1)
+    it = S.draw_iterate(g, np.random.default_rng(1))
+    net = A.acopf_net_create(g)
+    x = torch.as_tensor(it.x, device="cuda").requires_grad_(True)
+    assert torch.autograd.gradgradcheck(lambda z: AcopfEval.apply(z, net), (x,), eps=1e-6,
+                                        atol=1e-5, rtol=1e-4)
