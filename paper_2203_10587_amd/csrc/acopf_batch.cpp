@@ -193,10 +193,9 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     struct PerBase {
       Schedule sch;
       size_t work_off = 0;   // into the batch's work array
-      size_t slot_off = 0;   // into the batch's slot array
     };
     std::map<const Base*, PerBase> per_base;
-    size_t work_total = 0, slot_total = 0;
+    size_t work_total = 0;
     for (int k = 0; k < count; ++k) {
       const Base* B = nets[k]->base.get();
       if (per_base.count(B)) continue;
@@ -207,9 +206,7 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
         return rc;
       }
       pb.work_off = work_total;
-      pb.slot_off = slot_total;
       work_total += pb.sch.work.size();
-      slot_total += pb.sch.slots.size();
       per_base.emplace(B, std::move(pb));
     }
     // XCD queues, largest instances first (LPT on tile counts)
@@ -260,9 +257,8 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     const size_t s_tiles = align_up(tiles.size() * sizeof(Tile));
     const size_t s_tinst = align_up(tiles_inst.size() * sizeof(Tile));
     const size_t s_work = align_up(std::max<size_t>(work_total, 1) * sizeof(WorkItem));
-    const size_t s_slot = align_up(std::max<size_t>(slot_total, 1) * sizeof(uint32_t));
     const size_t s_fpart = align_up(size_t(fpo[count]) * sizeof(double));
-    e = hipMalloc(&b->mem, s_table + s_tiles + s_work + s_slot + s_fpart + s_tinst);
+    e = hipMalloc(&b->mem, s_table + s_tiles + s_work + s_fpart + s_tinst);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       b->mem = nullptr;
@@ -273,14 +269,12 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     b->d_table = reinterpret_cast<InstOff*>(base);
     b->d_tiles = reinterpret_cast<Tile*>(base + s_table);
     WorkItem* d_work = reinterpret_cast<WorkItem*>(base + s_table + s_tiles);
-    uint32_t* d_slot = reinterpret_cast<uint32_t*>(base + s_table + s_tiles + s_work);
-    b->d_fpart = reinterpret_cast<double*>(base + s_table + s_tiles + s_work + s_slot);
-    b->d_tiles_inst = reinterpret_cast<Tile*>(base + s_table + s_tiles + s_work + s_slot + s_fpart);
+    b->d_fpart = reinterpret_cast<double*>(base + s_table + s_tiles + s_work);
+    b->d_tiles_inst = reinterpret_cast<Tile*>(base + s_table + s_tiles + s_work + s_fpart);
     std::vector<InstOff> table(count);
     for (int k = 0; k < count; ++k) {
       InstOff I = net_inst(nets[k]);
       I.work = d_work + per_base[nets[k]->base.get()].work_off;
-      I.slots = d_slot + per_base[nets[k]->base.get()].slot_off;
       I.xo = b->xo[k];
       I.co = b->co[k];
       I.jo = b->jo[k];
@@ -297,9 +291,6 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
       if (e == hipSuccess && !sc.work.empty())
         e = hipMemcpy(d_work + kv.second.work_off, sc.work.data(), sc.work.size() * sizeof(WorkItem),
                       hipMemcpyHostToDevice);
-      if (e == hipSuccess && !sc.slots.empty())
-        e = hipMemcpy(d_slot + kv.second.slot_off, sc.slots.data(),
-                      sc.slots.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess)
       e = hipMemcpy(b->d_tiles_inst, tiles_inst.data(), tiles_inst.size() * sizeof(Tile),

@@ -268,11 +268,19 @@ void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,
   for (int k = 0; k < ng; ++k) hp->push_back(int32_t(hc->size()));
 }
 
-// Slot-map entry: signed sum of record `field` over branch ends [ea, ea+cnt);
-// the caps keep ea < 512, cnt <= 512 and bl < 256 (checked when the tile closes).
-static uint32_t slot(int ea, int cnt, int field, int neg, int kind, int bl) {
-  return uint32_t(ea) | (uint32_t(cnt) << 9) | (uint32_t(field) << 19) | (uint32_t(neg) << 21) |
-         (uint32_t(kind) << 22) | (uint32_t(bl) << 24);
+// Position of bus j in the ascending set {i} u N(i).
+static int rank_in(const Topology& T, int i, int j) {
+  int r = (i < j) ? 1 : 0, prev = -1;
+  for (int e = T.be_ptr[i]; e < T.be_ptr[i + 1]; ++e) {
+    const int code = T.be[e];
+    const int2 ft = T.ft[code >> 1];
+    const int o = (code & 1) ? ft.x : ft.y;
+    if (o != prev) {
+      if (o < j) ++r;
+      prev = o;
+    }
+  }
+  return r;
 }
 
 int make_tiles(const Topology& T, int tile_be, Schedule* S) {
@@ -280,28 +288,40 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
   if (!caps_for(tile_be, &caps)) return fail(ACOPF_EINVAL, "unsupported tile size");
   S->tiles.clear();
   S->work.clear();
-  S->slots.clear();
   // adjacency position of each branch end
   std::vector<int32_t> pos_from(T.nl), pos_to(T.nl);
   for (int e = 0; e < int(T.be.size()); ++e) {
     const int code = T.be[e];
     ((code & 1) ? pos_to : pos_from)[code >> 1] = e;
   }
-  auto far = [&](int e) {
-    const int code = T.be[e];
-    const int2 ft = T.ft[code >> 1];
-    return (code & 1) ? ft.x : ft.y;
-  };
+  // parallel-branch groups: every branch points at the smallest branch id
+  // joining the same bus pair
+  std::vector<int32_t> lead(T.nl);
+  for (int i = 0; i < T.nb; ++i) {
+    int prev = -1, first = -1;
+    for (int e = T.be_ptr[i]; e < T.be_ptr[i + 1]; ++e) {
+      const int code = T.be[e], l = code >> 1;
+      const int2 ft = T.ft[l];
+      const int o = (code & 1) ? ft.x : ft.y;
+      if (o != prev) {
+        prev = o;
+        first = l;  // ends of one far bus are sorted by branch id
+      }
+      lead[l] = first;
+    }
+  }
+  std::vector<int32_t> gsize(T.nl, 0);
+  for (int l = 0; l < T.nl; ++l) gsize[lead[l]]++;
+  for (int l = 0; l < T.nl; ++l)
+    if (gsize[lead[l]] > kMaxGroup)
+      return fail(ACOPF_EINVAL, "more than " + std::to_string(kMaxGroup) +
+                                    " parallel branches join one bus pair");
   std::vector<int32_t> seen(T.nl, -1);
   std::vector<int32_t> items;
-  struct Grp {
-    int j, ea, cnt;
-  };
-  std::vector<Grp> grp;
-  std::vector<uint32_t> sT, sV;
   bool tiler_error = false;
   auto close = [&](int b0, int b1) {
     const int e0 = T.be_ptr[b0], e1 = T.be_ptr[b1];
+    const int4 r0 = T.rows[b0], r1 = T.rows[b1];
     items.clear();
     for (int e = e0; e < e1; ++e) {
       const int l = T.be[e] >> 1;
@@ -310,67 +330,71 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
         items.push_back(l);
       }
     }
-    std::sort(items.begin(), items.end());
+    // groups together, in branch order, leaders first
+    std::sort(items.begin(), items.end(), [&](int a, int b) {
+      return lead[a] != lead[b] ? lead[a] < lead[b] : a < b;
+    });
     const int w0 = int(S->work.size());
-    for (int l : items) {
-      const int f = T.ft[l].x, t = T.ft[l].y;
-      const uint32_t sf = (f >= b0 && f < b1) ? uint32_t(pos_from[l] - e0) : kNoSlot;
-      const uint32_t st = (t >= b0 && t < b1) ? uint32_t(pos_to[l] - e0) : kNoSlot;
-      S->work.push_back({l, f, t, sf | (st << 16)});
-    }
-    // slot map: J P rows (shared by the Q rows), then H theta rows, then H v rows
-    const int sm0 = int(S->slots.size());
-    sT.clear();
-    sV.clear();
-    for (int i = b0; i < b1; ++i) {
-      const int bl = i - b0;
-      const int ea = T.be_ptr[i] - e0, deg = T.be_ptr[i + 1] - T.be_ptr[i];
-      grp.clear();
-      for (int e = T.be_ptr[i]; e < T.be_ptr[i + 1]; ++e) {
-        const int j = far(e);
-        if (grp.empty() || grp.back().j != j) grp.push_back({j, e - e0, 0});
-        grp.back().cnt++;
-      }
-      // members of {i} u N(i) ascending; the diagonal sits before the first j > i
-      std::vector<Grp> mem;
-      bool self = false;
-      for (const Grp& g : grp) {
-        if (!self && g.j > i) {
-          mem.push_back({i, ea, deg});
-          self = true;
+    int gmax = 1;
+    auto in_tile = [&](int bus) { return bus >= b0 && bus < b1; };
+    for (size_t k = 0; k < items.size();) {
+      size_t k1 = k + 1;
+      while (k1 < items.size() && lead[items[k1]] == lead[items[k]]) ++k1;
+      const int g = int(k1 - k);
+      gmax = std::max(gmax, g);
+      // no group straddles two waves
+      const int at = int(S->work.size()) - w0;
+      if (g > 1 && at / 64 != (at + g - 1) / 64) {
+        const int pad = 64 - at % 64;
+        for (int q = 0; q < pad; ++q) {
+          WorkItem d{};
+          d.l = -2;
+          d.jlo = d.hvlo = d.jhi = d.hvhi = d.hthi = -1;
+          d.slots = kNoSlot | (kNoSlot << 16);
+          S->work.push_back(d);
         }
-        mem.push_back(g);
       }
-      if (!self) mem.push_back({i, ea, deg});
-      for (const Grp& g : mem)  // theta columns
-        S->slots.push_back(g.j == i ? slot(g.ea, g.cnt, 0, 0, SK_SUM, bl)
-                                    : slot(g.ea, g.cnt, 0, 1, SK_SUM, bl));
-      for (const Grp& g : mem)  // v columns
-        S->slots.push_back(g.j == i ? slot(g.ea, g.cnt, 1, 0, SK_JDIAG_V, bl)
-                                    : slot(g.ea, g.cnt, 2, 0, SK_SUM, bl));
-      for (int g = T.gen_ptr[i]; g < T.gen_ptr[i + 1]; ++g)
-        S->slots.push_back(slot(0, 0, 0, 0, SK_GEN, bl));
-      for (const Grp& g : mem)  // H theta row: j <= i
-        if (g.j <= i) sT.push_back(g.j == i ? slot(g.ea, g.cnt, 0, 0, SK_SUM, bl)
-                                            : slot(g.ea, g.cnt, 0, 1, SK_SUM, bl));
-      for (const Grp& g : mem)  // H v row: theta_j for all j
-        sV.push_back(g.j == i ? slot(g.ea, g.cnt, 1, 0, SK_SUM, bl)
-                              : slot(g.ea, g.cnt, 1, 1, SK_SUM, bl));
-      for (const Grp& g : mem)  // H v row: v_j for j <= i
-        if (g.j <= i) sV.push_back(g.j == i ? slot(g.ea, g.cnt, 2, 0, SK_HDIAG_V, bl)
-                                            : slot(g.ea, g.cnt, 3, 0, SK_SUM, bl));
+      for (size_t m = k; m < k1; ++m) {
+        const int l = items[m];
+        const int f = T.ft[l].x, t = T.ft[l].y;
+        const int lo = std::min(f, t), hi = std::max(f, t);
+        WorkItem w{};
+        w.l = l;
+        w.f = f;
+        w.t = t;
+        const uint32_t sf = in_tile(f) ? uint32_t(pos_from[l] - e0) : kNoSlot;
+        const uint32_t st = in_tile(t) ? uint32_t(pos_to[l] - e0) : kNoSlot;
+        w.slots = sf | (st << 16);
+        w.grp = (m == k) ? g : 0;
+        w.jlo = w.hvlo = w.jhi = w.hvhi = w.hthi = -1;
+        w.alo = T.acnt[lo].x;
+        w.ahi = T.acnt[hi].x;
+        if (in_tile(lo)) {
+          const int r = rank_in(T, lo, hi);
+          w.jlo = T.rows[lo].x + r;
+          w.hvlo = T.rows[lo].w + r;
+        }
+        if (in_tile(hi)) {
+          const int r = rank_in(T, hi, lo);
+          w.jhi = T.rows[hi].x + r;
+          w.hvhi = T.rows[hi].w + r;
+          w.hthi = T.rows[hi].z + r;
+        }
+        S->work.push_back(w);
+      }
+      k = k1;
     }
-    const int nP = int(S->slots.size()) - sm0;
-    S->slots.insert(S->slots.end(), sT.begin(), sT.end());
-    S->slots.insert(S->slots.end(), sV.begin(), sV.end());
-    const int4 r0 = T.rows[b0], r1 = T.rows[b1];
-    // the slot map must cover exactly the tile's row segments, and every
-    // record range must lie inside the tile
-    bool ok = nP == r1.x - r0.x && int(sT.size()) == r1.z - r0.z && int(sV.size()) == r1.w - r0.w;
-    ok = ok && e1 - e0 <= 512 && b1 - b0 <= 256 && int(S->slots.size()) - sm0 <= caps.spl * caps.wg;
-    for (size_t k = sm0; ok && k < S->slots.size(); ++k) {
-      const uint32_t en = S->slots[k];
-      ok = int(en & 511u) + int((en >> 9) & 1023u) <= e1 - e0 && int(en >> 24) < b1 - b0;
+    // every stored position must lie in the tile's row segments
+    bool ok = e1 - e0 <= caps.be && b1 - b0 <= caps.nbus &&
+              2 * (r1.x - r0.x) + (r1.z - r0.z) + (r1.w - r0.w) <= caps.stage;
+    for (size_t k = w0; ok && k < S->work.size(); ++k) {
+      const WorkItem& w = S->work[k];
+      if (w.l < 0) continue;
+      if (w.jlo >= 0)
+        ok = ok && w.jlo >= r0.x && w.jlo + w.alo < r1.x && w.hvlo >= r0.w && w.hvlo < r1.w;
+      if (w.jhi >= 0)
+        ok = ok && w.jhi >= r0.x && w.jhi + w.ahi < r1.x && w.hvhi >= r0.w &&
+             w.hvhi + w.ahi < r1.w && w.hthi >= r0.z && w.hthi < r1.z;
     }
     if (!ok) {
       tiler_error = true;
@@ -385,38 +409,39 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
     tl.ne = e1 - e0;
     tl.w0 = w0;
     tl.nw = int(S->work.size()) - w0;
-    tl.sm0 = sm0;
-    tl.nP = nP;
-    tl.nT = int(sT.size());
-    tl.nV = int(sV.size());
+    tl.gmax = gmax;
+    tl.nP = r1.x - r0.x;
+    tl.nT = r1.z - r0.z;
+    tl.nV = r1.w - r0.w;
     tl.jP0 = r0.x;
     tl.jQ0 = r0.y;
     tl.hT0 = r0.z;
     tl.hV0 = r0.w;
     S->tiles.push_back(tl);
   };
-  const int slotcap = caps.spl * caps.wg;
-  int b0 = 0, cur_be = 0, cur_sl = 0;
+  int b0 = 0, cur_be = 0, cur_st = 0;
   for (int i = 0; i < T.nb; ++i) {
     const int d = T.be_ptr[i + 1] - T.be_ptr[i];
+    // staged entries of the bus: J P and Q rows, H theta row, H v row
     const int a = T.acnt[i].x, lo = T.acnt[i].y, g = T.gen_ptr[i + 1] - T.gen_ptr[i];
-    const int sl = (2 * a + g) + (lo + 1) + (a + lo + 1);  // J P row, H theta row, H v row
-    if (d > caps.be || sl > slotcap)
+    const int st = 2 * (2 * a + g) + (lo + 1) + (a + lo + 1);
+    if (d > caps.be || st > caps.stage)
       return fail(ACOPF_EINVAL, "bus " + std::to_string(i) + " has " + std::to_string(d) +
-                                    " branch ends and " + std::to_string(sl) +
+                                    " branch ends and " + std::to_string(st) +
                                     " row entries; a bus tile of this schedule holds at most " +
-                                    std::to_string(caps.be) + " and " + std::to_string(slotcap));
-    if (i > b0 && (cur_be + d > caps.be || cur_sl + sl > slotcap || i - b0 >= caps.nbus)) {
+                                    std::to_string(caps.be) + " and " +
+                                    std::to_string(caps.stage));
+    if (i > b0 && (cur_be + d > caps.be || cur_st + st > caps.stage || i - b0 >= caps.nbus)) {
       close(b0, i);
       b0 = i;
       cur_be = 0;
-      cur_sl = 0;
+      cur_st = 0;
     }
     cur_be += d;
-    cur_sl += sl;
+    cur_st += st;
   }
   close(b0, T.nb);
-  if (tiler_error) return fail(ACOPF_EINVAL, "internal: slot map does not match the pattern");
+  if (tiler_error) return fail(ACOPF_EINVAL, "internal: work item positions outside the tile");
   S->counts[0] = int(S->tiles.size());
   for (int c = 0; c < T.nchunks; ++c) {
     Tile tl{};
@@ -436,20 +461,7 @@ void removed_slots(const Topology& T, int32_t p, int32_t q, int32_t rm, int32_t 
   for (int k = 0; k < 8; ++k) rj[k] = INT_MAX;
   for (int k = 0; k < 4; ++k) rh[k] = INT_MAX;
   if (!rm) return;
-  auto rank = [&](int i, int j) {  // position of j in the ascending set {i} u N(i)
-    int r = (i < j) ? 1 : 0, prev = -1;
-    for (int e = T.be_ptr[i]; e < T.be_ptr[i + 1]; ++e) {
-      const int code = T.be[e];
-      const int2 ft = T.ft[code >> 1];
-      const int o = (code & 1) ? ft.x : ft.y;
-      if (o != prev) {
-        if (o < j) ++r;
-        prev = o;
-      }
-    }
-    return r;
-  };
-  const int rpq = rank(p, q), rqp = rank(q, p);
+  const int rpq = rank_in(T, p, q), rqp = rank_in(T, q, p);
   const int ap = T.acnt[p].x, aq = T.acnt[q].x;
   const int4 Rp = T.rows[p], Rq = T.rows[q];
   int32_t j[8] = {Rp.x + rpq, Rp.x + ap + rpq, Rq.x + rqp, Rq.x + aq + rqp,
@@ -497,7 +509,8 @@ int upload_base(Base* B) {
       {T.c0.data(), T.c0.size() * sizeof(double), 0},
       {B->plain.tiles.data(), B->plain.tiles.size() * sizeof(Tile), 0},
       {B->plain.work.data(), B->plain.work.size() * sizeof(WorkItem), 0},
-      {B->plain.slots.data(), B->plain.slots.size() * sizeof(uint32_t), 0},
+      {T.rows.data(), T.rows.size() * sizeof(int4), 0},
+      {T.acnt.data(), T.acnt.size() * sizeof(int2), 0},
       {nullptr, sizeof(NetDev), 0},
   };
   size_t total = 0;
@@ -532,14 +545,16 @@ int upload_base(Base* B) {
   nd.gen_c2 = static_cast<const double*>(at(6));
   nd.gen_c1 = static_cast<const double*>(at(7));
   nd.gen_c0 = static_cast<const double*>(at(8));
+  nd.rows = static_cast<const int4*>(at(11));
+  nd.acnt = static_cast<const int2*>(at(12));
   nd.base_mva = T.base;
   nd.jflow = T.jflow;
   nd.hpg = T.hpg;
+  nd.qoff = T.rows[0].y - T.rows[0].x;
   B->d_tiles = static_cast<Tile*>(at(9));
   B->d_work = static_cast<WorkItem*>(at(10));
-  B->d_slots = static_cast<uint32_t*>(at(11));
-  B->d_net = static_cast<NetDev*>(at(12));
-  parts[12].src = &nd;
+  B->d_net = static_cast<NetDev*>(at(13));
+  parts[13].src = &nd;
   for (const Part& p : parts) {
     if (p.bytes == 0) continue;
     e = hipMemcpy(base + p.off, p.src, p.bytes, hipMemcpyHostToDevice);
@@ -715,7 +730,6 @@ InstOff net_inst(const acopf_net_s* net) {
   InstOff I{};
   I.net = net->base->d_net;
   I.work = net->base->d_work;
-  I.slots = net->base->d_slots;
   I.out_l = net->out_l;
   I.out_rm = net->out_rm;
   for (int k = 0; k < 8; ++k) I.rj[k] = net->rj[k];

@@ -28,11 +28,10 @@ struct Topology {
   int32_t jflow = 0, hpg = 0;
 };
 
-// Tiles, work items and slot map of one schedule (tile size) for a network.
+// Tiles and work items of one schedule (tile size) for a network.
 struct Schedule {
   std::vector<Tile> tiles;        // [bus tiles][gen tiles]
   std::vector<WorkItem> work;
-  std::vector<uint32_t> slots;
   int counts[2] = {0, 0};
 };
 
@@ -45,7 +44,6 @@ struct Base {
   NetDev* d_net = nullptr;
   Tile* d_tiles = nullptr;           // plain-path schedule on the device
   WorkItem* d_work = nullptr;
-  uint32_t* d_slots = nullptr;
   Schedule plain;
   ~Base();
 };

@@ -6,15 +6,17 @@
 // Work is cut into tiles of two kinds:
 //   bus tile  a contiguous range of buses.  A host-built work list names
 //             every branch touching the tile (branch, endpoints, LDS slots of
-//             its ends); each is evaluated once into per-branch-end LDS
-//             records.  A host-built slot map then describes every output
-//             entry of the tile's CSR row segments as a signed sum of a
-//             contiguous range of records (branch ends are sorted by bus and
-//             far bus, so a diagonal entry sums a bus's ends and an
-//             off-diagonal entry the ends of one parallel-branch group), so
-//             one lane computes and stores one output entry.  The tile also
-//             writes the balance rows of c, and the flow-limit rows of the
-//             branches whose from-bus it owns.
+//             its ends, and the base positions of the off-diagonal entries
+//             it owns in the tile's rows); each is evaluated once.  The lane
+//             places those off-diagonal entries in an LDS copy of the tile's
+//             J and H row segments (a group of parallel branches sits in
+//             consecutive lanes of one wave and its first lane places the
+//             group's sum) and leaves per-branch-end records in LDS; after a
+//             barrier, a lane per bus sums its ends' records into the bus's
+//             diagonal entries (placed in the same copy) and balance rows;
+//             after another, the workgroup stores the row segments with
+//             consecutive lanes on consecutive entries.  The tile also writes
+//             the flow-limit rows of the branches whose from-bus it owns.
 //   gen tile  a fixed chunk of generators: f, grad f, the Pg diagonal of H
 #pragma once
 
@@ -29,32 +31,36 @@ constexpr uint32_t kNoSlot = 0xFFFFu;
 enum TileKind : int32_t { TILE_BUS = 1, TILE_GEN = 2 };
 
 // A unit of work.  Bus tile: buses [a0, a1), branch ends [e0, e0 + ne) of the
-// adjacency, work items [w0, w0 + nw), slot map [sm0, sm0 + nP + nT + nV) for
-// the J P rows (the J Q rows share it), the H theta rows and the H v rows,
-// whose base starts are jP0, jQ0, hT0, hV0.  Gen tile: generators [a0, a1);
+// adjacency, work items [w0, w0 + nw), the largest parallel-branch group
+// among them (gmax), and the tile's row segments as base positions: J P rows
+// [jP0, jP0 + nP) (Q rows [jQ0, jQ0 + nP)), H theta rows [hT0, hT0 + nT),
+// H v rows [hV0, hV0 + nV).  Gen tile: generators [a0, a1);
 // kind_aux = (chunk << 2) | kind.
 struct Tile {
   int32_t inst, kind_aux, a0, a1, e0, ne, w0, nw;
-  int32_t sm0, nP, nT, nV, jP0, jQ0, hT0, hV0;
+  int32_t gmax, nP, nT, nV, jP0, jQ0, hT0, hV0;
 };
 
-// One branch evaluated by a bus tile: branch id, its from and to bus, and
-// the tile-local branch-end slots of the two ends (kNoSlot if that end's bus
-// is outside the tile), packed as slot_from | slot_to << 16.
+// One branch evaluated by a bus tile.  l < 0 pads the list so that no
+// parallel-branch group straddles two waves.  slots = slot_from |
+// slot_to << 16: the tile-local branch-end records of the two ends
+// (kNoSlot if that end's bus is outside the tile).  With lo < hi the end
+// buses, the base positions this tile stores (-1 where the end's bus is
+// outside the tile), Q rows at +qoff from the P rows:
+//   jlo  J (P_lo, theta_hi); (P_lo, v_hi) at jlo + alo
+//   hvlo H (v_lo, theta_hi)
+//   jhi  J (P_hi, theta_lo); (P_hi, v_lo) at jhi + ahi
+//   hvhi H (v_hi, theta_lo); (v_hi, v_lo) at hvhi + ahi
+//   hthi H (theta_hi, theta_lo)
+// a_e = |{e} u N(e)|, the length of the theta part of bus e's rows.
+// grp: for the first branch of a group of parallel branches, the group size
+// (1 for a branch without a twin); 0 for the other members, which follow in
+// the next lanes.
 struct WorkItem {
   int32_t l, f, t;
   uint32_t slots;
-};
-
-// One output entry, packed in 32 bits: value = (-1)^neg * sum of record
-// field `field` over branch ends [ea, ea + cnt) of the tile, plus the bus
-// extra of `kind` for tile-local bus `bl`:
-//   ea (9 bits) | cnt << 9 (10) | field << 19 (2) | neg << 21 | kind << 22 (2) | bl << 24 (8)
-enum SlotKind : int32_t {
-  SK_SUM = 0,      // plain signed sum
-  SK_JDIAG_V = 1,  // J diagonal d/dv_i: + 2 gs v_i (P row) or - 2 bs v_i (Q row)
-  SK_GEN = 2,      // generator column: the constant -1
-  SK_HDIAG_V = 3,  // H (v_i, v_i): + 2 (lP_i gs - lQ_i bs)
+  int32_t jlo, hvlo, alo, grp;
+  int32_t jhi, hvhi, hthi, ahi;
 };
 
 // Admittances of one branch (pi model, from-side ideal transformer).
@@ -73,9 +79,12 @@ struct NetDev {
   const double* gen_c2;     // [ng]
   const double* gen_c1;
   const double* gen_c0;
+  const int4* rows;         // [nb + 1] base row starts: J P, J Q, H theta, H v
+  const int2* acnt;         // [nb] |{i} u N(i)|, |{j in N(i) : j < i}|
   double base_mva;
   int32_t jflow;            // base start of the flow rows in J
   int32_t hpg;              // base start of the Pg rows in H
+  int32_t qoff;             // J Q row of a bus minus its P row
 };
 
 // One evaluation instance.  Offsets index the packed buffers of Bufs.  An
@@ -86,7 +95,6 @@ struct NetDev {
 struct InstOff {
   const NetDev* net;
   const WorkItem* work;     // work items of the schedule in use
-  const uint32_t* slots;    // slot map of the schedule in use
   int32_t out_l;            // removed branch, -1 for none
   int32_t out_rm;           // 1 if the removal drops the (p, q) slots
   int32_t rj[8];
@@ -122,16 +130,17 @@ enum : unsigned {
 };
 
 // Tile capacities of one schedule: workgroup size, branch ends per bus tile
-// (LDS records), buses per bus tile (LDS bus terms) and slot-map entries per
-// lane (prefetched into registers at the start of the tile).
+// (LDS records), buses per bus tile (one lane each) and entries of the
+// tile's J and H row segments staged in LDS (2 nP + nT + nV).
 struct TileCaps {
-  int32_t wg, be, nbus, spl;
+  int32_t wg, be, nbus, stage;
 };
 
-constexpr TileCaps kCaps64 = {64, 64, 32, 8};
-constexpr TileCaps kCaps128 = {128, 128, 64, 8};
-constexpr TileCaps kCaps256 = {256, 256, 128, 8};
-constexpr TileCaps kCaps512 = {256, 512, 256, 12};
+constexpr TileCaps kCaps64 = {64, 64, 32, 768};
+constexpr TileCaps kCaps128 = {128, 128, 64, 1536};
+constexpr TileCaps kCaps256 = {256, 256, 128, 3072};
+constexpr TileCaps kCaps512 = {256, 512, 256, 6144};
+constexpr int kMaxGroup = 64;  // parallel branches between one bus pair
 constexpr int kDefaultTileBe = 256;
 
 inline bool caps_for(int tile_be, TileCaps* out) {

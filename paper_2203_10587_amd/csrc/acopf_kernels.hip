@@ -8,21 +8,22 @@
 //            Phase A, lane per branch touching the tile (uniform work): one
 //            sincos of theta_f - theta_t, both end flows, their first
 //            derivatives and the second derivatives of the branch's share of
-//            the Lagrangian; per end inside the tile an LDS record (flows,
-//            the six Jacobian terms, the four Hessian terms, or the two VJP
-//            terms).  A branch whose from-bus the tile owns also writes its
-//            flow-limit rows: h = P^2 + Q^2 at both ends and their Jacobian
-//            rows 2 (P dP + Q dQ) on (theta_f, theta_t, v_f, v_t).  Lanes
-//            also stage each bus's own terms (shunts, load, generation).
-//            Phase B, lane per output entry: a host-built slot map gives each
-//            entry of the tile's CSR row segments (J P and Q rows, H theta and
-//            v rows) as a signed sum over a contiguous range of records --
-//            branch ends are sorted by (bus, far bus, branch), so a diagonal
-//            entry sums all of a bus's ends and an off-diagonal entry the ends
-//            of one group of parallel branches -- plus a bus term; consecutive
-//            lanes store consecutive entries.  No atomics: every sum has one
-//            owner and a fixed order, so results are bitwise reproducible
-//            whatever the tiling.
+//            the Lagrangian.  The lane stores the branch's off-diagonal
+//            Jacobian and Hessian entries in the rows of the tile's buses at
+//            host-computed positions (parallel branches share those entries:
+//            a group sits in consecutive lanes of one wave and its first lane
+//            stores the sum, added in lane order), and leaves, per end
+//            inside the tile, that end's share of its own bus's rows and
+//            diagonal entries in an LDS record.  A branch whose from-bus the
+//            tile owns also writes its flow-limit rows: h = P^2 + Q^2 at both
+//            ends and their Jacobian rows 2 (P dP + Q dQ) on (theta_f,
+//            theta_t, v_f, v_t).
+//            Phase B, lane per bus: the records of the bus's ends, summed in
+//            adjacency order (by far bus, then branch), plus the bus's own
+//            terms (shunt, load, generation) give its diagonal entries and
+//            its balance rows.  No atomics: every sum has one owner and a
+//            fixed order, so results are bitwise reproducible whatever the
+//            tiling.
 //  gen tile  a fixed chunk of 256 generators: grad f, the Pg diagonal of H,
 //            the Pg/Qg part of the VJP and a fixed-tree partial sum of the
 //            cost; a second small kernel adds each instance's partials in
@@ -94,7 +95,9 @@ __device__ __forceinline__ void branch_eval(double thf, double tht, double vf, d
   o.Qt = fma(-y.btt, vt * vt, w * o.cQt);
 }
 
-// Record layout of phase A (structure of arrays in LDS, BE entries per field).
+// Record layout of phase A (structure of arrays in LDS, BE entries per
+// field): for each branch end inside the tile, its share of its own bus's
+// balance rows, diagonal Jacobian and Hessian entries and product rows.
 template <unsigned WHAT>
 struct Rec {
   static constexpr bool C = (WHAT & W_C) != 0;
@@ -103,39 +106,24 @@ struct Rec {
   static constexpr bool V = (WHAT & W_VJP) != 0;
   static constexpr bool HV = (WHAT & W_HVP) != 0;
   static constexpr bool JV = (WHAT & W_JVP) != 0;
-  static constexpr int oC = 0;                  // P_e, Q_e
-  static constexpr int oJ = oC + (C ? 2 : 0);   // dP/dth_e, dP/dv_e, dP/dv_o, dQ/... (o = far end)
-  static constexpr int oH = oJ + (J ? 6 : 0);   // d2/dth_e2, d2/dv_e dth_e, d2/dv_e2, d2/dv_e dv_o
-  static constexpr int oV = oH + (H ? 4 : 0);   // u_th_e, u_v_e
-  static constexpr int oHV = oV + (V ? 2 : 0);  // (H d)_th_e, (H d)_v_e
+  static constexpr int oC = 0;                   // P_e, Q_e
+  static constexpr int oJ = oC + (C ? 2 : 0);    // dP_e/dth_e, dP_e/dv_e, dQ_e/dth_e, dQ_e/dv_e
+  static constexpr int oH = oJ + (J ? 4 : 0);    // d2/dth_e2, d2/dv_e dth_e, d2/dv_e2
+  static constexpr int oV = oH + (H ? 3 : 0);    // u_th_e, u_v_e
+  static constexpr int oHV = oV + (V ? 2 : 0);   // (H d)_th_e, (H d)_v_e
   static constexpr int oJV = oHV + (HV ? 2 : 0); // (J d) of P_e, of Q_e
   static constexpr int N = oJV + (JV ? 2 : 0);
 };
 
-// Bus terms staged by phase A (structure of arrays, NBUS entries per field).
-template <unsigned WHAT>
-struct BusRec {
-  static constexpr bool C = (WHAT & W_C) != 0;
-  static constexpr bool J = (WHAT & W_J) != 0;
-  static constexpr bool H = (WHAT & W_H) != 0;
-  static constexpr bool V = (WHAT & W_VJP) != 0;
-  static constexpr bool HV = (WHAT & W_HVP) != 0;
-  static constexpr bool JV = (WHAT & W_JVP) != 0;
-  static constexpr int oJ = 0;                  // 2 gs v, -2 bs v
-  static constexpr int oH = oJ + (J ? 2 : 0);   // 2 (lP gs - lQ bs)
-  static constexpr int oC = oH + (H ? 1 : 0);   // (gs v^2 - Pg) + Pd, (-bs v^2 - Qg) + Qd
-  static constexpr int oV = oC + (C ? 2 : 0);   // 2 v (wP gs - wQ bs)
-  static constexpr int oHV = oV + (V ? 1 : 0);  // 2 (lP gs - lQ bs) d_v
-  static constexpr int oJV = oHV + (HV ? 1 : 0); // 2 gs v d_v - sum d_Pg, -2 bs v d_v - sum d_Qg
-  static constexpr int N = oJV + (JV ? 2 : 0);
-};
-
-template <unsigned WHAT, int BE, int NBUS>
+// LDS of a bus tile, in doubles: the records, then the staged copy of the
+// tile's row segments (J P rows, J Q rows, H theta rows, H v rows, as far as
+// the variant forms them).
+template <unsigned WHAT, int BE, int STAGE>
 struct Lds {
   static constexpr int kRec = Rec<WHAT>::N * BE;
-  static constexpr int kBus = kRec + BusRec<WHAT>::N * NBUS + NBUS;  // + (first end, count) per bus
+  static constexpr int kStage = (Rec<WHAT>::J || Rec<WHAT>::H) ? STAGE : 0;
   static constexpr int kGen = kGenChunk;
-  static constexpr int kMax = kBus > kGen ? kBus : kGen;
+  static constexpr int kMax = kRec + kStage > kGen ? kRec + kStage : kGen;
 };
 
 __device__ __forceinline__ int after_outage(int l, int ol) { return (ol >= 0 && l > ol) ? 1 : 0; }
@@ -143,8 +131,8 @@ __device__ __forceinline__ int after_outage(int l, int ol) { return (ol >= 0 && 
 // ---------------------------------------------------------------------------
 // bus tile
 
-// Position of a base slot in an instance that may have lost slots: -1 if
-// the slot itself was removed, else the base position minus the removed
+// Position of a base entry in an instance that may have lost entries: -1 if
+// the entry itself was removed, else the base position minus the removed
 // positions before it.
 template <int NR>
 __device__ __forceinline__ int shifted(int gp, const int32_t (&r)[NR]) {
@@ -178,14 +166,34 @@ __device__ __forceinline__ int place(int gp, const SegShift& sg, const int32_t (
   return sg.inside ? shifted(gp, r) : gp - sg.below;
 }
 
-template <unsigned WHAT, int WG, int BE, int NBUS, int SPL>
+// Sum over a parallel-branch group, left in its first lane: lanes
+// [lane, lane + g) hold the members' values, added in lane order.  Every
+// lane of the wave takes part (g = 0 or 1 leaves a lane's values as they
+// are); the caller keeps control flow uniform.
+template <int NV>
+__device__ __forceinline__ void group_sum(double (&v)[NV], int g, int gmax) {
+  double acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = v[q];
+  for (int d = 1; d < gmax; ++d) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double o = __shfl_down(v[q], d, 64);
+      if (d < g) acc[q] += o;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = acc[q];
+}
+
+template <unsigned WHAT, int WG, int BE, int NBUS, int STAGE>
 __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const Tile& T,
                          double* smem) {
   using R = Rec<WHAT>;
-  using U = BusRec<WHAT>;
-  constexpr bool SLOTS = R::J || R::H;
-  const int nS = T.nP + T.nT + T.nV;
-  uint32_t pre[SPL];
+  using L = Lds<WHAT, BE, STAGE>;
+  static_assert(NBUS <= WG, "one bus per lane");
+  static_assert(WG % 64 == 0, "whole waves");
+  static_assert(!(R::C && R::JV), "generator sums hold either x or the direction");
   constexpr bool DO_GF = (WHAT & W_GRADF) != 0 && !R::V;
   const int tid = threadIdx.x;
   const int nb = N.nb;
@@ -193,210 +201,273 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   const int nll = N.nl - (ol >= 0 ? 1 : 0);
   const int b0 = T.a0, nbus = T.a1 - T.a0, e0 = T.e0;
   double* rec = smem;
-  double* bus = smem + Lds<WHAT, BE, NBUS>::kRec;
-  int2* bus_e = reinterpret_cast<int2*>(bus + U::N * NBUS);
+  // staged row segments: tile-local index of a base position (J P rows,
+  // J Q rows, H theta rows, H v rows)
+  double* stg = smem + L::kRec;
+  const int gmax = T.gmax;
+  const int sP = -T.jP0, sQ = T.nP - T.jP0;
+  const int h0 = R::J ? 2 * T.nP : 0;
+  const int sT = h0 - T.hT0, sV = h0 + T.nT - T.hV0;
   const double* x = B.x + I.xo;
   const double* mul = (R::H || R::HV) ? B.lam + I.co : (R::V ? B.wc + I.co : nullptr);
   const bool hneed = R::V || R::HV || (R::H && B.hess != nullptr);
   const double* dir = (R::HV || R::JV) ? B.dir + I.xo : nullptr;
   double* cflow = (R::C && B.c) ? B.c + I.co + 2 * nb : nullptr;
   double* jflow = (R::J && B.jac) ? B.jac + I.jo + (N.jflow - 8 * I.out_rm) : nullptr;
+  double* jac = (R::J && B.jac) ? B.jac + I.jo : nullptr;
+  double* hess = (R::H && B.hess) ? B.hess + I.ho : nullptr;
 
-  // ---- phase A (1): lane per branch touching the tile
-  for (int k = tid; k < T.nw; k += WG) {
-    const WorkItem wi = I.work[T.w0 + k];
+  // ---- phase A (1): lane per branch touching the tile.  Off-diagonal
+  // entries go to the staged rows; each end's own-bus share goes to its
+  // LDS record.  The loop bound is uniform so that whole waves meet at the
+  // group sums.
+  for (int k0 = 0; k0 < T.nw; k0 += WG) {
+    const int k = k0 + tid;
+    WorkItem wi{};
+    wi.l = -2;  // lanes past the list: no branch, no group
+    if (k < T.nw) wi = I.work[T.w0 + k];
     const int l = wi.l, f = wi.f, t = wi.t;
     const uint32_t sf = wi.slots & 0xFFFFu, st = wi.slots >> 16;
-    if (l == ol) {  // removed branch: its ends keep their places and add zero
+    const bool live = l >= 0 && l != ol;
+    const bool fwd = f < t;  // the from bus is the lower-numbered end
+    if (l >= 0 && !live) {   // removed branch: its ends keep their places and add zero
 #pragma unroll
       for (int q = 0; q < R::N; ++q) {
         if (sf != kNoSlot) rec[q * BE + sf] = 0.0;
         if (st != kNoSlot) rec[q * BE + st] = 0.0;
       }
-      continue;
     }
-    const BranchY y = N.br_y[l];
     Br b;
-    branch_eval(x[f], x[t], x[nb + f], x[nb + t], y, b);
-    const int lp = l - after_outage(l, ol);
-    if constexpr (R::C) {
-      if (sf != kNoSlot) {
-        rec[(R::oC + 0) * BE + sf] = b.Pf;
-        rec[(R::oC + 1) * BE + sf] = b.Qf;
+    int lp = 0;
+    if (live) {
+      const BranchY y = N.br_y[l];
+      branch_eval(x[f], x[t], x[nb + f], x[nb + t], y, b);
+      lp = l - after_outage(l, ol);
+      if constexpr (R::C) {
+        if (sf != kNoSlot) {
+          rec[(R::oC + 0) * BE + sf] = b.Pf;
+          rec[(R::oC + 1) * BE + sf] = b.Qf;
+        }
+        if (st != kNoSlot) {
+          rec[(R::oC + 0) * BE + st] = b.Pt;
+          rec[(R::oC + 1) * BE + st] = b.Qt;
+        }
       }
-      if (st != kNoSlot) {
-        rec[(R::oC + 0) * BE + st] = b.Pt;
-        rec[(R::oC + 1) * BE + st] = b.Qt;
+      if constexpr (R::J) {
+        if (sf != kNoSlot) {
+          rec[(R::oJ + 0) * BE + sf] = b.Pf_a();
+          rec[(R::oJ + 1) * BE + sf] = b.Pf_f();
+          rec[(R::oJ + 2) * BE + sf] = b.Qf_a();
+          rec[(R::oJ + 3) * BE + sf] = b.Qf_f();
+        }
+        if (st != kNoSlot) {  // to end: d/dtheta_t = -d/dtheta_f
+          rec[(R::oJ + 0) * BE + st] = -b.Pt_a();
+          rec[(R::oJ + 1) * BE + st] = b.Pt_t();
+          rec[(R::oJ + 2) * BE + st] = -b.Qt_a();
+          rec[(R::oJ + 3) * BE + st] = b.Qt_t();
+        }
+      }
+      if constexpr (R::JV) {  // J d: first derivatives along the direction
+        const double da = dir[f] - dir[t], dvf = dir[nb + f], dvt = dir[nb + t];
+        const double jPf = fma(b.Pf_a(), da, fma(b.Pf_f(), dvf, b.Pf_t() * dvt));
+        const double jQf = fma(b.Qf_a(), da, fma(b.Qf_f(), dvf, b.Qf_t() * dvt));
+        const double jPt = fma(b.Pt_a(), da, fma(b.Pt_f(), dvf, b.Pt_t() * dvt));
+        const double jQt = fma(b.Qt_a(), da, fma(b.Qt_f(), dvf, b.Qt_t() * dvt));
+        if (sf != kNoSlot) {
+          rec[(R::oJV + 0) * BE + sf] = jPf;
+          rec[(R::oJV + 1) * BE + sf] = jQf;
+          double* o = B.out + I.co + 2 * nb;
+          o[lp] = 2.0 * fma(b.Pf, jPf, b.Qf * jQf);
+          o[nll + lp] = 2.0 * fma(b.Pt, jPt, b.Qt * jQt);
+        }
+        if (st != kNoSlot) {
+          rec[(R::oJV + 0) * BE + st] = jPt;
+          rec[(R::oJV + 1) * BE + st] = jQt;
+        }
+      }
+      if (sf != kNoSlot) {  // the from-bus owner writes the flow-limit rows
+        if (cflow) {
+          cflow[lp] = fma(b.Pf, b.Pf, b.Qf * b.Qf);
+          cflow[nll + lp] = fma(b.Pt, b.Pt, b.Qt * b.Qt);
+        }
+        if (jflow) {
+          const double hf_a = 2.0 * fma(b.Pf, b.Pf_a(), b.Qf * b.Qf_a());
+          const double hf_f = 2.0 * fma(b.Pf, b.Pf_f(), b.Qf * b.Qf_f());
+          const double hf_t = 2.0 * fma(b.Pf, b.Pf_t(), b.Qf * b.Qf_t());
+          const double ht_a = 2.0 * fma(b.Pt, b.Pt_a(), b.Qt * b.Qt_a());
+          const double ht_f = 2.0 * fma(b.Pt, b.Pt_f(), b.Qt * b.Qt_f());
+          const double ht_t = 2.0 * fma(b.Pt, b.Pt_t(), b.Qt * b.Qt_t());
+          double* rf = jflow + 4 * lp;
+          double* rt = jflow + 4 * nll + 4 * lp;
+          rf[0] = fwd ? hf_a : -hf_a;  // columns ascend: theta_lo, theta_hi, v_lo, v_hi
+          rf[1] = fwd ? -hf_a : hf_a;
+          rf[2] = fwd ? hf_f : hf_t;
+          rf[3] = fwd ? hf_t : hf_f;
+          rt[0] = fwd ? ht_a : -ht_a;
+          rt[1] = fwd ? -ht_a : ht_a;
+          rt[2] = fwd ? ht_f : ht_t;
+          rt[3] = fwd ? ht_t : ht_f;
+        }
       }
     }
     if constexpr (R::J) {
-      if (sf != kNoSlot) {
-        rec[(R::oJ + 0) * BE + sf] = b.Pf_a();
-        rec[(R::oJ + 1) * BE + sf] = b.Pf_f();
-        rec[(R::oJ + 2) * BE + sf] = b.Pf_t();
-        rec[(R::oJ + 3) * BE + sf] = b.Qf_a();
-        rec[(R::oJ + 4) * BE + sf] = b.Qf_f();
-        rec[(R::oJ + 5) * BE + sf] = b.Qf_t();
+      // rows of the lower (lo) and higher (hi) end bus, columns of the other:
+      // d/dtheta and d/dv of P, then of Q
+      double jv[8];
+      if (live) {
+        const double fP = -b.Pf_a(), fPv = b.Pf_t(), fQ = -b.Qf_a(), fQv = b.Qf_t();
+        const double tP = b.Pt_a(), tPv = b.Pt_f(), tQ = b.Qt_a(), tQv = b.Qt_f();
+        jv[0] = fwd ? fP : tP;
+        jv[1] = fwd ? fPv : tPv;
+        jv[2] = fwd ? fQ : tQ;
+        jv[3] = fwd ? fQv : tQv;
+        jv[4] = fwd ? tP : fP;
+        jv[5] = fwd ? tPv : fPv;
+        jv[6] = fwd ? tQ : fQ;
+        jv[7] = fwd ? tQv : fQv;
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) jv[q] = 0.0;
       }
-      if (st != kNoSlot) {  // to end: d/dtheta_t = -d/dtheta_f
-        rec[(R::oJ + 0) * BE + st] = -b.Pt_a();
-        rec[(R::oJ + 1) * BE + st] = b.Pt_t();
-        rec[(R::oJ + 2) * BE + st] = b.Pt_f();
-        rec[(R::oJ + 3) * BE + st] = -b.Qt_a();
-        rec[(R::oJ + 4) * BE + st] = b.Qt_t();
-        rec[(R::oJ + 5) * BE + st] = b.Qt_f();
-      }
-    }
-    if constexpr (R::JV) {  // J d: first derivatives along the direction
-      const double da = dir[f] - dir[t], dvf = dir[nb + f], dvt = dir[nb + t];
-      const double jPf = fma(b.Pf_a(), da, fma(b.Pf_f(), dvf, b.Pf_t() * dvt));
-      const double jQf = fma(b.Qf_a(), da, fma(b.Qf_f(), dvf, b.Qf_t() * dvt));
-      const double jPt = fma(b.Pt_a(), da, fma(b.Pt_f(), dvf, b.Pt_t() * dvt));
-      const double jQt = fma(b.Qt_a(), da, fma(b.Qt_f(), dvf, b.Qt_t() * dvt));
-      if (sf != kNoSlot) {
-        rec[(R::oJV + 0) * BE + sf] = jPf;
-        rec[(R::oJV + 1) * BE + sf] = jQf;
-        double* o = B.out + I.co + 2 * nb;
-        o[lp] = 2.0 * fma(b.Pf, jPf, b.Qf * jQf);
-        o[nll + lp] = 2.0 * fma(b.Pt, jPt, b.Qt * jQt);
-      }
-      if (st != kNoSlot) {
-        rec[(R::oJV + 0) * BE + st] = jPt;
-        rec[(R::oJV + 1) * BE + st] = jQt;
-      }
-    }
-    if (sf != kNoSlot) {  // the from-bus owner writes the flow-limit rows
-      if (cflow) {
-        cflow[lp] = fma(b.Pf, b.Pf, b.Qf * b.Qf);
-        cflow[nll + lp] = fma(b.Pt, b.Pt, b.Qt * b.Qt);
-      }
-      if (jflow) {
-        const double hf_a = 2.0 * fma(b.Pf, b.Pf_a(), b.Qf * b.Qf_a());
-        const double hf_f = 2.0 * fma(b.Pf, b.Pf_f(), b.Qf * b.Qf_f());
-        const double hf_t = 2.0 * fma(b.Pf, b.Pf_t(), b.Qf * b.Qf_t());
-        const double ht_a = 2.0 * fma(b.Pt, b.Pt_a(), b.Qt * b.Qt_a());
-        const double ht_f = 2.0 * fma(b.Pt, b.Pt_f(), b.Qt * b.Qt_f());
-        const double ht_t = 2.0 * fma(b.Pt, b.Pt_t(), b.Qt * b.Qt_t());
-        const bool asc = f < t;  // columns ascend: theta_lo, theta_hi, v_lo, v_hi
-        double* rf = jflow + 4 * lp;
-        double* rt = jflow + 4 * nll + 4 * lp;
-        rf[0] = asc ? hf_a : -hf_a;
-        rf[1] = asc ? -hf_a : hf_a;
-        rf[2] = asc ? hf_f : hf_t;
-        rf[3] = asc ? hf_t : hf_f;
-        rt[0] = asc ? ht_a : -ht_a;
-        rt[1] = asc ? -ht_a : ht_a;
-        rt[2] = asc ? ht_f : ht_t;
-        rt[3] = asc ? ht_t : ht_f;
+      if (gmax > 1) group_sum(jv, wi.grp, gmax);
+      if (wi.grp > 0) {  // (entries of a removed branch without a twin are never stored)
+        if (wi.jlo >= 0) {
+          stg[sP + wi.jlo] = jv[0];
+          stg[sP + wi.jlo + wi.alo] = jv[1];
+          stg[sQ + wi.jlo] = jv[2];
+          stg[sQ + wi.jlo + wi.alo] = jv[3];
+        }
+        if (wi.jhi >= 0) {
+          stg[sP + wi.jhi] = jv[4];
+          stg[sP + wi.jhi + wi.ahi] = jv[5];
+          stg[sQ + wi.jhi] = jv[6];
+          stg[sQ + wi.jhi + wi.ahi] = jv[7];
+        }
       }
     }
     if constexpr (R::H || R::V || R::HV) {
-      if (!hneed) continue;  // the full variant reads multipliers only when H is wanted
-      const double mf = mul[2 * nb + lp];
-      const double mt = mul[2 * nb + nll + lp];
-      // weights of dP, dQ in  lP P + lQ Q + mu (P^2 + Q^2)
-      const double oPf = fma(2.0 * mf, b.Pf, mul[f]);
-      const double oQf = fma(2.0 * mf, b.Qf, mul[nb + f]);
-      const double oPt = fma(2.0 * mt, b.Pt, mul[t]);
-      const double oQt = fma(2.0 * mt, b.Qt, mul[nb + t]);
-      // s, r: the weighted transfer terms; every second derivative and the
-      // VJP are short expressions in them (the Gauss-Newton cross terms
-      // Pt_f Pt_a + Qt_f Qt_a and Pf_t Pf_a + Qf_t Qf_a vanish identically)
-      const double s = fma(oPf, b.cP, fma(oQf, b.cQ, fma(oPt, b.cPt, oQt * b.cQt)));
-      const double r = fma(oQf, b.cP, fma(-oPf, b.cQ, fma(oPt, b.cQt, -(oQt * b.cPt))));
-      if constexpr (R::V) {
-        const double u_a = b.w * r;  // d/dtheta_f; d/dtheta_t = -u_a
-        const double u_f = fma(2.0 * b.vf, fma(oPf, b.gff, -(oQf * b.bff)), b.vt * s);
-        const double u_t = fma(2.0 * b.vt, fma(oPt, b.gtt, -(oQt * b.btt)), b.vf * s);
-        if (sf != kNoSlot) {
-          rec[(R::oV + 0) * BE + sf] = u_a;
-          rec[(R::oV + 1) * BE + sf] = u_f;
+      // (theta_hi, theta_lo), (v_lo, theta_hi), (v_hi, theta_lo), (v_hi, v_lo)
+      double hv4[4] = {0.0, 0.0, 0.0, 0.0};
+      if (live && hneed) {  // the full variant reads multipliers only when H is wanted
+        const double mf = mul[2 * nb + lp];
+        const double mt = mul[2 * nb + nll + lp];
+        // weights of dP, dQ in  lP P + lQ Q + mu (P^2 + Q^2)
+        const double oPf = fma(2.0 * mf, b.Pf, mul[f]);
+        const double oQf = fma(2.0 * mf, b.Qf, mul[nb + f]);
+        const double oPt = fma(2.0 * mt, b.Pt, mul[t]);
+        const double oQt = fma(2.0 * mt, b.Qt, mul[nb + t]);
+        // s, r: the weighted transfer terms; every second derivative and the
+        // VJP are short expressions in them (the Gauss-Newton cross terms
+        // Pt_f Pt_a + Qt_f Qt_a and Pf_t Pf_a + Qf_t Qf_a vanish identically)
+        const double s = fma(oPf, b.cP, fma(oQf, b.cQ, fma(oPt, b.cPt, oQt * b.cQt)));
+        const double r = fma(oQf, b.cP, fma(-oPf, b.cQ, fma(oPt, b.cQt, -(oQt * b.cPt))));
+        if constexpr (R::V) {
+          const double u_a = b.w * r;  // d/dtheta_f; d/dtheta_t = -u_a
+          const double u_f = fma(2.0 * b.vf, fma(oPf, b.gff, -(oQf * b.bff)), b.vt * s);
+          const double u_t = fma(2.0 * b.vt, fma(oPt, b.gtt, -(oQt * b.btt)), b.vf * s);
+          if (sf != kNoSlot) {
+            rec[(R::oV + 0) * BE + sf] = u_a;
+            rec[(R::oV + 1) * BE + sf] = u_f;
+          }
+          if (st != kNoSlot) {
+            rec[(R::oV + 0) * BE + st] = -u_a;
+            rec[(R::oV + 1) * BE + st] = u_t;
+          }
         }
-        if (st != kNoSlot) {
-          rec[(R::oV + 0) * BE + st] = -u_a;
-          rec[(R::oV + 1) * BE + st] = u_t;
+        if constexpr (R::H || R::HV) {
+          const double m2f = 2.0 * mf, m2t = 2.0 * mt;
+          const double ccf = fma(b.cP, b.cP, b.cQ * b.cQ), cct = fma(b.cPt, b.cPt, b.cQt * b.cQt);
+          // d2L/dtheta_f^2
+          const double a = fma(-b.w, s, (b.w * b.w) * fma(m2f, ccf, m2t * cct));
+          // d2L/dv_f dtheta_f and d2L/dv_t dtheta_t
+          const double beta_f =
+              fma(b.vt, r, -(2.0 * m2f) * (b.vf * b.w) * fma(b.gff, b.cQ, b.bff * b.cP));
+          const double beta_t =
+              -fma(b.vf, r, (2.0 * m2t) * (b.vt * b.w) * fma(b.gtt, b.cQt, b.btt * b.cPt));
+          const double pff = b.Pf_f(), qff = b.Qf_f(), ptt = b.Pt_t(), qtt = b.Qt_t();
+          const double vv_ff = fma(2.0, fma(oPf, b.gff, -(oQf * b.bff)),
+                                   fma(m2f, fma(pff, pff, qff * qff), m2t * (b.vt * b.vt) * cct));
+          const double vv_tt = fma(2.0, fma(oPt, b.gtt, -(oQt * b.btt)),
+                                   fma(m2f * (b.vf * b.vf), ccf, m2t * fma(ptt, ptt, qtt * qtt)));
+          const double vv_ft =
+              s + fma(m2f * b.vf, fma(2.0 * b.vf, fma(b.gff, b.cP, -(b.bff * b.cQ)), b.vt * ccf),
+                      m2t * b.vt * fma(2.0 * b.vt, fma(b.gtt, b.cPt, -(b.btt * b.cQt)), b.vf * cct));
+          if constexpr (R::H) {
+            if (sf != kNoSlot) {
+              rec[(R::oH + 0) * BE + sf] = a;
+              rec[(R::oH + 1) * BE + sf] = beta_f;
+              rec[(R::oH + 2) * BE + sf] = vv_ff;
+            }
+            if (st != kNoSlot) {
+              rec[(R::oH + 0) * BE + st] = a;
+              rec[(R::oH + 1) * BE + st] = beta_t;
+              rec[(R::oH + 2) * BE + st] = vv_tt;
+            }
+            // d/dtheta_t = -d/dtheta_f
+            hv4[0] = -a;
+            hv4[1] = fwd ? -beta_f : -beta_t;
+            hv4[2] = fwd ? -beta_t : -beta_f;
+            hv4[3] = vv_ft;
+          }
+          if constexpr (R::HV) {
+            // the branch's 4x4 block on (theta_f, theta_t, v_f, v_t) times d:
+            // theta rows +-(a da + beta_f d_vf - beta_t d_vt), v rows below
+            const double da = dir[f] - dir[t], dvf = dir[nb + f], dvt = dir[nb + t];
+            const double h_a = fma(a, da, fma(beta_f, dvf, -(beta_t * dvt)));
+            if (sf != kNoSlot) {
+              rec[(R::oHV + 0) * BE + sf] = h_a;
+              rec[(R::oHV + 1) * BE + sf] = fma(beta_f, da, fma(vv_ff, dvf, vv_ft * dvt));
+            }
+            if (st != kNoSlot) {
+              rec[(R::oHV + 0) * BE + st] = -h_a;
+              rec[(R::oHV + 1) * BE + st] = fma(-beta_t, da, fma(vv_ft, dvf, vv_tt * dvt));
+            }
+          }
         }
       }
-      if constexpr (R::H || R::HV) {
-        const double m2f = 2.0 * mf, m2t = 2.0 * mt;
-        const double ccf = fma(b.cP, b.cP, b.cQ * b.cQ), cct = fma(b.cPt, b.cPt, b.cQt * b.cQt);
-        // d2L/dtheta_f^2
-        const double a = fma(-b.w, s, (b.w * b.w) * fma(m2f, ccf, m2t * cct));
-        // d2L/dv_f dtheta_f and d2L/dv_t dtheta_t
-        const double beta_f =
-            fma(b.vt, r, -(2.0 * m2f) * (b.vf * b.w) * fma(b.gff, b.cQ, b.bff * b.cP));
-        const double beta_t =
-            -fma(b.vf, r, (2.0 * m2t) * (b.vt * b.w) * fma(b.gtt, b.cQt, b.btt * b.cPt));
-        const double pff = b.Pf_f(), qff = b.Qf_f(), ptt = b.Pt_t(), qtt = b.Qt_t();
-        const double vv_ff = fma(2.0, fma(oPf, b.gff, -(oQf * b.bff)),
-                                 fma(m2f, fma(pff, pff, qff * qff), m2t * (b.vt * b.vt) * cct));
-        const double vv_tt = fma(2.0, fma(oPt, b.gtt, -(oQt * b.btt)),
-                                 fma(m2f * (b.vf * b.vf), ccf, m2t * fma(ptt, ptt, qtt * qtt)));
-        const double vv_ft =
-            s + fma(m2f * b.vf, fma(2.0 * b.vf, fma(b.gff, b.cP, -(b.bff * b.cQ)), b.vt * ccf),
-                    m2t * b.vt * fma(2.0 * b.vt, fma(b.gtt, b.cPt, -(b.btt * b.cQt)), b.vf * cct));
-        if constexpr (R::H) {
-          if (sf != kNoSlot) {
-            rec[(R::oH + 0) * BE + sf] = a;
-            rec[(R::oH + 1) * BE + sf] = beta_f;
-            rec[(R::oH + 2) * BE + sf] = vv_ff;
-            rec[(R::oH + 3) * BE + sf] = vv_ft;
-          }
-          if (st != kNoSlot) {
-            rec[(R::oH + 0) * BE + st] = a;
-            rec[(R::oH + 1) * BE + st] = beta_t;
-            rec[(R::oH + 2) * BE + st] = vv_tt;
-            rec[(R::oH + 3) * BE + st] = vv_ft;
-          }
-        }
-        if constexpr (R::HV) {
-          // the branch's 4x4 block on (theta_f, theta_t, v_f, v_t) times d:
-          // theta rows +-(a da + beta_f d_vf - beta_t d_vt), v rows below
-          const double da = dir[f] - dir[t], dvf = dir[nb + f], dvt = dir[nb + t];
-          const double h_a = fma(a, da, fma(beta_f, dvf, -(beta_t * dvt)));
-          if (sf != kNoSlot) {
-            rec[(R::oHV + 0) * BE + sf] = h_a;
-            rec[(R::oHV + 1) * BE + sf] = fma(beta_f, da, fma(vv_ff, dvf, vv_ft * dvt));
-          }
-          if (st != kNoSlot) {
-            rec[(R::oHV + 0) * BE + st] = -h_a;
-            rec[(R::oHV + 1) * BE + st] = fma(-beta_t, da, fma(vv_ft, dvf, vv_tt * dvt));
+      if constexpr (R::H) {
+        if (gmax > 1) group_sum(hv4, wi.grp, gmax);
+        if (wi.grp > 0) {
+          if (wi.jlo >= 0) stg[sV + wi.hvlo] = hv4[1];
+          if (wi.jhi >= 0) {
+            stg[sT + wi.hthi] = hv4[0];
+            stg[sV + wi.hvhi] = hv4[2];
+            stg[sV + wi.hvhi + wi.ahi] = hv4[3];
           }
         }
       }
     }
   }
 
-  // slot-map entries of this lane, fetched here so that their latency
-  // overlaps the bus pass and the barrier (not live across the branch pass,
-  // the register peak)
-  if constexpr (SLOTS) {
-    const uint32_t* smg = I.slots + T.sm0;
-#pragma unroll
-    for (int r = 0; r < SPL; ++r) {
-      const int k = threadIdx.x + r * WG;
-      pre[r] = k < nS ? smg[k] : 0u;
-    }
-  }
-
-  // ---- phase A (2): lane per bus, the bus's own terms
-  const bool jout = R::J && B.jac != nullptr;
-  const bool hout = R::H && B.hess != nullptr;
+  // ---- phase A (2): lane per bus, the bus's own terms (kept in registers
+  // across the barrier by the same lane)
+  const bool has_bus = tid < nbus;
+  const int i = b0 + tid;
+  int ea = 0, eb = 0;
+  int4 rw = make_int4(0, 0, 0, 0);
+  int2 ac = make_int2(0, 0);
+  int ngb = 0;
+  double jbP = 0.0, jbQ = 0.0, hb = 0.0, cbP = 0.0, cbQ = 0.0, vb = 0.0, hvb = 0.0;
+  double jvP = 0.0, jvQ = 0.0;
   double* c = (R::C && B.c) ? B.c + I.co : nullptr;
-  for (int ib = tid; ib < nbus; ib += WG) {
-    const int i = b0 + ib;
-    const int ea = N.be_ptr[i];
-    bus_e[ib] = make_int2(ea - e0, N.be_ptr[i + 1] - ea);
+  if (has_bus) {
+    ea = N.be_ptr[i] - e0;
+    eb = N.be_ptr[i + 1] - e0;
     const double4 bd = N.bus[i];  // pd, qd, gs, bs
     const double vi = x[nb + i];
-    if constexpr (U::J) {
-      bus[(U::oJ + 0) * NBUS + ib] = 2.0 * bd.z * vi;
-      bus[(U::oJ + 1) * NBUS + ib] = -2.0 * bd.w * vi;
+    if constexpr (R::J || R::H) {
+      rw = N.rows[i];
+      ac = N.acnt[i];
     }
-    if constexpr (U::H) {
-      if (hout) bus[U::oH * NBUS + ib] = 2.0 * fma(mul[i], bd.z, -(mul[nb + i] * bd.w));
+    if constexpr (R::J) {
+      jbP = 2.0 * bd.z * vi;
+      jbQ = -2.0 * bd.w * vi;
+      ngb = N.gen_ptr[i + 1] - N.gen_ptr[i];
     }
-    if constexpr (U::C) {
+    if constexpr (R::H) {
+      if (hess) hb = 2.0 * fma(mul[i], bd.z, -(mul[nb + i] * bd.w));
+    }
+    if constexpr (R::C) {
       if (c) {
         double pg = 0, qg = 0;
         for (int g = N.gen_ptr[i], g1 = N.gen_ptr[i + 1]; g < g1; ++g) {
@@ -404,128 +475,142 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
           pg += x[2 * nb + k];
           qg += x[2 * nb + N.ng + k];
         }
-        bus[(U::oC + 0) * NBUS + ib] = (bd.z * vi * vi - pg) + bd.x;
-        bus[(U::oC + 1) * NBUS + ib] = (-bd.w * vi * vi - qg) + bd.y;
+        cbP = (bd.z * vi * vi - pg) + bd.x;
+        cbQ = (-bd.w * vi * vi - qg) + bd.y;
       }
     }
-    if constexpr (U::V) {
-      bus[U::oV * NBUS + ib] = 2.0 * vi * fma(mul[i], bd.z, -(mul[nb + i] * bd.w));
+    if constexpr (R::V) {
+      vb = 2.0 * vi * fma(mul[i], bd.z, -(mul[nb + i] * bd.w));
     }
-    if constexpr (U::HV) {
-      bus[U::oHV * NBUS + ib] = 2.0 * fma(mul[i], bd.z, -(mul[nb + i] * bd.w)) * dir[nb + i];
+    if constexpr (R::HV) {
+      hvb = 2.0 * fma(mul[i], bd.z, -(mul[nb + i] * bd.w)) * dir[nb + i];
     }
-    if constexpr (U::JV) {
+    if constexpr (R::JV) {
       double dpg = 0, dqg = 0;
       for (int g = N.gen_ptr[i], g1 = N.gen_ptr[i + 1]; g < g1; ++g) {
         const int k = N.gen_list[g];
         dpg += dir[2 * nb + k];
         dqg += dir[2 * nb + N.ng + k];
       }
-      bus[(U::oJV + 0) * NBUS + ib] = 2.0 * bd.z * vi * dir[nb + i] - dpg;
-      bus[(U::oJV + 1) * NBUS + ib] = -2.0 * bd.w * vi * dir[nb + i] - dqg;
+      jvP = 2.0 * bd.z * vi * dir[nb + i] - dpg;
+      jvQ = -2.0 * bd.w * vi * dir[nb + i] - dqg;
     }
   }
   __syncthreads();
 
-  // ---- phase B: lane per output entry, from the prefetched slot map
-  if constexpr (SLOTS) {
-    const bool rm = I.out_rm != 0;
-    const SegShift shP(T.jP0, T.nP, I.rj), shQ(T.jQ0, T.nP, I.rj);
-    const SegShift shT(T.hT0, T.nT, I.rh), shV(T.hV0, T.nV, I.rh);
-    double* jac = jout ? B.jac + I.jo : nullptr;
-    double* hess = hout ? B.hess + I.ho : nullptr;
-#pragma unroll
-    for (int r = 0; r < SPL; ++r) {
-      const int k = tid + r * WG;
-      if (k >= nS) continue;
-      const uint32_t ent = pre[r];
-      const int ea = ent & 511u, cnt = (ent >> 9) & 1023u, fld = (ent >> 19) & 3u;
-      const bool neg = (ent >> 21) & 1u;
-      const int kind = (ent >> 22) & 3u, bl = ent >> 24;
-      if (k < T.nP) {
-        if (!jout) continue;
-        double vp = 0.0, vq = 0.0;
-        for (int e = ea; e < ea + cnt; ++e) {
-          vp += rec[(R::oJ + fld) * BE + e];
-          vq += rec[(R::oJ + 3 + fld) * BE + e];
-        }
-        if (neg) {
-          vp = -vp;
-          vq = -vq;
-        }
-        if (kind == SK_JDIAG_V) {
-          vp += bus[(U::oJ + 0) * NBUS + bl];
-          vq += bus[(U::oJ + 1) * NBUS + bl];
-        } else if (kind == SK_GEN) {
-          vp = -1.0;
-          vq = -1.0;
-        }
-        const int gp = rm ? place(T.jP0 + k, shP, I.rj) : T.jP0 + k;
-        const int gq = rm ? place(T.jQ0 + k, shQ, I.rj) : T.jQ0 + k;
-        if (gp >= 0) jac[gp] = vp;
-        if (gq >= 0) jac[gq] = vq;
-      } else {
-        if (!hout) continue;
-        double v = 0.0;
-        for (int e = ea; e < ea + cnt; ++e) v += rec[(R::oH + fld) * BE + e];
-        if (neg) v = -v;
-        if (kind == SK_HDIAG_V) v += bus[U::oH * NBUS + bl];
-        const bool th = k < T.nP + T.nT;
-        const int base = th ? T.hT0 + (k - T.nP) : T.hV0 + (k - T.nP - T.nT);
-        const int gp = rm ? place(base, th ? shT : shV, I.rh) : base;
-        if (gp >= 0) hess[gp] = v;
+  // ---- phase B: lane per bus, its ends' records summed in adjacency order
+  // into the diagonal entries (staged) and the bus's rows
+  if (has_bus) {
+  if constexpr (R::C) {
+    if (c) {
+      double sp = 0.0, sq = 0.0;
+      for (int e = ea; e < eb; ++e) {
+        sp += rec[(R::oC + 0) * BE + e];
+        sq += rec[(R::oC + 1) * BE + e];
+      }
+      c[i] = sp + cbP;
+      c[nb + i] = sq + cbQ;
+    }
+  }
+  if constexpr (DO_GF) {
+    if (B.gradf) {
+      double* gradf = B.gradf + I.xo;
+      gradf[i] = 0.0;
+      gradf[nb + i] = 0.0;
+    }
+  }
+  if constexpr (R::J) {
+    if (jac) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int e = ea; e < eb; ++e) {
+        s0 += rec[(R::oJ + 0) * BE + e];
+        s1 += rec[(R::oJ + 1) * BE + e];
+        s2 += rec[(R::oJ + 2) * BE + e];
+        s3 += rec[(R::oJ + 3) * BE + e];
+      }
+      // (theta_i), (v_i) of the P row, the same of the Q row, then the
+      // generator columns (constant -1)
+      const int pt = rw.x + ac.y, pv = rw.x + ac.x + ac.y;
+      stg[sP + pt] = s0;
+      stg[sP + pv] = s1 + jbP;
+      stg[sQ + pt] = s2;
+      stg[sQ + pv] = s3 + jbQ;
+      for (int g = 0; g < ngb; ++g) {
+        stg[sP + rw.x + 2 * ac.x + g] = -1.0;
+        stg[sQ + rw.x + 2 * ac.x + g] = -1.0;
       }
     }
   }
-  if constexpr (R::C || R::V || R::HV || R::JV || DO_GF) {
-    double* gradf = (DO_GF && B.gradf) ? B.gradf + I.xo : nullptr;
-    for (int ib = tid; ib < nbus; ib += WG) {
-      const int i = b0 + ib;
-      const int2 be = bus_e[ib];
-      if constexpr (R::C) {
-        if (c) {
-          double sp = 0.0, sq = 0.0;
-          for (int e = be.x; e < be.x + be.y; ++e) {
-            sp += rec[(R::oC + 0) * BE + e];
-            sq += rec[(R::oC + 1) * BE + e];
-          }
-          c[i] = sp + bus[(U::oC + 0) * NBUS + ib];
-          c[nb + i] = sq + bus[(U::oC + 1) * NBUS + ib];
+  if constexpr (R::H) {
+    if (hess) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (int e = ea; e < eb; ++e) {
+        s0 += rec[(R::oH + 0) * BE + e];
+        s1 += rec[(R::oH + 1) * BE + e];
+        s2 += rec[(R::oH + 2) * BE + e];
+      }
+      stg[sT + rw.z + ac.y] = s0;
+      stg[sV + rw.w + ac.y] = s1;
+      stg[sV + rw.w + ac.x + ac.y] = s2 + hb;
+    }
+  }
+  if constexpr (R::V) {
+    double ut = 0.0, uv = 0.0;
+    for (int e = ea; e < eb; ++e) {
+      ut += rec[(R::oV + 0) * BE + e];
+      uv += rec[(R::oV + 1) * BE + e];
+    }
+    double* u = B.u + I.xo;
+    u[i] = ut;
+    u[nb + i] = uv + vb;
+  }
+  if constexpr (R::HV) {
+    double ht = 0.0, hv = 0.0;
+    for (int e = ea; e < eb; ++e) {
+      ht += rec[(R::oHV + 0) * BE + e];
+      hv += rec[(R::oHV + 1) * BE + e];
+    }
+    double* o = B.out + I.xo;
+    o[i] = ht;
+    o[nb + i] = hv + hvb;
+  }
+  if constexpr (R::JV) {
+    double jp = 0.0, jq = 0.0;
+    for (int e = ea; e < eb; ++e) {
+      jp += rec[(R::oJV + 0) * BE + e];
+      jq += rec[(R::oJV + 1) * BE + e];
+    }
+    double* o = B.out + I.co;
+    o[i] = jp + jvP;
+    o[nb + i] = jq + jvQ;
+  }
+  }
+
+  // ---- phase C: the staged row segments, consecutive lanes on consecutive
+  // entries; an N-1 instance skips the removed positions and shifts the rest
+  if constexpr (R::J || R::H) {
+    __syncthreads();
+    const bool rm = I.out_rm != 0;
+    const SegShift shP(T.jP0, T.nP, I.rj), shQ(T.jQ0, T.nP, I.rj);
+    const SegShift shT(T.hT0, T.nT, I.rh), shV(T.hV0, T.nV, I.rh);
+    if constexpr (R::J) {
+      if (jac) {
+        for (int k = tid; k < 2 * T.nP; k += WG) {
+          const bool q = k >= T.nP;
+          const int gp = q ? T.jQ0 + (k - T.nP) : T.jP0 + k;
+          const int p = rm ? place(gp, q ? shQ : shP, I.rj) : gp;
+          if (p >= 0) jac[p] = stg[k];
         }
       }
-      if (gradf) {
-        gradf[i] = 0.0;
-        gradf[nb + i] = 0.0;
-      }
-      if constexpr (R::V) {
-        double ut = 0.0, uv = 0.0;
-        for (int e = be.x; e < be.x + be.y; ++e) {
-          ut += rec[(R::oV + 0) * BE + e];
-          uv += rec[(R::oV + 1) * BE + e];
+    }
+    if constexpr (R::H) {
+      if (hess) {
+        for (int k = tid; k < T.nT + T.nV; k += WG) {
+          const bool v = k >= T.nT;
+          const int gp = v ? T.hV0 + (k - T.nT) : T.hT0 + k;
+          const int p = rm ? place(gp, v ? shV : shT, I.rh) : gp;
+          if (p >= 0) hess[p] = stg[h0 + k];
         }
-        double* u = B.u + I.xo;
-        u[i] = ut;
-        u[nb + i] = uv + bus[U::oV * NBUS + ib];
-      }
-      if constexpr (R::HV) {
-        double ht = 0.0, hv = 0.0;
-        for (int e = be.x; e < be.x + be.y; ++e) {
-          ht += rec[(R::oHV + 0) * BE + e];
-          hv += rec[(R::oHV + 1) * BE + e];
-        }
-        double* o = B.out + I.xo;
-        o[i] = ht;
-        o[nb + i] = hv + bus[U::oHV * NBUS + ib];
-      }
-      if constexpr (R::JV) {
-        double jp = 0.0, jq = 0.0;
-        for (int e = be.x; e < be.x + be.y; ++e) {
-          jp += rec[(R::oJV + 0) * BE + e];
-          jq += rec[(R::oJV + 1) * BE + e];
-        }
-        double* o = B.out + I.co;
-        o[i] = jp + bus[(U::oJV + 0) * NBUS + ib];
-        o[nb + i] = jq + bus[(U::oJV + 1) * NBUS + ib];
       }
     }
   }
@@ -608,17 +693,17 @@ __global__ __launch_bounds__(256) void k_fsum(const InstOff* __restrict__ table,
 
 // ---------------------------------------------------------------------------
 
-template <unsigned WHAT, int WG, int BE, int NBUS, int SPL>
+template <unsigned WHAT, int WG, int BE, int NBUS, int STAGE>
 __global__ __launch_bounds__(WG) void k_eval(Bufs B, const InstOff* __restrict__ table,
                                              InstOff one, const Tile* __restrict__ tiles,
                                              int ntiles) {
-  __shared__ double smem[Lds<WHAT, BE, NBUS>::kMax];
+  __shared__ double smem[Lds<WHAT, BE, STAGE>::kMax];
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const Tile T = tiles[t];
     const InstOff I = table ? table[T.inst] : one;
     const NetDev& N = *I.net;
     if ((T.kind_aux & 3) == TILE_BUS) {
-      bus_tile<WHAT, WG, BE, NBUS, SPL>(B, I, N, T, smem);
+      bus_tile<WHAT, WG, BE, NBUS, STAGE>(B, I, N, T, smem);
     } else {
       if constexpr ((WHAT & (W_F | W_GRADF | W_H | W_VJP | W_HVP)) != 0)
         gen_tile<WHAT, WG>(B, I, N, T.a0, T.a1, T.kind_aux >> 2, smem);
@@ -635,7 +720,7 @@ hipError_t launch_caps(int tile_be, const Bufs& b, const InstOff* table, const I
   switch (tile_be) {
 #define ACOPF_CASE(C)                                                                      \
   case C.be:                                                                               \
-    k_eval<WHAT, C.wg, C.be, C.nbus, C.spl><<<blocks, C.wg, 0, s>>>(b, table, one, tiles, ntiles); \
+    k_eval<WHAT, C.wg, C.be, C.nbus, C.stage><<<blocks, C.wg, 0, s>>>(b, table, one, tiles, ntiles); \
     break;
     ACOPF_CASE(kCaps64)
     ACOPF_CASE(kCaps128)
