@@ -11,7 +11,6 @@ oracle timed on a bounded sample on this host.
     python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--workload c2|c1|c3]
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -24,20 +23,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "bus-evals/sec for f,g,∇f,J,H (batched vs plain, FP64); p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2203_10587_amd/csrc/acopf_kernels.hip",
-                  "paper_2203_10587_amd/csrc/acopf_internal.h"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def kernel_hash():
-    h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 # ---------------------------------------------------------------------------
@@ -135,6 +124,7 @@ def load_traffic(kernel_name, workload):
     try:
         doc = json.load(open(p))
         ent = doc.get(workload)
+        from paper_2203_10587_amd.profiling import kernel_hash
         if not ent or ent.get("kernel_hash") != kernel_hash():
             return None
         return float(ent["fetch_bytes"]) + float(ent["write_bytes"])
