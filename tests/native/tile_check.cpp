@@ -6,11 +6,17 @@
 #include <cstdio>
 extern "C" int tile_check(const acopf_net_desc* d, int tile_be) {
   Topology T;
-  if (build_topology(d, &T)) { printf("topology: %s\n", t_err.c_str()); return 1; }
+  if (build_topology(d, &T)) {
+    printf("topology: %s\n", t_err.c_str());
+    return 1;
+  }
   std::vector<int32_t> jp, jc, hp, hc;
   build_pattern(T, -1, &jp, &jc, &hp, &hc);
   Schedule S;
-  if (make_tiles(T, tile_be, &S)) { printf("tiles: %s\n", t_err.c_str()); return 2; }
+  if (make_tiles(T, tile_be, &S)) {
+    printf("tiles: %s\n", t_err.c_str());
+    return 2;
+  }
   const int nb = T.nb;
   const int qoff = T.rows[0].y - T.rows[0].x;
   std::vector<int> jcnt(T.jflow, 0), hcnt(T.hpg, 0);
@@ -77,7 +83,11 @@ extern "C" int tile_check(const acopf_net_desc* d, int tile_be) {
   }
   for (int p = 0; p < T.jflow; ++p) chk(jcnt[p] == 1, "J coverage", p, jcnt[p]);
   for (int p = 0; p < T.hpg; ++p) chk(hcnt[p] == 1, "H coverage", p, hcnt[p]);
-  printf("tile_be %d: %d tiles, %zu work items, %d failures\n", tile_be, S.counts[0], S.work.size(), bad);
+  if (bad) {
+    printf("tile_be %d: %d tiles, %zu work items, %d failures\n", tile_be, S.counts[0],
+           S.work.size(), bad);
+    fflush(stdout);
+  }
   return bad ? 3 : 0;
 }
 // The host code references the kernel launchers; this check never launches.
