@@ -137,8 +137,8 @@ struct TileCaps {
 };
 
 constexpr TileCaps kCaps64 = {64, 64, 32, 768};
-constexpr TileCaps kCaps128 = {128, 128, 64, 1536};
-constexpr TileCaps kCaps256 = {256, 256, 128, 3072};
+constexpr TileCaps kCaps128 = {128, 128, 64, 1152};
+constexpr TileCaps kCaps256 = {256, 256, 128, 2304};
 constexpr TileCaps kCaps512 = {256, 512, 256, 6144};
 constexpr int kMaxGroup = 64;  // parallel branches between one bus pair
 constexpr int kDefaultTileBe = 256;

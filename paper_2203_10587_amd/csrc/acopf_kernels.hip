@@ -44,6 +44,8 @@
 // through theta, so every d/dtheta_t is the negative of d/dtheta_f.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "acopf_internal.h"
 
 namespace acopf {
@@ -221,222 +223,238 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   // entries go to the staged rows; each end's own-bus share goes to its
   // LDS record.  The loop bound is uniform so that whole waves meet at the
   // group sums.
-  for (int k0 = 0; k0 < T.nw; k0 += WG) {
-    const int k = k0 + tid;
-    WorkItem wi{};
-    wi.l = -2;  // lanes past the list: no branch, no group
-    if (k < T.nw) wi = I.work[T.w0 + k];
-    const int l = wi.l, f = wi.f, t = wi.t;
-    const uint32_t sf = wi.slots & 0xFFFFu, st = wi.slots >> 16;
-    const bool live = l >= 0 && l != ol;
-    const bool fwd = f < t;  // the from bus is the lower-numbered end
-    if (l >= 0 && !live) {   // removed branch: its ends keep their places and add zero
-#pragma unroll
-      for (int q = 0; q < R::N; ++q) {
-        if (sf != kNoSlot) rec[q * BE + sf] = 0.0;
-        if (st != kNoSlot) rec[q * BE + st] = 0.0;
-      }
-    }
-    Br b;
-    int lp = 0;
-    if (live) {
-      const BranchY y = N.br_y[l];
-      branch_eval(x[f], x[t], x[nb + f], x[nb + t], y, b);
-      lp = l - after_outage(l, ol);
-      if constexpr (R::C) {
-        if (sf != kNoSlot) {
-          rec[(R::oC + 0) * BE + sf] = b.Pf;
-          rec[(R::oC + 1) * BE + sf] = b.Qf;
-        }
-        if (st != kNoSlot) {
-          rec[(R::oC + 0) * BE + st] = b.Pt;
-          rec[(R::oC + 1) * BE + st] = b.Qt;
+  // A variant that forms both first and second derivatives walks the
+  // branches twice (flows and Jacobian, then Hessian), recomputing the flows
+  // from L2-resident inputs: the register peak is then the larger pass's,
+  // not their union, which keeps more waves resident.
+  auto branch_pass = [&](auto parts) {
+    constexpr unsigned P = decltype(parts)::value;
+    constexpr bool pC = (P & W_C) != 0, pJ = (P & W_J) != 0, pH = (P & W_H) != 0;
+    constexpr bool pV = (P & W_VJP) != 0, pHV = (P & W_HVP) != 0, pJV = (P & W_JVP) != 0;
+    constexpr bool FIRST = P == WHAT || (P & ~W_H) != 0;
+    for (int k0 = 0; k0 < T.nw; k0 += WG) {
+      const int k = k0 + tid;
+      WorkItem wi{};
+      wi.l = -2;  // lanes past the list: no branch, no group
+      if (k < T.nw) wi = I.work[T.w0 + k];
+      const int l = wi.l, f = wi.f, t = wi.t;
+      const uint32_t sf = wi.slots & 0xFFFFu, st = wi.slots >> 16;
+      const bool live = l >= 0 && l != ol;
+      const bool fwd = f < t;  // the from bus is the lower-numbered end
+      if (FIRST && l >= 0 && !live) {  // removed branch: its ends keep their places and add zero
+  #pragma unroll
+        for (int q = 0; q < R::N; ++q) {
+          if (sf != kNoSlot) rec[q * BE + sf] = 0.0;
+          if (st != kNoSlot) rec[q * BE + st] = 0.0;
         }
       }
-      if constexpr (R::J) {
-        if (sf != kNoSlot) {
-          rec[(R::oJ + 0) * BE + sf] = b.Pf_a();
-          rec[(R::oJ + 1) * BE + sf] = b.Pf_f();
-          rec[(R::oJ + 2) * BE + sf] = b.Qf_a();
-          rec[(R::oJ + 3) * BE + sf] = b.Qf_f();
-        }
-        if (st != kNoSlot) {  // to end: d/dtheta_t = -d/dtheta_f
-          rec[(R::oJ + 0) * BE + st] = -b.Pt_a();
-          rec[(R::oJ + 1) * BE + st] = b.Pt_t();
-          rec[(R::oJ + 2) * BE + st] = -b.Qt_a();
-          rec[(R::oJ + 3) * BE + st] = b.Qt_t();
-        }
-      }
-      if constexpr (R::JV) {  // J d: first derivatives along the direction
-        const double da = dir[f] - dir[t], dvf = dir[nb + f], dvt = dir[nb + t];
-        const double jPf = fma(b.Pf_a(), da, fma(b.Pf_f(), dvf, b.Pf_t() * dvt));
-        const double jQf = fma(b.Qf_a(), da, fma(b.Qf_f(), dvf, b.Qf_t() * dvt));
-        const double jPt = fma(b.Pt_a(), da, fma(b.Pt_f(), dvf, b.Pt_t() * dvt));
-        const double jQt = fma(b.Qt_a(), da, fma(b.Qt_f(), dvf, b.Qt_t() * dvt));
-        if (sf != kNoSlot) {
-          rec[(R::oJV + 0) * BE + sf] = jPf;
-          rec[(R::oJV + 1) * BE + sf] = jQf;
-          double* o = B.out + I.co + 2 * nb;
-          o[lp] = 2.0 * fma(b.Pf, jPf, b.Qf * jQf);
-          o[nll + lp] = 2.0 * fma(b.Pt, jPt, b.Qt * jQt);
-        }
-        if (st != kNoSlot) {
-          rec[(R::oJV + 0) * BE + st] = jPt;
-          rec[(R::oJV + 1) * BE + st] = jQt;
-        }
-      }
-      if (sf != kNoSlot) {  // the from-bus owner writes the flow-limit rows
-        if (cflow) {
-          cflow[lp] = fma(b.Pf, b.Pf, b.Qf * b.Qf);
-          cflow[nll + lp] = fma(b.Pt, b.Pt, b.Qt * b.Qt);
-        }
-        if (jflow) {
-          const double hf_a = 2.0 * fma(b.Pf, b.Pf_a(), b.Qf * b.Qf_a());
-          const double hf_f = 2.0 * fma(b.Pf, b.Pf_f(), b.Qf * b.Qf_f());
-          const double hf_t = 2.0 * fma(b.Pf, b.Pf_t(), b.Qf * b.Qf_t());
-          const double ht_a = 2.0 * fma(b.Pt, b.Pt_a(), b.Qt * b.Qt_a());
-          const double ht_f = 2.0 * fma(b.Pt, b.Pt_f(), b.Qt * b.Qt_f());
-          const double ht_t = 2.0 * fma(b.Pt, b.Pt_t(), b.Qt * b.Qt_t());
-          double* rf = jflow + 4 * lp;
-          double* rt = jflow + 4 * nll + 4 * lp;
-          rf[0] = fwd ? hf_a : -hf_a;  // columns ascend: theta_lo, theta_hi, v_lo, v_hi
-          rf[1] = fwd ? -hf_a : hf_a;
-          rf[2] = fwd ? hf_f : hf_t;
-          rf[3] = fwd ? hf_t : hf_f;
-          rt[0] = fwd ? ht_a : -ht_a;
-          rt[1] = fwd ? -ht_a : ht_a;
-          rt[2] = fwd ? ht_f : ht_t;
-          rt[3] = fwd ? ht_t : ht_f;
-        }
-      }
-    }
-    if constexpr (R::J) {
-      // rows of the lower (lo) and higher (hi) end bus, columns of the other:
-      // d/dtheta and d/dv of P, then of Q
-      double jv[8];
+      Br b;
+      int lp = 0;
       if (live) {
-        const double fP = -b.Pf_a(), fPv = b.Pf_t(), fQ = -b.Qf_a(), fQv = b.Qf_t();
-        const double tP = b.Pt_a(), tPv = b.Pt_f(), tQ = b.Qt_a(), tQv = b.Qt_f();
-        jv[0] = fwd ? fP : tP;
-        jv[1] = fwd ? fPv : tPv;
-        jv[2] = fwd ? fQ : tQ;
-        jv[3] = fwd ? fQv : tQv;
-        jv[4] = fwd ? tP : fP;
-        jv[5] = fwd ? tPv : fPv;
-        jv[6] = fwd ? tQ : fQ;
-        jv[7] = fwd ? tQv : fQv;
-      } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) jv[q] = 0.0;
-      }
-      if (gmax > 1) group_sum(jv, wi.grp, gmax);
-      if (wi.grp > 0) {  // (entries of a removed branch without a twin are never stored)
-        if (wi.jlo >= 0) {
-          stg[sP + wi.jlo] = jv[0];
-          stg[sP + wi.jlo + wi.alo] = jv[1];
-          stg[sQ + wi.jlo] = jv[2];
-          stg[sQ + wi.jlo + wi.alo] = jv[3];
-        }
-        if (wi.jhi >= 0) {
-          stg[sP + wi.jhi] = jv[4];
-          stg[sP + wi.jhi + wi.ahi] = jv[5];
-          stg[sQ + wi.jhi] = jv[6];
-          stg[sQ + wi.jhi + wi.ahi] = jv[7];
-        }
-      }
-    }
-    if constexpr (R::H || R::V || R::HV) {
-      // (theta_hi, theta_lo), (v_lo, theta_hi), (v_hi, theta_lo), (v_hi, v_lo)
-      double hv4[4] = {0.0, 0.0, 0.0, 0.0};
-      if (live && hneed) {  // the full variant reads multipliers only when H is wanted
-        const double mf = mul[2 * nb + lp];
-        const double mt = mul[2 * nb + nll + lp];
-        // weights of dP, dQ in  lP P + lQ Q + mu (P^2 + Q^2)
-        const double oPf = fma(2.0 * mf, b.Pf, mul[f]);
-        const double oQf = fma(2.0 * mf, b.Qf, mul[nb + f]);
-        const double oPt = fma(2.0 * mt, b.Pt, mul[t]);
-        const double oQt = fma(2.0 * mt, b.Qt, mul[nb + t]);
-        // s, r: the weighted transfer terms; every second derivative and the
-        // VJP are short expressions in them (the Gauss-Newton cross terms
-        // Pt_f Pt_a + Qt_f Qt_a and Pf_t Pf_a + Qf_t Qf_a vanish identically)
-        const double s = fma(oPf, b.cP, fma(oQf, b.cQ, fma(oPt, b.cPt, oQt * b.cQt)));
-        const double r = fma(oQf, b.cP, fma(-oPf, b.cQ, fma(oPt, b.cQt, -(oQt * b.cPt))));
-        if constexpr (R::V) {
-          const double u_a = b.w * r;  // d/dtheta_f; d/dtheta_t = -u_a
-          const double u_f = fma(2.0 * b.vf, fma(oPf, b.gff, -(oQf * b.bff)), b.vt * s);
-          const double u_t = fma(2.0 * b.vt, fma(oPt, b.gtt, -(oQt * b.btt)), b.vf * s);
+        const BranchY y = N.br_y[l];
+        branch_eval(x[f], x[t], x[nb + f], x[nb + t], y, b);
+        lp = l - after_outage(l, ol);
+        if constexpr (pC) {
           if (sf != kNoSlot) {
-            rec[(R::oV + 0) * BE + sf] = u_a;
-            rec[(R::oV + 1) * BE + sf] = u_f;
+            rec[(R::oC + 0) * BE + sf] = b.Pf;
+            rec[(R::oC + 1) * BE + sf] = b.Qf;
           }
           if (st != kNoSlot) {
-            rec[(R::oV + 0) * BE + st] = -u_a;
-            rec[(R::oV + 1) * BE + st] = u_t;
+            rec[(R::oC + 0) * BE + st] = b.Pt;
+            rec[(R::oC + 1) * BE + st] = b.Qt;
           }
         }
-        if constexpr (R::H || R::HV) {
-          const double m2f = 2.0 * mf, m2t = 2.0 * mt;
-          const double ccf = fma(b.cP, b.cP, b.cQ * b.cQ), cct = fma(b.cPt, b.cPt, b.cQt * b.cQt);
-          // d2L/dtheta_f^2
-          const double a = fma(-b.w, s, (b.w * b.w) * fma(m2f, ccf, m2t * cct));
-          // d2L/dv_f dtheta_f and d2L/dv_t dtheta_t
-          const double beta_f =
-              fma(b.vt, r, -(2.0 * m2f) * (b.vf * b.w) * fma(b.gff, b.cQ, b.bff * b.cP));
-          const double beta_t =
-              -fma(b.vf, r, (2.0 * m2t) * (b.vt * b.w) * fma(b.gtt, b.cQt, b.btt * b.cPt));
-          const double pff = b.Pf_f(), qff = b.Qf_f(), ptt = b.Pt_t(), qtt = b.Qt_t();
-          const double vv_ff = fma(2.0, fma(oPf, b.gff, -(oQf * b.bff)),
-                                   fma(m2f, fma(pff, pff, qff * qff), m2t * (b.vt * b.vt) * cct));
-          const double vv_tt = fma(2.0, fma(oPt, b.gtt, -(oQt * b.btt)),
-                                   fma(m2f * (b.vf * b.vf), ccf, m2t * fma(ptt, ptt, qtt * qtt)));
-          const double vv_ft =
-              s + fma(m2f * b.vf, fma(2.0 * b.vf, fma(b.gff, b.cP, -(b.bff * b.cQ)), b.vt * ccf),
-                      m2t * b.vt * fma(2.0 * b.vt, fma(b.gtt, b.cPt, -(b.btt * b.cQt)), b.vf * cct));
-          if constexpr (R::H) {
-            if (sf != kNoSlot) {
-              rec[(R::oH + 0) * BE + sf] = a;
-              rec[(R::oH + 1) * BE + sf] = beta_f;
-              rec[(R::oH + 2) * BE + sf] = vv_ff;
-            }
-            if (st != kNoSlot) {
-              rec[(R::oH + 0) * BE + st] = a;
-              rec[(R::oH + 1) * BE + st] = beta_t;
-              rec[(R::oH + 2) * BE + st] = vv_tt;
-            }
-            // d/dtheta_t = -d/dtheta_f
-            hv4[0] = -a;
-            hv4[1] = fwd ? -beta_f : -beta_t;
-            hv4[2] = fwd ? -beta_t : -beta_f;
-            hv4[3] = vv_ft;
+        if constexpr (pJ) {
+          if (sf != kNoSlot) {
+            rec[(R::oJ + 0) * BE + sf] = b.Pf_a();
+            rec[(R::oJ + 1) * BE + sf] = b.Pf_f();
+            rec[(R::oJ + 2) * BE + sf] = b.Qf_a();
+            rec[(R::oJ + 3) * BE + sf] = b.Qf_f();
           }
-          if constexpr (R::HV) {
-            // the branch's 4x4 block on (theta_f, theta_t, v_f, v_t) times d:
-            // theta rows +-(a da + beta_f d_vf - beta_t d_vt), v rows below
-            const double da = dir[f] - dir[t], dvf = dir[nb + f], dvt = dir[nb + t];
-            const double h_a = fma(a, da, fma(beta_f, dvf, -(beta_t * dvt)));
-            if (sf != kNoSlot) {
-              rec[(R::oHV + 0) * BE + sf] = h_a;
-              rec[(R::oHV + 1) * BE + sf] = fma(beta_f, da, fma(vv_ff, dvf, vv_ft * dvt));
-            }
-            if (st != kNoSlot) {
-              rec[(R::oHV + 0) * BE + st] = -h_a;
-              rec[(R::oHV + 1) * BE + st] = fma(-beta_t, da, fma(vv_ft, dvf, vv_tt * dvt));
-            }
+          if (st != kNoSlot) {  // to end: d/dtheta_t = -d/dtheta_f
+            rec[(R::oJ + 0) * BE + st] = -b.Pt_a();
+            rec[(R::oJ + 1) * BE + st] = b.Pt_t();
+            rec[(R::oJ + 2) * BE + st] = -b.Qt_a();
+            rec[(R::oJ + 3) * BE + st] = b.Qt_t();
+          }
+        }
+        if constexpr (pJV) {  // J d: first derivatives along the direction
+          const double da = dir[f] - dir[t], dvf = dir[nb + f], dvt = dir[nb + t];
+          const double jPf = fma(b.Pf_a(), da, fma(b.Pf_f(), dvf, b.Pf_t() * dvt));
+          const double jQf = fma(b.Qf_a(), da, fma(b.Qf_f(), dvf, b.Qf_t() * dvt));
+          const double jPt = fma(b.Pt_a(), da, fma(b.Pt_f(), dvf, b.Pt_t() * dvt));
+          const double jQt = fma(b.Qt_a(), da, fma(b.Qt_f(), dvf, b.Qt_t() * dvt));
+          if (sf != kNoSlot) {
+            rec[(R::oJV + 0) * BE + sf] = jPf;
+            rec[(R::oJV + 1) * BE + sf] = jQf;
+            double* o = B.out + I.co + 2 * nb;
+            o[lp] = 2.0 * fma(b.Pf, jPf, b.Qf * jQf);
+            o[nll + lp] = 2.0 * fma(b.Pt, jPt, b.Qt * jQt);
+          }
+          if (st != kNoSlot) {
+            rec[(R::oJV + 0) * BE + st] = jPt;
+            rec[(R::oJV + 1) * BE + st] = jQt;
+          }
+        }
+        if ((pC || pJ) && sf != kNoSlot) {  // the from-bus owner writes the flow-limit rows
+          if (cflow) {
+            cflow[lp] = fma(b.Pf, b.Pf, b.Qf * b.Qf);
+            cflow[nll + lp] = fma(b.Pt, b.Pt, b.Qt * b.Qt);
+          }
+          if (jflow) {
+            const double hf_a = 2.0 * fma(b.Pf, b.Pf_a(), b.Qf * b.Qf_a());
+            const double hf_f = 2.0 * fma(b.Pf, b.Pf_f(), b.Qf * b.Qf_f());
+            const double hf_t = 2.0 * fma(b.Pf, b.Pf_t(), b.Qf * b.Qf_t());
+            const double ht_a = 2.0 * fma(b.Pt, b.Pt_a(), b.Qt * b.Qt_a());
+            const double ht_f = 2.0 * fma(b.Pt, b.Pt_f(), b.Qt * b.Qt_f());
+            const double ht_t = 2.0 * fma(b.Pt, b.Pt_t(), b.Qt * b.Qt_t());
+            double* rf = jflow + 4 * lp;
+            double* rt = jflow + 4 * nll + 4 * lp;
+            rf[0] = fwd ? hf_a : -hf_a;  // columns ascend: theta_lo, theta_hi, v_lo, v_hi
+            rf[1] = fwd ? -hf_a : hf_a;
+            rf[2] = fwd ? hf_f : hf_t;
+            rf[3] = fwd ? hf_t : hf_f;
+            rt[0] = fwd ? ht_a : -ht_a;
+            rt[1] = fwd ? -ht_a : ht_a;
+            rt[2] = fwd ? ht_f : ht_t;
+            rt[3] = fwd ? ht_t : ht_f;
           }
         }
       }
-      if constexpr (R::H) {
-        if (gmax > 1) group_sum(hv4, wi.grp, gmax);
-        if (wi.grp > 0) {
-          if (wi.jlo >= 0) stg[sV + wi.hvlo] = hv4[1];
+      if constexpr (pJ) {
+        // rows of the lower (lo) and higher (hi) end bus, columns of the other:
+        // d/dtheta and d/dv of P, then of Q
+        double jv[8];
+        if (live) {
+          const double fP = -b.Pf_a(), fPv = b.Pf_t(), fQ = -b.Qf_a(), fQv = b.Qf_t();
+          const double tP = b.Pt_a(), tPv = b.Pt_f(), tQ = b.Qt_a(), tQv = b.Qt_f();
+          jv[0] = fwd ? fP : tP;
+          jv[1] = fwd ? fPv : tPv;
+          jv[2] = fwd ? fQ : tQ;
+          jv[3] = fwd ? fQv : tQv;
+          jv[4] = fwd ? tP : fP;
+          jv[5] = fwd ? tPv : fPv;
+          jv[6] = fwd ? tQ : fQ;
+          jv[7] = fwd ? tQv : fQv;
+        } else {
+  #pragma unroll
+          for (int q = 0; q < 8; ++q) jv[q] = 0.0;
+        }
+        if (gmax > 1) group_sum(jv, wi.grp, gmax);
+        if (wi.grp > 0) {  // (entries of a removed branch without a twin are never stored)
+          if (wi.jlo >= 0) {
+            stg[sP + wi.jlo] = jv[0];
+            stg[sP + wi.jlo + wi.alo] = jv[1];
+            stg[sQ + wi.jlo] = jv[2];
+            stg[sQ + wi.jlo + wi.alo] = jv[3];
+          }
           if (wi.jhi >= 0) {
-            stg[sT + wi.hthi] = hv4[0];
-            stg[sV + wi.hvhi] = hv4[2];
-            stg[sV + wi.hvhi + wi.ahi] = hv4[3];
+            stg[sP + wi.jhi] = jv[4];
+            stg[sP + wi.jhi + wi.ahi] = jv[5];
+            stg[sQ + wi.jhi] = jv[6];
+            stg[sQ + wi.jhi + wi.ahi] = jv[7];
+          }
+        }
+      }
+      if constexpr (pH || pV || pHV) {
+        // (theta_hi, theta_lo), (v_lo, theta_hi), (v_hi, theta_lo), (v_hi, v_lo)
+        double hv4[4] = {0.0, 0.0, 0.0, 0.0};
+        if (live && hneed) {  // the full variant reads multipliers only when H is wanted
+          const double mf = mul[2 * nb + lp];
+          const double mt = mul[2 * nb + nll + lp];
+          // weights of dP, dQ in  lP P + lQ Q + mu (P^2 + Q^2)
+          const double oPf = fma(2.0 * mf, b.Pf, mul[f]);
+          const double oQf = fma(2.0 * mf, b.Qf, mul[nb + f]);
+          const double oPt = fma(2.0 * mt, b.Pt, mul[t]);
+          const double oQt = fma(2.0 * mt, b.Qt, mul[nb + t]);
+          // s, r: the weighted transfer terms; every second derivative and the
+          // VJP are short expressions in them (the Gauss-Newton cross terms
+          // Pt_f Pt_a + Qt_f Qt_a and Pf_t Pf_a + Qf_t Qf_a vanish identically)
+          const double s = fma(oPf, b.cP, fma(oQf, b.cQ, fma(oPt, b.cPt, oQt * b.cQt)));
+          const double r = fma(oQf, b.cP, fma(-oPf, b.cQ, fma(oPt, b.cQt, -(oQt * b.cPt))));
+          if constexpr (pV) {
+            const double u_a = b.w * r;  // d/dtheta_f; d/dtheta_t = -u_a
+            const double u_f = fma(2.0 * b.vf, fma(oPf, b.gff, -(oQf * b.bff)), b.vt * s);
+            const double u_t = fma(2.0 * b.vt, fma(oPt, b.gtt, -(oQt * b.btt)), b.vf * s);
+            if (sf != kNoSlot) {
+              rec[(R::oV + 0) * BE + sf] = u_a;
+              rec[(R::oV + 1) * BE + sf] = u_f;
+            }
+            if (st != kNoSlot) {
+              rec[(R::oV + 0) * BE + st] = -u_a;
+              rec[(R::oV + 1) * BE + st] = u_t;
+            }
+          }
+          if constexpr (pH || pHV) {
+            const double m2f = 2.0 * mf, m2t = 2.0 * mt;
+            const double ccf = fma(b.cP, b.cP, b.cQ * b.cQ), cct = fma(b.cPt, b.cPt, b.cQt * b.cQt);
+            // d2L/dtheta_f^2
+            const double a = fma(-b.w, s, (b.w * b.w) * fma(m2f, ccf, m2t * cct));
+            // d2L/dv_f dtheta_f and d2L/dv_t dtheta_t
+            const double beta_f =
+                fma(b.vt, r, -(2.0 * m2f) * (b.vf * b.w) * fma(b.gff, b.cQ, b.bff * b.cP));
+            const double beta_t =
+                -fma(b.vf, r, (2.0 * m2t) * (b.vt * b.w) * fma(b.gtt, b.cQt, b.btt * b.cPt));
+            const double pff = b.Pf_f(), qff = b.Qf_f(), ptt = b.Pt_t(), qtt = b.Qt_t();
+            const double vv_ff = fma(2.0, fma(oPf, b.gff, -(oQf * b.bff)),
+                                     fma(m2f, fma(pff, pff, qff * qff), m2t * (b.vt * b.vt) * cct));
+            const double vv_tt = fma(2.0, fma(oPt, b.gtt, -(oQt * b.btt)),
+                                     fma(m2f * (b.vf * b.vf), ccf, m2t * fma(ptt, ptt, qtt * qtt)));
+            const double vv_ft =
+                s + fma(m2f * b.vf, fma(2.0 * b.vf, fma(b.gff, b.cP, -(b.bff * b.cQ)), b.vt * ccf),
+                        m2t * b.vt * fma(2.0 * b.vt, fma(b.gtt, b.cPt, -(b.btt * b.cQt)), b.vf * cct));
+            if constexpr (pH) {
+              if (sf != kNoSlot) {
+                rec[(R::oH + 0) * BE + sf] = a;
+                rec[(R::oH + 1) * BE + sf] = beta_f;
+                rec[(R::oH + 2) * BE + sf] = vv_ff;
+              }
+              if (st != kNoSlot) {
+                rec[(R::oH + 0) * BE + st] = a;
+                rec[(R::oH + 1) * BE + st] = beta_t;
+                rec[(R::oH + 2) * BE + st] = vv_tt;
+              }
+              // d/dtheta_t = -d/dtheta_f
+              hv4[0] = -a;
+              hv4[1] = fwd ? -beta_f : -beta_t;
+              hv4[2] = fwd ? -beta_t : -beta_f;
+              hv4[3] = vv_ft;
+            }
+            if constexpr (pHV) {
+              // the branch's 4x4 block on (theta_f, theta_t, v_f, v_t) times d:
+              // theta rows +-(a da + beta_f d_vf - beta_t d_vt), v rows below
+              const double da = dir[f] - dir[t], dvf = dir[nb + f], dvt = dir[nb + t];
+              const double h_a = fma(a, da, fma(beta_f, dvf, -(beta_t * dvt)));
+              if (sf != kNoSlot) {
+                rec[(R::oHV + 0) * BE + sf] = h_a;
+                rec[(R::oHV + 1) * BE + sf] = fma(beta_f, da, fma(vv_ff, dvf, vv_ft * dvt));
+              }
+              if (st != kNoSlot) {
+                rec[(R::oHV + 0) * BE + st] = -h_a;
+                rec[(R::oHV + 1) * BE + st] = fma(-beta_t, da, fma(vv_ft, dvf, vv_tt * dvt));
+              }
+            }
+          }
+        }
+        if constexpr (pH) {
+          if (gmax > 1) group_sum(hv4, wi.grp, gmax);
+          if (wi.grp > 0) {
+            if (wi.jlo >= 0) stg[sV + wi.hvlo] = hv4[1];
+            if (wi.jhi >= 0) {
+              stg[sT + wi.hthi] = hv4[0];
+              stg[sV + wi.hvhi] = hv4[2];
+              stg[sV + wi.hvhi + wi.ahi] = hv4[3];
+            }
           }
         }
       }
     }
+  };
+  if constexpr (R::H && (R::C || R::J)) {
+    branch_pass(std::integral_constant<unsigned, WHAT & ~W_H>{});
+    branch_pass(std::integral_constant<unsigned, W_H>{});
+  } else {
+    branch_pass(std::integral_constant<unsigned, WHAT>{});
   }
 
   // ---- phase A (2): lane per bus, the bus's own terms (kept in registers
