@@ -51,6 +51,11 @@
 namespace acopf {
 namespace {
 
+// Every output is written once and never read back by these kernels: stream
+// it past the caches (a non-temporal store) so that x, the multipliers and
+// the network data stay resident in L2.
+__device__ __forceinline__ void put(double* p, double v) { __builtin_nontemporal_store(v, p); }
+
 // ---------------------------------------------------------------------------
 // one branch: both end flows; first derivatives with respect to
 // (theta_f, v_f, v_t) are formed where they are used (members below)
@@ -288,8 +293,8 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
             rec[(R::oJV + 0) * BE + sf] = jPf;
             rec[(R::oJV + 1) * BE + sf] = jQf;
             double* o = B.out + I.co + 2 * nb;
-            o[lp] = 2.0 * fma(b.Pf, jPf, b.Qf * jQf);
-            o[nll + lp] = 2.0 * fma(b.Pt, jPt, b.Qt * jQt);
+            put(&o[lp], 2.0 * fma(b.Pf, jPf, b.Qf * jQf));
+            put(&o[nll + lp], 2.0 * fma(b.Pt, jPt, b.Qt * jQt));
           }
           if (st != kNoSlot) {
             rec[(R::oJV + 0) * BE + st] = jPt;
@@ -298,8 +303,8 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
         }
         if ((pC || pJ) && sf != kNoSlot) {  // the from-bus owner writes the flow-limit rows
           if (cflow) {
-            cflow[lp] = fma(b.Pf, b.Pf, b.Qf * b.Qf);
-            cflow[nll + lp] = fma(b.Pt, b.Pt, b.Qt * b.Qt);
+            put(&cflow[lp], fma(b.Pf, b.Pf, b.Qf * b.Qf));
+            put(&cflow[nll + lp], fma(b.Pt, b.Pt, b.Qt * b.Qt));
           }
           if (jflow) {
             const double hf_a = 2.0 * fma(b.Pf, b.Pf_a(), b.Qf * b.Qf_a());
@@ -310,14 +315,14 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
             const double ht_t = 2.0 * fma(b.Pt, b.Pt_t(), b.Qt * b.Qt_t());
             double* rf = jflow + 4 * lp;
             double* rt = jflow + 4 * nll + 4 * lp;
-            rf[0] = fwd ? hf_a : -hf_a;  // columns ascend: theta_lo, theta_hi, v_lo, v_hi
-            rf[1] = fwd ? -hf_a : hf_a;
-            rf[2] = fwd ? hf_f : hf_t;
-            rf[3] = fwd ? hf_t : hf_f;
-            rt[0] = fwd ? ht_a : -ht_a;
-            rt[1] = fwd ? -ht_a : ht_a;
-            rt[2] = fwd ? ht_f : ht_t;
-            rt[3] = fwd ? ht_t : ht_f;
+            put(&rf[0], fwd ? hf_a : -hf_a);  // columns ascend: theta_lo, theta_hi, v_lo, v_hi
+            put(&rf[1], fwd ? -hf_a : hf_a);
+            put(&rf[2], fwd ? hf_f : hf_t);
+            put(&rf[3], fwd ? hf_t : hf_f);
+            put(&rt[0], fwd ? ht_a : -ht_a);
+            put(&rt[1], fwd ? -ht_a : ht_a);
+            put(&rt[2], fwd ? ht_f : ht_t);
+            put(&rt[3], fwd ? ht_t : ht_f);
           }
         }
       }
@@ -526,15 +531,15 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
         sp += rec[(R::oC + 0) * BE + e];
         sq += rec[(R::oC + 1) * BE + e];
       }
-      c[i] = sp + cbP;
-      c[nb + i] = sq + cbQ;
+      put(&c[i], sp + cbP);
+      put(&c[nb + i], sq + cbQ);
     }
   }
   if constexpr (DO_GF) {
     if (B.gradf) {
       double* gradf = B.gradf + I.xo;
-      gradf[i] = 0.0;
-      gradf[nb + i] = 0.0;
+      put(&gradf[i], 0.0);
+      put(&gradf[nb + i], 0.0);
     }
   }
   if constexpr (R::J) {
@@ -579,8 +584,8 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       uv += rec[(R::oV + 1) * BE + e];
     }
     double* u = B.u + I.xo;
-    u[i] = ut;
-    u[nb + i] = uv + vb;
+    put(&u[i], ut);
+    put(&u[nb + i], uv + vb);
   }
   if constexpr (R::HV) {
     double ht = 0.0, hv = 0.0;
@@ -589,8 +594,8 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       hv += rec[(R::oHV + 1) * BE + e];
     }
     double* o = B.out + I.xo;
-    o[i] = ht;
-    o[nb + i] = hv + hvb;
+    put(&o[i], ht);
+    put(&o[nb + i], hv + hvb);
   }
   if constexpr (R::JV) {
     double jp = 0.0, jq = 0.0;
@@ -599,8 +604,8 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       jq += rec[(R::oJV + 1) * BE + e];
     }
     double* o = B.out + I.co;
-    o[i] = jp + jvP;
-    o[nb + i] = jq + jvQ;
+    put(&o[i], jp + jvP);
+    put(&o[nb + i], jq + jvQ);
   }
   }
 
@@ -617,7 +622,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
           const bool q = k >= T.nP;
           const int gp = q ? T.jQ0 + (k - T.nP) : T.jP0 + k;
           const int p = rm ? place(gp, q ? shQ : shP, I.rj) : gp;
-          if (p >= 0) jac[p] = stg[k];
+          if (p >= 0) put(&jac[p], stg[k]);
         }
       }
     }
@@ -627,7 +632,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
           const bool v = k >= T.nT;
           const int gp = v ? T.hV0 + (k - T.nT) : T.hT0 + k;
           const int p = rm ? place(gp, v ? shV : shT, I.rh) : gp;
-          if (p >= 0) hess[p] = stg[h0 + k];
+          if (p >= 0) put(&hess[p], stg[h0 + k]);
         }
       }
     }
@@ -665,20 +670,20 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
       const double p = Bm * pg;
       const double grad = Bm * fma(2.0 * c2, p, c1);
       if (gradf) {
-        gradf[2 * nb + k] = grad;
-        gradf[2 * nb + ng + k] = 0.0;
+        put(&gradf[2 * nb + k], grad);
+        put(&gradf[2 * nb + ng + k], 0.0);
       }
-      if (hess) hess[hpg + k] = sigma * (2.0 * c2 * Bm * Bm);
+      if (hess) put(&hess[hpg + k], sigma * (2.0 * c2 * Bm * Bm));
       if constexpr (DO_V) {
         const double* w = B.wc + I.co;
         const int bus = N.gen_bus[k];
-        B.u[I.xo + 2 * nb + k] = fma(wf, grad, -w[bus]);
-        B.u[I.xo + 2 * nb + ng + k] = -w[nb + bus];
+        put(&B.u[I.xo + 2 * nb + k], fma(wf, grad, -w[bus]));
+        put(&B.u[I.xo + 2 * nb + ng + k], -w[nb + bus]);
       }
       if constexpr (DO_HV) {
         double* o = B.out + I.xo;
-        o[2 * nb + k] = sigma * (2.0 * c2 * Bm * Bm) * B.dir[I.xo + 2 * nb + k];
-        o[2 * nb + ng + k] = 0.0;
+        put(&o[2 * nb + k], sigma * (2.0 * c2 * Bm * Bm) * B.dir[I.xo + 2 * nb + k]);
+        put(&o[2 * nb + ng + k], 0.0);
       }
       if (fout) term = fma(fma(c2, p, c1), p, N.gen_c0[k]);
     }
@@ -706,7 +711,7 @@ __global__ __launch_bounds__(256) void k_fsum(const InstOff* __restrict__ table,
   const int nch = I.net->nchunks;
   double s = 0.0;
   for (int ch = 0; ch < nch; ++ch) s += fpart[I.fpo + ch];
-  f[I.k] = s;
+  put(&f[I.k], s);
 }
 
 // ---------------------------------------------------------------------------
