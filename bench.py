@@ -175,6 +175,9 @@ def main():
     ap.add_argument("--grid-mult", type=int, default=-1)
     ap.add_argument("--xcd", type=int, default=-1)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every schedule on this workload's batch, cache the fastest "
+                         "(paper_2203_10587_amd/tune.py; $ACOPF_TUNE_CACHE overrides the file) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB five times (the "
                          "reference kernel for scaling HBM traffic counters)")
@@ -235,6 +238,22 @@ def main():
         nets = [A.acopf_net_create_outage(base, int(l)) for l in w["outages"]]
     else:
         nets = [A.acopf_net_create(g) for g in w["grids"]]
+    if args.autotune:
+        ts = torch.empty(K, dtype=torch.float64)
+        bx = A.acopf_batch_create(nets, **tune.DEFAULT)
+        nx_, nc_ = int(bx.x_off[-1]), int(bx.c_off[-1])
+        xt, lt = torch.empty(nx_, dtype=torch.float64), torch.empty(nc_, dtype=torch.float64)
+        for k, it in enumerate(w["iterates"]):
+            xt[bx.x_off[k]:bx.x_off[k + 1]] = torch.from_numpy(it.x)
+            lt[bx.c_off[k]:bx.c_off[k + 1]] = torch.from_numpy(it.lam)
+            ts[k] = it.sigma
+        outs = [torch.empty(n, dtype=torch.float64, device=dev)
+                for n in (K, nx_, nc_, int(bx.j_off[-1]), int(bx.h_off[-1]))]
+        bx.close()
+        best = tune.autotune(nets, xt.to(dev), ts.to(dev), lt.to(dev), outs, reps=20)
+        print(json.dumps({"autotune": best, "bucket": tune.bucket(nets),
+                          "cache": tune.cache_path()}), flush=True)
+        return
     sched = tune.lookup_or_default(nets)
     if args.tile_be:
         sched["tile_be"] = args.tile_be
