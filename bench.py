@@ -306,6 +306,33 @@ def main():
     log(f"[bench] batched: {total_ms / args.steps:.4f} ms/step, {value:.4e} bus-evals/s "
         f"(wall {wall:.3f}s)")
 
+    # coupling rows over the same batch: a contingency star joining every
+    # other instance to instance 0 (Pg of each generator), values and the
+    # Jacobian's +-1 entries, timed like the batched step
+    coupled = None
+    if K > 1:
+        cp = A.acopf_couple_create(batch, list(range(1, K)), [0] * (K - 1))
+        cc = torch.empty(cp.rows, dtype=torch.float64, device=dev)
+        cj = torch.empty(cp.nnz, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            A.acopf_couple_eval(cp, x, cc, cj, stream)
+        cs_, ce_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        cs_.record(stream)
+        for _ in range(args.steps):
+            A.acopf_couple_eval(cp, x, cc, cj, stream)
+        ce_.record(stream)
+        torch.cuda.synchronize()
+        cms = cs_.elapsed_time(ce_) / args.steps
+        cbytes = 40 * cp.rows  # reads 2 x 8 B of x, writes 8 B of c and 2 x 8 B of J per row
+        coupled = {"links": K - 1, "rows": cp.rows, "ms": cms,
+                   "rows_per_s": cp.rows / (cms / 1e3),
+                   "achieved_GBps": cbytes / (cms / 1e3) / 1e9,
+                   "frac": cbytes / (cms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                   "algorithmic_bytes": cbytes}
+        log(f"[bench] coupled: {cp.rows} rows in {cms * 1e3:.1f} us")
+        cp.close()
+
     # plain path: the same kernels, one instance per launch, into the same buffers
     L = A.lib()
     import ctypes as C
@@ -363,6 +390,7 @@ def main():
                    "outputs": "f, grad_f, c, J, H", "schedule": sched},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "plain": plain,
+        "coupled": coupled,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": alg, "kernel_ms": avg_ms},

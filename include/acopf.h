@@ -265,6 +265,51 @@ int acopf_batch_draw_iterates(acopf_batch batch, int32_t first, int32_t count,
                               const uint64_t* seeds, double pmin, double pmax, double qmin,
                               double qmax, double* x, double* lambda, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Coupling rows between instances of a batch (paper: SCOPFLOW, TCOPFLOW and
+ * SOPFLOW sections -- the contingency, time and scenario coupling
+ * constraints  -delta <= x_a - x_b <= delta  that join subproblems into one
+ * block-structured NLP; here on generator real power, the paper's example of
+ * such a coupling).  Link l joins instance child[l] to instance parent[l]
+ * (a contingency to its base case, a period to the one before it, a
+ * scenario to the base).  Its row block holds, for each generator k in
+ * order, the row  Pg_k(child) - Pg_k(parent); blocks follow the links'
+ * order.  The bounds +-delta belong to the solver; the rows are linear, so
+ * they add nothing to H.  With the batch's per-instance blocks, the coupled
+ * problem's constraints are [c_0; ...; c_{K-1}; rows] over x = the packed x.
+ * ---------------------------------------------------------------------- */
+
+typedef struct acopf_couple_s* acopf_couple;
+
+/* child, parent: HOST arrays of nlinks instance indices of `batch` (which
+ * must outlive the coupling).  Errors: EINVAL (index out of range, a link
+ * joining an instance to itself, different generator counts), ENOMEM, EHIP. */
+int acopf_couple_create(acopf_batch batch, const int32_t* child, const int32_t* parent,
+                        int32_t nlinks, acopf_couple* out);
+int acopf_couple_destroy(acopf_couple cp);
+
+/* Number of coupling rows and of their Jacobian nonzeros (two per row). */
+int acopf_couple_dims(acopf_couple cp, int64_t* rows, int64_t* nnz);
+
+/* CSR pattern of the rows over the batch's packed x (HOST arrays: rowptr of
+ * rows + 1 entries, col of nnz entries; columns ascending in each row). */
+int acopf_couple_pattern(acopf_couple cp, int64_t* rowptr, int64_t* col);
+
+/* Row values c[r] = x[child column] - x[parent column] and the Jacobian
+ * values (+1 / -1 in pattern order).  DEVICE pointers; c or jac_val may be
+ * NULL.  Errors: EINVAL, EHIP. */
+int acopf_couple_eval(acopf_couple cp, const double* x, double* c, double* jac_val,
+                      hipStream_t stream);
+
+/* u += J' w for the coupling rows: w has one entry per row, u is packed
+ * like x and keeps what it holds (add the batch's own VJP first).  Each
+ * entry of u is updated by one thread, adding its rows in row order.  DEVICE
+ * pointers.  Errors: EINVAL, EHIP. */
+int acopf_couple_vjp(acopf_couple cp, const double* w, double* u, hipStream_t stream);
+
+/* out = J d for the coupling rows (out: one entry per row; DEVICE). */
+int acopf_couple_jvp(acopf_couple cp, const double* d, double* out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

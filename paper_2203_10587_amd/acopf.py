@@ -89,6 +89,13 @@ _SIGS = {
                                + [C.c_uint, C.c_void_p]),
     "acopf_batch_draw_iterates": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
                                   + [C.c_double] * 4 + [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "acopf_couple_create": (C.c_int, [C.c_void_p, _i32p, _i32p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "acopf_couple_destroy": (C.c_int, [C.c_void_p]),
+    "acopf_couple_dims": (C.c_int, [C.c_void_p, _i64p, _i64p]),
+    "acopf_couple_pattern": (C.c_int, [C.c_void_p, _i64p, _i64p]),
+    "acopf_couple_eval": (C.c_int, [C.c_void_p] * 5),
+    "acopf_couple_vjp": (C.c_int, [C.c_void_p] * 4),
+    "acopf_couple_jvp": (C.c_int, [C.c_void_p] * 4),
 }
 
 
@@ -397,3 +404,69 @@ def acopf_batch_jvp(b: Batch, x, d, out, stream=None):
     nx, nc = int(b.x_off[-1]), int(b.c_off[-1])
     _check(lib().acopf_batch_jvp(b.handle, _ptr(x, nx, "x"), _ptr(d, nx, "d"), _ptr(out, nc, "out"),
                                  _stream(stream)))
+
+
+class Couple:
+    """Owner of an acopf_couple handle; keeps its batch alive."""
+
+    def __init__(self, handle, batch: Batch, child, parent):
+        self.handle = handle
+        self.batch = batch
+        self.child = np.asarray(child, np.int32)
+        self.parent = np.asarray(parent, np.int32)
+        rows, nnz = C.c_int64(), C.c_int64()
+        _check(lib().acopf_couple_dims(handle, C.byref(rows), C.byref(nnz)))
+        self.rows, self.nnz = int(rows.value), int(nnz.value)
+
+    def close(self):
+        if self.handle:
+            _check(lib().acopf_couple_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().acopf_couple_destroy(self.handle)
+        except Exception:
+            pass
+
+
+def acopf_couple_create(batch: Batch, child: Sequence[int], parent: Sequence[int]) -> Couple:
+    ch = np.ascontiguousarray(child, dtype=np.int32)
+    pa = np.ascontiguousarray(parent, dtype=np.int32)
+    if ch.shape != pa.shape or ch.ndim != 1:
+        raise ValueError("child and parent must be 1-D arrays of equal length")
+    h = C.c_void_p()
+    _check(lib().acopf_couple_create(batch.handle, ch.ctypes.data_as(_i32p),
+                                     pa.ctypes.data_as(_i32p), len(ch), C.byref(h)))
+    return Couple(h, batch, ch, pa)
+
+
+def acopf_couple_destroy(cp: Couple):
+    cp.close()
+
+
+def acopf_couple_pattern(cp: Couple):
+    """(rowptr, col) of the coupling rows over the packed x, int64 numpy."""
+    rp = np.empty(cp.rows + 1, np.int64)
+    col = np.empty(max(cp.nnz, 1), np.int64)
+    _check(lib().acopf_couple_pattern(cp.handle, rp.ctypes.data_as(_i64p), col.ctypes.data_as(_i64p)))
+    return rp, col[:cp.nnz]
+
+
+def acopf_couple_eval(cp: Couple, x, c, jac_val, stream=None):
+    nx = int(cp.batch.x_off[-1])
+    _check(lib().acopf_couple_eval(cp.handle, _ptr(x, nx, "x"), _ptr(c, cp.rows, "c"),
+                                   _ptr(jac_val, cp.nnz, "jac_val"), _stream(stream)))
+
+
+def acopf_couple_vjp(cp: Couple, w, u, stream=None):
+    nx = int(cp.batch.x_off[-1])
+    _check(lib().acopf_couple_vjp(cp.handle, _ptr(w, cp.rows, "w"), _ptr(u, nx, "u"),
+                                  _stream(stream)))
+
+
+def acopf_couple_jvp(cp: Couple, d, out, stream=None):
+    nx = int(cp.batch.x_off[-1])
+    _check(lib().acopf_couple_jvp(cp.handle, _ptr(d, nx, "d"), _ptr(out, cp.rows, "out"),
+                                  _stream(stream)))

@@ -10,7 +10,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libacopf.so")
-SOURCES = ["acopf_host.cpp", "acopf_batch.cpp", "acopf_kernels.hip", "acopf_rng.hip"]
+SOURCES = ["acopf_host.cpp", "acopf_batch.cpp", "acopf_kernels.hip", "acopf_rng.hip",
+           "acopf_couple.hip"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [

@@ -10,6 +10,7 @@
 //   - a small cache of instantiated HIP graphs keyed by the buffer set.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstring>
 #include <list>
 #include <map>
@@ -49,6 +50,21 @@ struct acopf_batch_s {
   int max_len = 0;                      // max n + m over instances
   hipStream_t cap_stream = nullptr;
   std::list<std::pair<acopf::GraphKey, hipGraphExec_t>> graphs;  // most recent first
+  std::atomic<int> refs{0};             // couplings built on this batch
+};
+
+// Coupling rows over a batch: per row the child and the parent column of the
+// packed x; per coupled column the rows touching it (row << 1 | parent).
+struct acopf_couple_s {
+  acopf_batch batch = nullptr;
+  int64_t rows = 0;
+  std::vector<int64_t> cols;   // 2 per row: child column, parent column
+  int32_t ncols = 0;
+  void* mem = nullptr;
+  int64_t* d_cols = nullptr;
+  int64_t* d_tcol = nullptr;
+  int32_t* d_tptr = nullptr;
+  int32_t* d_tent = nullptr;
 };
 
 using namespace acopf;
@@ -311,6 +327,8 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
 
 int acopf_batch_destroy(acopf_batch batch) {
   if (!batch) return ACOPF_OK;
+  if (batch->refs.load() != 0)
+    return fail(ACOPF_ESTATE, "batch still has couplings; destroy them first");
   free_batch(batch);
   return ACOPF_OK;
 }
@@ -436,6 +454,160 @@ int acopf_batch_vjp(acopf_batch b, const double* x, const double* w_f, const dou
   bufs.u = u;
   bufs.fpart = b->d_fpart;
   return run_batch(b, K_VJP, bufs, stream);
+}
+
+// ---------------------------------------------------------------------------
+// coupling rows
+
+int acopf_couple_create(acopf_batch b, const int32_t* child, const int32_t* parent,
+                        int32_t nlinks, acopf_couple* out) {
+  if (!out) return fail(ACOPF_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!b || nlinks < 0 || (nlinks > 0 && (!child || !parent)))
+    return fail(ACOPF_EINVAL, "null batch or link arrays");
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != b->device) return fail(ACOPF_EINVAL, "batch lives on another device");
+  acopf_couple cp = nullptr;
+  try {
+    cp = new acopf_couple_s;
+    cp->batch = b;
+    for (int32_t l = 0; l < nlinks; ++l) {
+      const int32_t a = child[l], p = parent[l];
+      if (a < 0 || a >= b->count || p < 0 || p >= b->count)
+        return delete cp, fail(ACOPF_EINVAL, "link " + std::to_string(l) + ": instance out of range");
+      if (a == p)
+        return delete cp, fail(ACOPF_EINVAL, "link " + std::to_string(l) + " joins an instance to itself");
+      const acopf_dims &da = b->nets[a]->dims, &dp = b->nets[p]->dims;
+      if (da.ngen != dp.ngen)
+        return delete cp, fail(ACOPF_EINVAL, "link " + std::to_string(l) +
+                                                  ": the instances have different generator counts");
+      // Pg block of x: [theta; v; Pg; Qg]
+      for (int32_t k = 0; k < da.ngen; ++k) {
+        cp->cols.push_back(b->xo[a] + 2 * int64_t(da.nbus) + k);
+        cp->cols.push_back(b->xo[p] + 2 * int64_t(dp.nbus) + k);
+      }
+    }
+    cp->rows = int64_t(cp->cols.size() / 2);
+    if (cp->rows >= (int64_t(1) << 30))
+      return delete cp, fail(ACOPF_EINVAL, "more than 2^30 coupling rows");
+    // the transposed product: rows touching each coupled column, in row order
+    std::vector<std::pair<int64_t, int32_t>> ent;
+    ent.reserve(cp->cols.size());
+    for (int64_t r = 0; r < cp->rows; ++r) {
+      ent.push_back({cp->cols[2 * r], int32_t(r << 1)});
+      ent.push_back({cp->cols[2 * r + 1], int32_t((r << 1) | 1)});
+    }
+    std::sort(ent.begin(), ent.end());
+    std::vector<int64_t> tcol;
+    std::vector<int32_t> tptr, tent;
+    for (size_t q = 0; q < ent.size(); ++q) {
+      if (q == 0 || ent[q].first != ent[q - 1].first) {
+        tcol.push_back(ent[q].first);
+        tptr.push_back(int32_t(q));
+      }
+      tent.push_back(ent[q].second);
+    }
+    tptr.push_back(int32_t(ent.size()));
+    cp->ncols = int32_t(tcol.size());
+    const size_t s_cols = align_up(std::max<size_t>(cp->cols.size(), 1) * sizeof(int64_t));
+    const size_t s_tcol = align_up(std::max<size_t>(tcol.size(), 1) * sizeof(int64_t));
+    const size_t s_tptr = align_up(tptr.size() * sizeof(int32_t));
+    const size_t s_tent = align_up(std::max<size_t>(tent.size(), 1) * sizeof(int32_t));
+    e = hipMalloc(&cp->mem, s_cols + s_tcol + s_tptr + s_tent);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      cp->mem = nullptr;
+      delete cp;
+      return fail(ACOPF_ENOMEM, std::string("hipMalloc of coupling rows: ") + hipGetErrorString(e));
+    }
+    char* base = static_cast<char*>(cp->mem);
+    cp->d_cols = reinterpret_cast<int64_t*>(base);
+    cp->d_tcol = reinterpret_cast<int64_t*>(base + s_cols);
+    cp->d_tptr = reinterpret_cast<int32_t*>(base + s_cols + s_tcol);
+    cp->d_tent = reinterpret_cast<int32_t*>(base + s_cols + s_tcol + s_tptr);
+    if (!cp->cols.empty())
+      e = hipMemcpy(cp->d_cols, cp->cols.data(), cp->cols.size() * sizeof(int64_t),
+                    hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tcol.empty())
+      e = hipMemcpy(cp->d_tcol, tcol.data(), tcol.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(cp->d_tptr, tptr.data(), tptr.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tent.empty())
+      e = hipMemcpy(cp->d_tent, tent.data(), tent.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(cp->mem);
+      delete cp;
+      return hip_fail(e, "coupling upload");
+    }
+  } catch (const std::bad_alloc&) {
+    if (cp) {
+      if (cp->mem) (void)hipFree(cp->mem);
+      delete cp;
+    }
+    return fail(ACOPF_ENOMEM, "host allocation failed");
+  }
+  b->refs.fetch_add(1);
+  *out = cp;
+  t_err.clear();
+  return ACOPF_OK;
+}
+
+int acopf_couple_destroy(acopf_couple cp) {
+  if (!cp) return ACOPF_OK;
+  if (cp->mem) (void)hipFree(cp->mem);
+  cp->batch->refs.fetch_sub(1);
+  delete cp;
+  return ACOPF_OK;
+}
+
+int acopf_couple_dims(acopf_couple cp, int64_t* rows, int64_t* nnz) {
+  if (!cp) return fail(ACOPF_EINVAL, "null coupling");
+  if (rows) *rows = cp->rows;
+  if (nnz) *nnz = 2 * cp->rows;
+  return ACOPF_OK;
+}
+
+int acopf_couple_pattern(acopf_couple cp, int64_t* rowptr, int64_t* col) {
+  if (!cp || !rowptr || !col) return fail(ACOPF_EINVAL, "null coupling or output array");
+  for (int64_t r = 0; r <= cp->rows; ++r) rowptr[r] = 2 * r;
+  for (int64_t r = 0; r < cp->rows; ++r) {
+    const int64_t a = cp->cols[2 * r], p = cp->cols[2 * r + 1];
+    col[2 * r] = std::min(a, p);
+    col[2 * r + 1] = std::max(a, p);
+  }
+  return ACOPF_OK;
+}
+
+static int couple_device(acopf_couple cp) {
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != cp->batch->device) return fail(ACOPF_EINVAL, "coupling lives on another device");
+  return ACOPF_OK;
+}
+
+int acopf_couple_eval(acopf_couple cp, const double* x, double* c, double* jac_val,
+                      hipStream_t stream) {
+  if (!cp || !x) return fail(ACOPF_EINVAL, "null coupling or x");
+  if (int rc = couple_device(cp)) return rc;
+  hipError_t e = launch_couple_rows(cp->d_cols, cp->rows, x, c, jac_val, stream);
+  return e == hipSuccess ? ACOPF_OK : hip_fail(e, "coupling rows launch");
+}
+
+int acopf_couple_vjp(acopf_couple cp, const double* w, double* u, hipStream_t stream) {
+  if (!cp || !w || !u) return fail(ACOPF_EINVAL, "null coupling, w or u");
+  if (int rc = couple_device(cp)) return rc;
+  hipError_t e = launch_couple_vjp(cp->d_tcol, cp->d_tptr, cp->d_tent, cp->ncols, w, u, stream);
+  return e == hipSuccess ? ACOPF_OK : hip_fail(e, "coupling VJP launch");
+}
+
+int acopf_couple_jvp(acopf_couple cp, const double* d, double* out, hipStream_t stream) {
+  if (!cp || !d || !out) return fail(ACOPF_EINVAL, "null coupling, d or out");
+  if (int rc = couple_device(cp)) return rc;
+  hipError_t e = launch_couple_rows(cp->d_cols, cp->rows, d, out, nullptr, stream);
+  return e == hipSuccess ? ACOPF_OK : hip_fail(e, "coupling JVP launch");
 }
 
 }  // extern "C"

@@ -182,4 +182,11 @@ hipError_t launch_draw(const InstOff* table, int first, int count, int max_len,
                        const uint64_t* seeds, double pmin, double pmax, double qmin, double qmax,
                        double* x, double* lam, hipStream_t stream);
 
+// Coupling rows: lane per row (values and +-1 Jacobian entries), and lane
+// per coupled column for u += J' w.
+hipError_t launch_couple_rows(const int64_t* cols, int64_t rows, const double* x, double* c,
+                              double* jac, hipStream_t stream);
+hipError_t launch_couple_vjp(const int64_t* tcol, const int32_t* tptr, const int32_t* tent,
+                             int32_t ncols, const double* w, double* u, hipStream_t stream);
+
 }  // namespace acopf
