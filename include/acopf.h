@@ -108,7 +108,7 @@ typedef struct {
 
 typedef struct {
   int64_t n;         /* variables: 2 nbus + 2 ngen                         */
-  int64_t m;         /* constraints: 2 nbus + 2 (live branches)            */
+  int64_t m;         /* 2 nbus + 2 (live branches) (+ nbus, cartesian)     */
   int64_t nnz_jac;   /* Jacobian pattern entries                           */
   int64_t nnz_hess;  /* lower-Hessian pattern entries                      */
   int32_t nbus, nbranch, ngen;
@@ -148,6 +148,39 @@ int acopf_pattern(acopf_net net, int32_t* jac_rowptr, int32_t* jac_col,
 int acopf_pattern_host(const acopf_net_desc* desc, int32_t outage, acopf_dims* dims,
                        int32_t* jac_rowptr, int32_t* jac_col,
                        int32_t* hess_rowptr, int32_t* hess_col);
+
+/* Representation of the network equations (paper: OPFLOW section, the
+ * formulations it lists beside the polar power balance).
+ *
+ * ACOPF_POLAR (what acopf_net_create builds): everything above.
+ *
+ * ACOPF_CARTESIAN, the power-balance-cartesian form: bus voltages are
+ * V_i = e_i + j f_i, so x = [e (nb); f (nb); Pg (ng); Qg (ng)] and, with
+ * A = e_f e_t + f_f f_t and B = f_f e_t - e_f f_t,
+ *   P_f =  g_ff |V_f|^2 + g_ft A + b_ft B,   Q_f = -b_ff |V_f|^2 + g_ft B - b_ft A,
+ *   P_t =  g_tt |V_t|^2 + g_tf A - b_tf B,   Q_t = -b_tt |V_t|^2 - g_tf B - b_tf A,
+ * with the same admittances as the polar form; the shunt and load terms use
+ * |V_i|^2 = e_i^2 + f_i^2.  c gains nb rows after the flow rows,
+ *   c = [g^P; g^Q; h^f; h^t; e_i^2 + f_i^2 (nb)],   m = 3 nb + 2 nl,
+ * the squared voltage magnitudes that carry the voltage bounds in this form.
+ * Pattern: every polar rule with theta -> e and v -> f, then one J row per
+ * bus with columns e_i, f_i (nnz_jac grows by 2 nb); the H pattern is
+ * unchanged (the magnitude rows add only diagonal entries).  Every entry
+ * point below (single net, N-1 child, batch, products) evaluates both forms;
+ * an N-1 child keeps its base's form; a batch needs one form throughout, and
+ * acopf_batch_draw_iterates serves only the polar one (EINVAL otherwise). */
+enum { ACOPF_POLAR = 0, ACOPF_CARTESIAN = 1 };
+
+/* acopf_net_create in the representation `form` (EINVAL for another value). */
+int acopf_net_create_form(const acopf_net_desc* desc, int32_t form, acopf_net* out);
+
+/* The representation of a net (its base's, for an N-1 child). */
+int acopf_net_form(acopf_net net, int32_t* form);
+
+/* acopf_pattern_host in the representation `form`. */
+int acopf_pattern_host_form(const acopf_net_desc* desc, int32_t form, int32_t outage,
+                            acopf_dims* dims, int32_t* jac_rowptr, int32_t* jac_col,
+                            int32_t* hess_rowptr, int32_t* hess_col);
 
 /* f (1 value), grad_f (n) and c (m) at x (n); DEVICE pointers.  Any output
  * may be NULL to skip it (x may not). */

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(PKG, "libacopf.so")
 
 ACOPF_OK, ACOPF_EINVAL, ACOPF_ENOMEM, ACOPF_EHIP, ACOPF_EBUDGET, ACOPF_ESTATE = 0, -1, -2, -3, -4, -5
 ACOPF_F, ACOPF_GRADF, ACOPF_C, ACOPF_J, ACOPF_H, ACOPF_ALL = 1, 2, 4, 8, 16, 31
+ACOPF_POLAR, ACOPF_CARTESIAN = 0, 1
 
 _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)
@@ -58,12 +59,17 @@ _SIGS = {
     "acopf_last_error": (C.c_char_p, []),
     "acopf_version": (C.c_int, []),
     "acopf_net_create": (C.c_int, [C.POINTER(acopf_net_desc), C.POINTER(C.c_void_p)]),
+    "acopf_net_create_form": (C.c_int, [C.POINTER(acopf_net_desc), C.c_int32,
+                                        C.POINTER(C.c_void_p)]),
+    "acopf_net_form": (C.c_int, [C.c_void_p, _i32p]),
     "acopf_net_create_outage": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "acopf_net_destroy": (C.c_int, [C.c_void_p]),
     "acopf_dims_get": (C.c_int, [C.c_void_p, C.POINTER(acopf_dims)]),
     "acopf_pattern": (C.c_int, [C.c_void_p, _i32p, _i32p, _i32p, _i32p]),
     "acopf_pattern_host": (C.c_int, [C.POINTER(acopf_net_desc), C.c_int32, C.POINTER(acopf_dims),
                                      _i32p, _i32p, _i32p, _i32p]),
+    "acopf_pattern_host_form": (C.c_int, [C.POINTER(acopf_net_desc), C.c_int32, C.c_int32,
+                                          C.POINTER(acopf_dims), _i32p, _i32p, _i32p, _i32p]),
     "acopf_eval_f_g": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p]),
     "acopf_eval_jac": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -222,6 +228,20 @@ def acopf_net_create(grid) -> Net:
     return Net(h, _dims(h))
 
 
+def acopf_net_create_form(grid, form: int) -> Net:
+    """A net in the representation `form` (ACOPF_POLAR or ACOPF_CARTESIAN)."""
+    d = _Desc(grid)
+    h = C.c_void_p()
+    _check(lib().acopf_net_create_form(C.byref(d.desc), int(form), C.byref(h)))
+    return Net(h, _dims(h))
+
+
+def acopf_net_form(net: Net) -> int:
+    out = C.c_int32()
+    _check(lib().acopf_net_form(net.handle, C.byref(out)))
+    return int(out.value)
+
+
 def acopf_net_create_outage(base: Net, branch: int) -> Net:
     h = C.c_void_p()
     _check(lib().acopf_net_create_outage(base.handle, int(branch), C.byref(h)))
@@ -244,17 +264,21 @@ def acopf_pattern(net: Net):
 
 
 def acopf_pattern_host(grid, outage: int = -1):
+    return acopf_pattern_host_form(grid, ACOPF_POLAR, outage)
+
+
+def acopf_pattern_host_form(grid, form: int, outage: int = -1):
     d = _Desc(grid)
     dims = acopf_dims()
-    _check(lib().acopf_pattern_host(C.byref(d.desc), int(outage), C.byref(dims), None, None, None,
-                                    None))
+    _check(lib().acopf_pattern_host_form(C.byref(d.desc), int(form), int(outage), C.byref(dims),
+                                         None, None, None, None))
     jp = np.empty(dims.m + 1, np.int32)
     jc = np.empty(dims.nnz_jac, np.int32)
     hp = np.empty(dims.n + 1, np.int32)
     hc = np.empty(dims.nnz_hess, np.int32)
-    _check(lib().acopf_pattern_host(C.byref(d.desc), int(outage), None,
-                                    jp.ctypes.data_as(_i32p), jc.ctypes.data_as(_i32p),
-                                    hp.ctypes.data_as(_i32p), hc.ctypes.data_as(_i32p)))
+    _check(lib().acopf_pattern_host_form(C.byref(d.desc), int(form), int(outage), None,
+                                         jp.ctypes.data_as(_i32p), jc.ctypes.data_as(_i32p),
+                                         hp.ctypes.data_as(_i32p), hc.ctypes.data_as(_i32p)))
     return dims, jp, jc, hp, hc
 
 

@@ -36,6 +36,7 @@ struct GraphKey {
 struct acopf_batch_s {
   std::vector<acopf_net> nets;
   int32_t count = 0;
+  int32_t form = ACOPF_POLAR;  // shared by every instance
   acopf_sched sched{};
   std::vector<int64_t> xo, co, jo, ho;
   int device = 0;
@@ -111,6 +112,7 @@ hipError_t enqueue(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStre
 }
 
 int run_batch(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStream_t stream) {
+  if (b->form == ACOPF_CARTESIAN) variant |= W_CART;
   int cur = 0;
   hipError_t e = hipGetDevice(&cur);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -183,6 +185,9 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     if (!nets[k]) return fail(ACOPF_EINVAL, "null net at index " + std::to_string(k));
     if (nets[k]->base->device != dev)
       return fail(ACOPF_EINVAL, "net " + std::to_string(k) + " lives on another device");
+    if (nets[k]->base->topo.form != nets[0]->base->topo.form)
+      return fail(ACOPF_EINVAL, "net " + std::to_string(k) +
+                                    " uses another representation than net 0");
   }
   acopf_batch_s* b = nullptr;
   try {
@@ -190,6 +195,7 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     b->nets.assign(nets, nets + count);
     for (acopf_net n : b->nets) n->refs.fetch_add(1);
     b->count = count;
+    b->form = nets[0]->base->topo.form;
     b->sched = s;
     b->device = dev;
     b->xo.assign(count + 1, 0);
@@ -420,7 +426,8 @@ int acopf_batch_eval_range(acopf_batch b, int32_t first, int32_t count, const do
   bufs.fpart = b->d_fpart;
   const int t0 = b->inst_tile_off[first], t1 = b->inst_tile_off[first + count];
   const InstOff none{};
-  e = launch_eval(variant_of(what), b->sched.tile_be, bufs, b->d_table, none, b->d_tiles_inst + t0,
+  const unsigned variant = variant_of(what) | (b->form == ACOPF_CARTESIAN ? W_CART : 0u);
+  e = launch_eval(variant, b->sched.tile_be, bufs, b->d_table, none, b->d_tiles_inst + t0,
                   t1 - t0, 0, stream);
   if (e == hipSuccess && bufs.f) e = launch_fsum(b->d_table, none, first, count, bufs.fpart, bufs.f, stream);
   if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
@@ -434,6 +441,7 @@ int acopf_batch_draw_iterates(acopf_batch b, int32_t first, int32_t count, const
   if (first < 0 || count < 1 || first > b->count - count)
     return fail(ACOPF_EINVAL, "instance window out of range");
   if (count > 65535) return fail(ACOPF_EINVAL, "at most 65535 instances per draw");
+  if (b->form != ACOPF_POLAR) return fail(ACOPF_EINVAL, "iterates are drawn for the polar representation only");
   int cur = 0;
   hipError_t e = hipGetDevice(&cur);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

@@ -195,9 +195,10 @@ int outage_info(const Topology& T, int32_t l, int32_t* p, int32_t* q, int32_t* r
 
 void fill_dims(const Topology& T, int32_t outage, int32_t rm, acopf_dims* d) {
   const int live = T.nl - (outage >= 0 ? 1 : 0);
+  const bool cart = T.form == ACOPF_CARTESIAN;
   d->n = 2 * int64_t(T.nb) + 2 * int64_t(T.ng);
-  d->m = 2 * int64_t(T.nb) + 2 * int64_t(live);
-  d->nnz_jac = T.nnz_jac - (outage >= 0 ? 8 + 8 * rm : 0);
+  d->m = 2 * int64_t(T.nb) + 2 * int64_t(live) + (cart ? T.nb : 0);
+  d->nnz_jac = T.nnz_jac - (outage >= 0 ? 8 + 8 * rm : 0) + (cart ? 2 * int64_t(T.nb) : 0);
   d->nnz_hess = T.nnz_hess - (outage >= 0 ? 4 * rm : 0);
   d->nbus = T.nb;
   d->nbranch = live;
@@ -245,6 +246,13 @@ void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,
       jc->push_back(b);
       jc->push_back(nb + a);
       jc->push_back(nb + b);
+      jp->push_back(int32_t(jc->size()));
+    }
+  }
+  if (T.form == ACOPF_CARTESIAN) {  // magnitude rows e_i^2 + f_i^2: columns e_i, f_i
+    for (int i = 0; i < nb; ++i) {
+      jc->push_back(i);
+      jc->push_back(nb + i);
       jp->push_back(int32_t(jc->size()));
     }
   }
@@ -576,13 +584,26 @@ const char* acopf_last_error(void) { return t_err.c_str(); }
 
 int acopf_version(void) { return 10000; }
 
+static bool form_ok(int32_t form) { return form == ACOPF_POLAR || form == ACOPF_CARTESIAN; }
+
 int acopf_pattern_host(const acopf_net_desc* desc, int32_t outage, acopf_dims* dims,
                        int32_t* jac_rowptr, int32_t* jac_col, int32_t* hess_rowptr,
                        int32_t* hess_col) {
+  return acopf_pattern_host_form(desc, ACOPF_POLAR, outage, dims, jac_rowptr, jac_col,
+                                 hess_rowptr, hess_col);
+}
+
+int acopf_pattern_host_form(const acopf_net_desc* desc, int32_t form, int32_t outage,
+                            acopf_dims* dims, int32_t* jac_rowptr, int32_t* jac_col,
+                            int32_t* hess_rowptr, int32_t* hess_col) {
+  if (!form_ok(form)) return fail(ACOPF_EINVAL, "form must be ACOPF_POLAR or ACOPF_CARTESIAN");
   try {
     Topology T;
     int rc = build_topology(desc, &T);
     if (rc) return rc;
+    T.form = form;
+    if (form == ACOPF_CARTESIAN && 2 * int64_t(T.nb) + T.nnz_jac >= INT_MAX)
+      return fail(ACOPF_EINVAL, "pattern exceeds 2^31 entries");
     int32_t p = -1, q = -1, rm = 0;
     if (outage >= 0) {
       rc = outage_info(T, outage, &p, &q, &rm);
@@ -613,12 +634,20 @@ int acopf_pattern_host(const acopf_net_desc* desc, int32_t outage, acopf_dims* d
 }
 
 int acopf_net_create(const acopf_net_desc* desc, acopf_net* out) {
+  return acopf_net_create_form(desc, ACOPF_POLAR, out);
+}
+
+int acopf_net_create_form(const acopf_net_desc* desc, int32_t form, acopf_net* out) {
   if (!out) return fail(ACOPF_EINVAL, "null output handle");
   *out = nullptr;
+  if (!form_ok(form)) return fail(ACOPF_EINVAL, "form must be ACOPF_POLAR or ACOPF_CARTESIAN");
   try {
     auto B = std::make_shared<Base>();
     int rc = build_topology(desc, &B->topo);
     if (rc) return rc;
+    B->topo.form = form;
+    if (form == ACOPF_CARTESIAN && 2 * int64_t(B->topo.nb) + B->topo.nnz_jac >= INT_MAX)
+      return fail(ACOPF_EINVAL, "pattern exceeds 2^31 entries");
     rc = upload_base(B.get());
     if (rc) return rc;
     std::unique_ptr<acopf_net_s> net(new acopf_net_s());
@@ -680,6 +709,12 @@ int acopf_net_destroy(acopf_net net) {
 int acopf_dims_get(acopf_net net, acopf_dims* out) {
   if (!net || !out) return fail(ACOPF_EINVAL, "null argument");
   *out = net->dims;
+  return ACOPF_OK;
+}
+
+int acopf_net_form(acopf_net net, int32_t* form) {
+  if (!net || !form) return fail(ACOPF_EINVAL, "null argument");
+  *form = net->base->topo.form;
   return ACOPF_OK;
 }
 
@@ -761,6 +796,7 @@ static int run_plain(const acopf_net_s* net, unsigned variant, Bufs b, bool bus,
   const int t0 = bus ? 0 : nbu;
   const int t1 = gen ? nbu + ngt : nbu;
   const InstOff one = net_inst(net);
+  if (B.topo.form == ACOPF_CARTESIAN) variant |= W_CART;
   hipError_t e = launch_eval(variant, kDefaultTileBe, b, nullptr, one, B.d_tiles + t0, t1 - t0, 0, s);
   if (e == hipSuccess && b.f) e = launch_fsum(nullptr, one, 0, 1, b.fpart, b.f, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");

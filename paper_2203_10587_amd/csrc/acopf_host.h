@@ -14,6 +14,7 @@ namespace acopf {
 // Host copy of a base network and everything derived from it.
 struct Topology {
   int32_t nb = 0, nl = 0, ng = 0, nchunks = 1;
+  int32_t form = ACOPF_POLAR;  // ACOPF_POLAR or ACOPF_CARTESIAN
   double base = 100.0;
   std::vector<int2> ft;
   std::vector<BranchY> y;

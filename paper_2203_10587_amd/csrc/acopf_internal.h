@@ -127,6 +127,7 @@ struct Bufs {
 
 enum : unsigned {
   W_F = 1u, W_GRADF = 2u, W_C = 4u, W_J = 8u, W_H = 16u, W_VJP = 32u, W_HVP = 64u, W_JVP = 128u,
+  W_CART = 256u,  // power-balance-cartesian representation (x = [e; f; Pg; Qg])
 };
 
 // Tile capacities of one schedule: workgroup size, branch ends per bus tile

@@ -102,6 +102,71 @@ __device__ __forceinline__ void branch_eval(double thf, double tht, double vf, d
   o.Qt = fma(-y.btt, vt * vt, w * o.cQt);
 }
 
+// ---------------------------------------------------------------------------
+// one branch in the power-balance-cartesian representation: V = e + j f, so
+// with A = e_f e_t + f_f f_t, B = f_f e_t - e_f f_t (the real and imaginary
+// parts of V_f conj(V_t)) the flows are quadratic forms
+//   P_f =  g_ff |V_f|^2 + g_ft A + b_ft B,   Q_f = -b_ff |V_f|^2 + g_ft B - b_ft A
+//   P_t =  g_tt |V_t|^2 + g_tf A - b_tf B,   Q_t = -b_tt |V_t|^2 - g_tf B - b_tf A
+// in the local variables z = (e_f, f_f, e_t, f_t); their gradients below are
+// written out per component K, and their Hessians are constant.
+
+struct BrC {
+  double ef, ff, et, ft;
+  double gff, bff, gft, bft, gtf, btf, gtt, btt;
+  double Pf, Qf, Pt, Qt;
+  template <int K>
+  __device__ __forceinline__ double gPf() const {
+    if constexpr (K == 0) return fma(2.0 * gff, ef, fma(gft, et, -(bft * ft)));
+    if constexpr (K == 1) return fma(2.0 * gff, ff, fma(gft, ft, bft * et));
+    if constexpr (K == 2) return fma(gft, ef, bft * ff);
+    return fma(gft, ff, -(bft * ef));
+  }
+  template <int K>
+  __device__ __forceinline__ double gQf() const {
+    if constexpr (K == 0) return fma(-2.0 * bff, ef, -fma(bft, et, gft * ft));
+    if constexpr (K == 1) return fma(-2.0 * bff, ff, fma(gft, et, -(bft * ft)));
+    if constexpr (K == 2) return fma(gft, ff, -(bft * ef));
+    return -fma(bft, ff, gft * ef);
+  }
+  template <int K>
+  __device__ __forceinline__ double gPt() const {
+    if constexpr (K == 0) return fma(gtf, et, btf * ft);
+    if constexpr (K == 1) return fma(gtf, ft, -(btf * et));
+    if constexpr (K == 2) return fma(2.0 * gtt, et, fma(gtf, ef, -(btf * ff)));
+    return fma(2.0 * gtt, ft, fma(gtf, ff, btf * ef));
+  }
+  template <int K>
+  __device__ __forceinline__ double gQt() const {
+    if constexpr (K == 0) return fma(gtf, ft, -(btf * et));
+    if constexpr (K == 1) return -fma(gtf, et, btf * ft);
+    if constexpr (K == 2) return fma(-2.0 * btt, et, -fma(gtf, ff, btf * ef));
+    return fma(-2.0 * btt, ft, fma(gtf, ef, -(btf * ff)));
+  }
+};
+
+__device__ __forceinline__ void branch_eval_cart(double ef, double ff, double et, double ft,
+                                                 const BranchY& y, BrC& o) {
+  const double A = fma(ef, et, ff * ft), Bq = fma(ff, et, -(ef * ft));
+  const double F = fma(ef, ef, ff * ff), Tm = fma(et, et, ft * ft);
+  o.ef = ef;
+  o.ff = ff;
+  o.et = et;
+  o.ft = ft;
+  o.gff = y.gff;
+  o.bff = y.bff;
+  o.gft = y.gft;
+  o.bft = y.bft;
+  o.gtf = y.gtf;
+  o.btf = y.btf;
+  o.gtt = y.gtt;
+  o.btt = y.btt;
+  o.Pf = fma(y.gff, F, fma(y.gft, A, y.bft * Bq));
+  o.Qf = fma(-y.bff, F, fma(y.gft, Bq, -(y.bft * A)));
+  o.Pt = fma(y.gtt, Tm, fma(y.gtf, A, -(y.btf * Bq)));
+  o.Qt = fma(-y.btt, Tm, -fma(y.gtf, Bq, y.btf * A));
+}
+
 // Record layout of phase A (structure of arrays in LDS, BE entries per
 // field): for each branch end inside the tile, its share of its own bus's
 // balance rows, diagonal Jacobian and Hessian entries and product rows.
@@ -201,6 +266,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   static_assert(NBUS <= WG, "one bus per lane");
   static_assert(WG % 64 == 0, "whole waves");
   static_assert(!(R::C && R::JV), "generator sums hold either x or the direction");
+  constexpr bool CART = (WHAT & W_CART) != 0;
   constexpr bool DO_GF = (WHAT & W_GRADF) != 0 && !R::V;
   const int tid = threadIdx.x;
   const int nb = N.nb;
@@ -237,6 +303,228 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
     constexpr bool pC = (P & W_C) != 0, pJ = (P & W_J) != 0, pH = (P & W_H) != 0;
     constexpr bool pV = (P & W_VJP) != 0, pHV = (P & W_HVP) != 0, pJV = (P & W_JVP) != 0;
     constexpr bool FIRST = P == WHAT || (P & ~W_H) != 0;
+    if constexpr (CART) {
+    for (int k0 = 0; k0 < T.nw; k0 += WG) {
+      const int k = k0 + tid;
+      WorkItem wi{};
+      wi.l = -2;  // lanes past the list: no branch, no group
+      if (k < T.nw) wi = I.work[T.w0 + k];
+      const int l = wi.l, f = wi.f, t = wi.t;
+      const uint32_t sf = wi.slots & 0xFFFFu, st = wi.slots >> 16;
+      const bool live = l >= 0 && l != ol;
+      const bool fwd = f < t;
+      if (FIRST && l >= 0 && !live) {
+#pragma unroll
+        for (int q = 0; q < R::N; ++q) {
+          if (sf != kNoSlot) rec[q * BE + sf] = 0.0;
+          if (st != kNoSlot) rec[q * BE + st] = 0.0;
+        }
+      }
+      BrC b;
+      int lp = 0;
+      if (live) {
+        const BranchY y = N.br_y[l];
+        branch_eval_cart(x[f], x[nb + f], x[t], x[nb + t], y, b);
+        lp = l - after_outage(l, ol);
+        if constexpr (pC) {
+          if (sf != kNoSlot) {
+            rec[(R::oC + 0) * BE + sf] = b.Pf;
+            rec[(R::oC + 1) * BE + sf] = b.Qf;
+          }
+          if (st != kNoSlot) {
+            rec[(R::oC + 0) * BE + st] = b.Pt;
+            rec[(R::oC + 1) * BE + st] = b.Qt;
+          }
+        }
+        if constexpr (pJ) {  // own-bus columns (e_e, f_e) of the end's P and Q rows
+          if (sf != kNoSlot) {
+            rec[(R::oJ + 0) * BE + sf] = b.gPf<0>();
+            rec[(R::oJ + 1) * BE + sf] = b.gPf<1>();
+            rec[(R::oJ + 2) * BE + sf] = b.gQf<0>();
+            rec[(R::oJ + 3) * BE + sf] = b.gQf<1>();
+          }
+          if (st != kNoSlot) {
+            rec[(R::oJ + 0) * BE + st] = b.gPt<2>();
+            rec[(R::oJ + 1) * BE + st] = b.gPt<3>();
+            rec[(R::oJ + 2) * BE + st] = b.gQt<2>();
+            rec[(R::oJ + 3) * BE + st] = b.gQt<3>();
+          }
+        }
+        if constexpr (pJV) {
+          const double d0 = dir[f], d1 = dir[nb + f], d2 = dir[t], d3 = dir[nb + t];
+          const double jPf = fma(b.gPf<0>(), d0, fma(b.gPf<1>(), d1, fma(b.gPf<2>(), d2, b.gPf<3>() * d3)));
+          const double jQf = fma(b.gQf<0>(), d0, fma(b.gQf<1>(), d1, fma(b.gQf<2>(), d2, b.gQf<3>() * d3)));
+          const double jPt = fma(b.gPt<0>(), d0, fma(b.gPt<1>(), d1, fma(b.gPt<2>(), d2, b.gPt<3>() * d3)));
+          const double jQt = fma(b.gQt<0>(), d0, fma(b.gQt<1>(), d1, fma(b.gQt<2>(), d2, b.gQt<3>() * d3)));
+          if (sf != kNoSlot) {
+            rec[(R::oJV + 0) * BE + sf] = jPf;
+            rec[(R::oJV + 1) * BE + sf] = jQf;
+            double* o = B.out + I.co + 2 * nb;
+            put(&o[lp], 2.0 * fma(b.Pf, jPf, b.Qf * jQf));
+            put(&o[nll + lp], 2.0 * fma(b.Pt, jPt, b.Qt * jQt));
+          }
+          if (st != kNoSlot) {
+            rec[(R::oJV + 0) * BE + st] = jPt;
+            rec[(R::oJV + 1) * BE + st] = jQt;
+          }
+        }
+        if ((pC || pJ) && sf != kNoSlot) {  // the from-bus owner writes the flow-limit rows
+          if (cflow) {
+            put(&cflow[lp], fma(b.Pf, b.Pf, b.Qf * b.Qf));
+            put(&cflow[nll + lp], fma(b.Pt, b.Pt, b.Qt * b.Qt));
+          }
+          if (jflow) {
+            const double hf0 = 2.0 * fma(b.Pf, b.gPf<0>(), b.Qf * b.gQf<0>());
+            const double hf1 = 2.0 * fma(b.Pf, b.gPf<1>(), b.Qf * b.gQf<1>());
+            const double hf2 = 2.0 * fma(b.Pf, b.gPf<2>(), b.Qf * b.gQf<2>());
+            const double hf3 = 2.0 * fma(b.Pf, b.gPf<3>(), b.Qf * b.gQf<3>());
+            const double ht0 = 2.0 * fma(b.Pt, b.gPt<0>(), b.Qt * b.gQt<0>());
+            const double ht1 = 2.0 * fma(b.Pt, b.gPt<1>(), b.Qt * b.gQt<1>());
+            const double ht2 = 2.0 * fma(b.Pt, b.gPt<2>(), b.Qt * b.gQt<2>());
+            const double ht3 = 2.0 * fma(b.Pt, b.gPt<3>(), b.Qt * b.gQt<3>());
+            double* rf = jflow + 4 * lp;
+            double* rt = jflow + 4 * nll + 4 * lp;
+            // columns ascend: e_lo, e_hi, f_lo, f_hi
+            put(&rf[0], fwd ? hf0 : hf2);
+            put(&rf[1], fwd ? hf2 : hf0);
+            put(&rf[2], fwd ? hf1 : hf3);
+            put(&rf[3], fwd ? hf3 : hf1);
+            put(&rt[0], fwd ? ht0 : ht2);
+            put(&rt[1], fwd ? ht2 : ht0);
+            put(&rt[2], fwd ? ht1 : ht3);
+            put(&rt[3], fwd ? ht3 : ht1);
+          }
+        }
+      }
+      if constexpr (pJ) {
+        // rows of the lo and hi end bus, columns (e, f) of the other end: P then Q
+        double jv[8];
+        if (live) {
+          const double fP = b.gPf<2>(), fPf = b.gPf<3>(), fQ = b.gQf<2>(), fQf = b.gQf<3>();
+          const double tP = b.gPt<0>(), tPf = b.gPt<1>(), tQ = b.gQt<0>(), tQf = b.gQt<1>();
+          jv[0] = fwd ? fP : tP;
+          jv[1] = fwd ? fPf : tPf;
+          jv[2] = fwd ? fQ : tQ;
+          jv[3] = fwd ? fQf : tQf;
+          jv[4] = fwd ? tP : fP;
+          jv[5] = fwd ? tPf : fPf;
+          jv[6] = fwd ? tQ : fQ;
+          jv[7] = fwd ? tQf : fQf;
+        } else {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) jv[q] = 0.0;
+        }
+        if (gmax > 1) group_sum(jv, wi.grp, gmax);
+        if (wi.grp > 0) {
+          if (wi.jlo >= 0) {
+            stg[sP + wi.jlo] = jv[0];
+            stg[sP + wi.jlo + wi.alo] = jv[1];
+            stg[sQ + wi.jlo] = jv[2];
+            stg[sQ + wi.jlo + wi.alo] = jv[3];
+          }
+          if (wi.jhi >= 0) {
+            stg[sP + wi.jhi] = jv[4];
+            stg[sP + wi.jhi + wi.ahi] = jv[5];
+            stg[sQ + wi.jhi] = jv[6];
+            stg[sQ + wi.jhi + wi.ahi] = jv[7];
+          }
+        }
+      }
+      if constexpr (pH || pV || pHV) {
+        // (e_hi, e_lo), (f_lo, e_hi), (f_hi, e_lo), (f_hi, f_lo)
+        double hv4[4] = {0.0, 0.0, 0.0, 0.0};
+        if (live && hneed) {
+          const double mf = mul[2 * nb + lp];
+          const double mt = mul[2 * nb + nll + lp];
+          const double oPf = fma(2.0 * mf, b.Pf, mul[f]);
+          const double oQf = fma(2.0 * mf, b.Qf, mul[nb + f]);
+          const double oPt = fma(2.0 * mt, b.Pt, mul[t]);
+          const double oQt = fma(2.0 * mt, b.Qt, mul[nb + t]);
+          if constexpr (pV) {  // u = sum of the weighted flow gradients
+            const double u0 = fma(oPf, b.gPf<0>(), fma(oQf, b.gQf<0>(), fma(oPt, b.gPt<0>(), oQt * b.gQt<0>())));
+            const double u1 = fma(oPf, b.gPf<1>(), fma(oQf, b.gQf<1>(), fma(oPt, b.gPt<1>(), oQt * b.gQt<1>())));
+            const double u2 = fma(oPf, b.gPf<2>(), fma(oQf, b.gQf<2>(), fma(oPt, b.gPt<2>(), oQt * b.gQt<2>())));
+            const double u3 = fma(oPf, b.gPf<3>(), fma(oQf, b.gQf<3>(), fma(oPt, b.gPt<3>(), oQt * b.gQt<3>())));
+            if (sf != kNoSlot) {
+              rec[(R::oV + 0) * BE + sf] = u0;
+              rec[(R::oV + 1) * BE + sf] = u1;
+            }
+            if (st != kNoSlot) {
+              rec[(R::oV + 0) * BE + st] = u2;
+              rec[(R::oV + 1) * BE + st] = u3;
+            }
+          }
+          if constexpr (pH || pHV) {
+            // H = W + 2 mu_f (gPf gPf' + gQf gQf') + 2 mu_t (gPt gPt' + gQt gQt'),
+            // W = sum of the weights times the constant flow Hessians:
+            // W00 = W11 = 2 cf, W22 = W33 = 2 ct, W02 = W13 = cA, W12 = cB,
+            // W03 = -cB, W01 = W23 = 0
+            const double cf = fma(oPf, b.gff, -(oQf * b.bff));
+            const double ct = fma(oPt, b.gtt, -(oQt * b.btt));
+            const double cA = fma(oPf, b.gft, fma(-oQf, b.bft, fma(oPt, b.gtf, -(oQt * b.btf))));
+            const double cB = fma(oPf, b.bft, fma(oQf, b.gft, -fma(oPt, b.btf, oQt * b.gtf)));
+            const double m2f = 2.0 * mf, m2t = 2.0 * mt;
+            const double pf0 = b.gPf<0>(), pf1 = b.gPf<1>(), pf2 = b.gPf<2>(), pf3 = b.gPf<3>();
+            const double qf0 = b.gQf<0>(), qf1 = b.gQf<1>(), qf2 = b.gQf<2>(), qf3 = b.gQf<3>();
+            const double pt0 = b.gPt<0>(), pt1 = b.gPt<1>(), pt2 = b.gPt<2>(), pt3 = b.gPt<3>();
+            const double qt0 = b.gQt<0>(), qt1 = b.gQt<1>(), qt2 = b.gQt<2>(), qt3 = b.gQt<3>();
+            auto gn = [&](double w, double pa, double pb, double qa, double qb, double sa,
+                          double sb, double ra, double rb) {
+              return fma(m2f, fma(pa, pb, qa * qb), fma(m2t, fma(sa, sb, ra * rb), w));
+            };
+            const double h00 = gn(2.0 * cf, pf0, pf0, qf0, qf0, pt0, pt0, qt0, qt0);
+            const double h10 = gn(0.0, pf1, pf0, qf1, qf0, pt1, pt0, qt1, qt0);
+            const double h11 = gn(2.0 * cf, pf1, pf1, qf1, qf1, pt1, pt1, qt1, qt1);
+            const double h22 = gn(2.0 * ct, pf2, pf2, qf2, qf2, pt2, pt2, qt2, qt2);
+            const double h32 = gn(0.0, pf3, pf2, qf3, qf2, pt3, pt2, qt3, qt2);
+            const double h33 = gn(2.0 * ct, pf3, pf3, qf3, qf3, pt3, pt3, qt3, qt3);
+            const double h02 = gn(cA, pf0, pf2, qf0, qf2, pt0, pt2, qt0, qt2);
+            const double h03 = gn(-cB, pf0, pf3, qf0, qf3, pt0, pt3, qt0, qt3);
+            const double h12 = gn(cB, pf1, pf2, qf1, qf2, pt1, pt2, qt1, qt2);
+            const double h13 = gn(cA, pf1, pf3, qf1, qf3, pt1, pt3, qt1, qt3);
+            if constexpr (pH) {
+              if (sf != kNoSlot) {
+                rec[(R::oH + 0) * BE + sf] = h00;
+                rec[(R::oH + 1) * BE + sf] = h10;
+                rec[(R::oH + 2) * BE + sf] = h11;
+              }
+              if (st != kNoSlot) {
+                rec[(R::oH + 0) * BE + st] = h22;
+                rec[(R::oH + 1) * BE + st] = h32;
+                rec[(R::oH + 2) * BE + st] = h33;
+              }
+              hv4[0] = h02;
+              hv4[1] = fwd ? h12 : h03;
+              hv4[2] = fwd ? h03 : h12;
+              hv4[3] = h13;
+            }
+            if constexpr (pHV) {
+              const double d0 = dir[f], d1 = dir[nb + f], d2 = dir[t], d3 = dir[nb + t];
+              if (sf != kNoSlot) {
+                rec[(R::oHV + 0) * BE + sf] = fma(h00, d0, fma(h10, d1, fma(h02, d2, h03 * d3)));
+                rec[(R::oHV + 1) * BE + sf] = fma(h10, d0, fma(h11, d1, fma(h12, d2, h13 * d3)));
+              }
+              if (st != kNoSlot) {
+                rec[(R::oHV + 0) * BE + st] = fma(h02, d0, fma(h12, d1, fma(h22, d2, h32 * d3)));
+                rec[(R::oHV + 1) * BE + st] = fma(h03, d0, fma(h13, d1, fma(h32, d2, h33 * d3)));
+              }
+            }
+          }
+        }
+        if constexpr (pH) {
+          if (gmax > 1) group_sum(hv4, wi.grp, gmax);
+          if (wi.grp > 0) {
+            if (wi.jlo >= 0) stg[sV + wi.hvlo] = hv4[1];
+            if (wi.jhi >= 0) {
+              stg[sT + wi.hthi] = hv4[0];
+              stg[sV + wi.hvhi] = hv4[2];
+              stg[sV + wi.hvhi + wi.ahi] = hv4[3];
+            }
+          }
+        }
+      }
+    }
+    } else {
     for (int k0 = 0; k0 < T.nw; k0 += WG) {
       const int k = k0 + tid;
       WorkItem wi{};
@@ -454,6 +742,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
         }
       }
     }
+    }
   };
   if constexpr (R::H && (R::C || R::J)) {
     branch_pass(std::integral_constant<unsigned, WHAT & ~W_H>{});
@@ -472,12 +761,24 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   int ngb = 0;
   double jbP = 0.0, jbQ = 0.0, hb = 0.0, cbP = 0.0, cbQ = 0.0, vb = 0.0, hvb = 0.0;
   double jvP = 0.0, jvQ = 0.0;
+  // cartesian only: e_i, the shunt columns of e_i, and the magnitude row
+  // e_i^2 + f_i^2 with its product rows
+  double ei = 0.0, fi = 0.0, m2 = 0.0, jbPe = 0.0, jbQe = 0.0, hvbe = 0.0, vbe = 0.0, jvm = 0.0;
   double* c = (R::C && B.c) ? B.c + I.co : nullptr;
   if (has_bus) {
     ea = N.be_ptr[i] - e0;
     eb = N.be_ptr[i + 1] - e0;
     const double4 bd = N.bus[i];  // pd, qd, gs, bs
-    const double vi = x[nb + i];
+    const double vi = x[nb + i];  // v_i, or f_i in the cartesian representation
+    // the squared magnitude |V_i|^2 and the weight of its row (cartesian)
+    double lvm = 0.0;
+    (void)lvm;
+    if constexpr (CART) {
+      ei = x[i];
+      fi = vi;
+      m2 = fma(ei, ei, vi * vi);
+      if (R::H || R::V || R::HV) lvm = hneed ? mul[2 * nb + 2 * nll + i] : 0.0;
+    }
     if constexpr (R::J || R::H) {
       rw = N.rows[i];
       ac = N.acnt[i];
@@ -485,10 +786,17 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
     if constexpr (R::J) {
       jbP = 2.0 * bd.z * vi;
       jbQ = -2.0 * bd.w * vi;
+      if constexpr (CART) {
+        jbPe = 2.0 * bd.z * ei;
+        jbQe = -2.0 * bd.w * ei;
+      }
       ngb = N.gen_ptr[i + 1] - N.gen_ptr[i];
     }
     if constexpr (R::H) {
-      if (hess) hb = 2.0 * fma(mul[i], bd.z, -(mul[nb + i] * bd.w));
+      if (hess) {
+        hb = CART ? 2.0 * (fma(mul[i], bd.z, -(mul[nb + i] * bd.w)) + lvm)
+                  : 2.0 * fma(mul[i], bd.z, -(mul[nb + i] * bd.w));
+      }
     }
     if constexpr (R::C) {
       if (c) {
@@ -498,15 +806,32 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
           pg += x[2 * nb + k];
           qg += x[2 * nb + N.ng + k];
         }
-        cbP = (bd.z * vi * vi - pg) + bd.x;
-        cbQ = (-bd.w * vi * vi - qg) + bd.y;
+        if constexpr (CART) {
+          cbP = (bd.z * m2 - pg) + bd.x;
+          cbQ = (-bd.w * m2 - qg) + bd.y;
+        } else {
+          cbP = (bd.z * vi * vi - pg) + bd.x;
+          cbQ = (-bd.w * vi * vi - qg) + bd.y;
+        }
       }
     }
     if constexpr (R::V) {
-      vb = 2.0 * vi * fma(mul[i], bd.z, -(mul[nb + i] * bd.w));
+      if constexpr (CART) {
+        const double kap = 2.0 * (fma(mul[i], bd.z, -(mul[nb + i] * bd.w)) + lvm);
+        vb = kap * vi;
+        vbe = kap * ei;
+      } else {
+        vb = 2.0 * vi * fma(mul[i], bd.z, -(mul[nb + i] * bd.w));
+      }
     }
     if constexpr (R::HV) {
-      hvb = 2.0 * fma(mul[i], bd.z, -(mul[nb + i] * bd.w)) * dir[nb + i];
+      if constexpr (CART) {
+        const double kap = 2.0 * (fma(mul[i], bd.z, -(mul[nb + i] * bd.w)) + lvm);
+        hvb = kap * dir[nb + i];
+        hvbe = kap * dir[i];
+      } else {
+        hvb = 2.0 * fma(mul[i], bd.z, -(mul[nb + i] * bd.w)) * dir[nb + i];
+      }
     }
     if constexpr (R::JV) {
       double dpg = 0, dqg = 0;
@@ -515,8 +840,14 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
         dpg += dir[2 * nb + k];
         dqg += dir[2 * nb + N.ng + k];
       }
-      jvP = 2.0 * bd.z * vi * dir[nb + i] - dpg;
-      jvQ = -2.0 * bd.w * vi * dir[nb + i] - dqg;
+      if constexpr (CART) {  // d|V_i|^2 along the direction
+        jvm = 2.0 * fma(ei, dir[i], vi * dir[nb + i]);
+        jvP = bd.z * jvm - dpg;
+        jvQ = -bd.w * jvm - dqg;
+      } else {
+        jvP = 2.0 * bd.z * vi * dir[nb + i] - dpg;
+        jvQ = -2.0 * bd.w * vi * dir[nb + i] - dqg;
+      }
     }
   }
   __syncthreads();
@@ -533,6 +864,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       }
       put(&c[i], sp + cbP);
       put(&c[nb + i], sq + cbQ);
+      if constexpr (CART) put(&c[2 * nb + 2 * nll + i], m2);
     }
   }
   if constexpr (DO_GF) {
@@ -554,10 +886,15 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       // (theta_i), (v_i) of the P row, the same of the Q row, then the
       // generator columns (constant -1)
       const int pt = rw.x + ac.y, pv = rw.x + ac.x + ac.y;
-      stg[sP + pt] = s0;
+      stg[sP + pt] = CART ? s0 + jbPe : s0;
       stg[sP + pv] = s1 + jbP;
-      stg[sQ + pt] = s2;
+      stg[sQ + pt] = CART ? s2 + jbQe : s2;
       stg[sQ + pv] = s3 + jbQ;
+      if constexpr (CART) {  // the magnitude row (e_i, f_i), after the flow rows
+        double* jm = jflow + 8 * nll + 2 * i;
+        put(&jm[0], 2.0 * ei);
+        put(&jm[1], 2.0 * fi);
+      }
       for (int g = 0; g < ngb; ++g) {
         stg[sP + rw.x + 2 * ac.x + g] = -1.0;
         stg[sQ + rw.x + 2 * ac.x + g] = -1.0;
@@ -572,7 +909,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
         s1 += rec[(R::oH + 1) * BE + e];
         s2 += rec[(R::oH + 2) * BE + e];
       }
-      stg[sT + rw.z + ac.y] = s0;
+      stg[sT + rw.z + ac.y] = CART ? s0 + hb : s0;
       stg[sV + rw.w + ac.y] = s1;
       stg[sV + rw.w + ac.x + ac.y] = s2 + hb;
     }
@@ -584,7 +921,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       uv += rec[(R::oV + 1) * BE + e];
     }
     double* u = B.u + I.xo;
-    put(&u[i], ut);
+    put(&u[i], CART ? ut + vbe : ut);
     put(&u[nb + i], uv + vb);
   }
   if constexpr (R::HV) {
@@ -594,7 +931,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       hv += rec[(R::oHV + 1) * BE + e];
     }
     double* o = B.out + I.xo;
-    put(&o[i], ht);
+    put(&o[i], CART ? ht + hvbe : ht);
     put(&o[nb + i], hv + hvb);
   }
   if constexpr (R::JV) {
@@ -606,6 +943,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
     double* o = B.out + I.co;
     put(&o[i], jp + jvP);
     put(&o[nb + i], jq + jvQ);
+    if constexpr (CART) put(&o[2 * nb + 2 * nll + i], jvm);
   }
   }
 
@@ -768,7 +1106,19 @@ hipError_t launch_fsum(const InstOff* table, const InstOff& one, int first, int 
 hipError_t launch_eval(unsigned kvariant, int tile_be, const Bufs& b, const InstOff* table,
                        const InstOff& one, const Tile* tiles, int ntiles, int grid,
                        hipStream_t stream) {
+  constexpr unsigned C = W_CART;
   switch (kvariant) {
+    case K_FG | C: return launch_caps<K_FG | C>(tile_be, b, table, one, tiles, ntiles, grid, stream);
+    case K_J | C: return launch_caps<K_J | C>(tile_be, b, table, one, tiles, ntiles, grid, stream);
+    case K_H | C: return launch_caps<K_H | C>(tile_be, b, table, one, tiles, ntiles, grid, stream);
+    case K_ALL | C:
+      return launch_caps<K_ALL | C>(tile_be, b, table, one, tiles, ntiles, grid, stream);
+    case K_VJP | C:
+      return launch_caps<K_VJP | C>(tile_be, b, table, one, tiles, ntiles, grid, stream);
+    case K_HVP | C:
+      return launch_caps<K_HVP | C>(tile_be, b, table, one, tiles, ntiles, grid, stream);
+    case K_JVP | C:
+      return launch_caps<K_JVP | C>(tile_be, b, table, one, tiles, ntiles, grid, stream);
     case K_FG: return launch_caps<K_FG>(tile_be, b, table, one, tiles, ntiles, grid, stream);
     case K_J: return launch_caps<K_J>(tile_be, b, table, one, tiles, ntiles, grid, stream);
     case K_H: return launch_caps<K_H>(tile_be, b, table, one, tiles, ntiles, grid, stream);

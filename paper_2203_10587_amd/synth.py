@@ -131,6 +131,20 @@ def draw_iterate(g: Grid, rng: np.random.Generator, sigma: float = 1.0) -> Itera
     return Iterate(x=x, lam=lam.astype(np.float64), sigma=float(sigma))
 
 
+def draw_iterate_cartesian(g: Grid, rng: np.random.Generator, sigma: float = 1.0) -> Iterate:
+    """Iterate of the cartesian representation x = [e; f; Pg; Qg]:
+    e~U(.9,1.1), f~U(-.2,.2), Pg/Qg uniform in bounds, lambda~N(0,1) over
+    the m + nbus rows (balance, flow, then magnitude rows)."""
+    nb, ng = g.nbus, g.ngen
+    e = rng.uniform(0.9, 1.1, nb)
+    f = rng.uniform(-0.2, 0.2, nb)
+    pg = rng.uniform(g.gen_pmin, g.gen_pmax) if ng else np.zeros(0)
+    qg = rng.uniform(g.gen_qmin, g.gen_qmax) if ng else np.zeros(0)
+    lam = rng.standard_normal(g.m + nb)
+    x = np.concatenate([e, f, pg, qg]).astype(np.float64)
+    return Iterate(x=x, lam=lam.astype(np.float64), sigma=float(sigma))
+
+
 def _branch_params(nl: int, rng: np.random.Generator, n_xfmr: int = 0):
     r = rng.uniform(0.005, 0.05, nl)
     x = rng.uniform(0.05, 0.3, nl)

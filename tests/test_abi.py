@@ -109,3 +109,34 @@ def test_null_arguments_return_einval():
     assert L.acopf_eval_f_g(None, None, None, None, None, None) == A.ACOPF_EINVAL
     assert L.acopf_batch_create(None, 0, None, C.byref(C.c_void_p())) == A.ACOPF_EINVAL
     assert L.acopf_last_error()
+
+
+@pytest.mark.parametrize("name,g", [x for x in _grids() if x[0] in ("ring9", "rand30", "star40", "nogen")])
+def test_host_pattern_cartesian_bit_exact(name, g):
+    """The cartesian representation: the polar rows with (e, f) in the places
+    of (theta, v), then one (e_i, f_i) row per bus; the same H pattern."""
+    from oracle import cartesian as OC
+    dims, jp, jc, hp, hc = A.acopf_pattern_host_form(g, A.ACOPF_CARTESIAN)
+    ojp, ojc, ohp, ohc = OC.pattern(O.prepare(g))
+    for a, b in ((jp, ojp), (jc, ojc), (hp, ohp), (hc, ohc)):
+        np.testing.assert_array_equal(a, b)
+    assert (dims.n, dims.m) == (g.n, g.m + g.nbus)
+    if g.nbranch:
+        for l in (0, g.nbranch - 1):
+            dims, jp, jc, hp, hc = A.acopf_pattern_host_form(g, A.ACOPF_CARTESIAN, l)
+            ojp, ojc, ohp, ohc = OC.pattern(O.prepare(S.remove_branch(g, l)))
+            for a, b in ((jp, ojp), (jc, ojc), (hp, ohp), (hc, ohc)):
+                np.testing.assert_array_equal(a, b)
+            assert dims.m == g.m - 2 + g.nbus
+
+
+def test_form_validation():
+    g = S.config0(0)[0]
+    with pytest.raises(A.AcopfError) as ei:
+        A.acopf_pattern_host_form(g, 2)
+    assert ei.value.code == A.ACOPF_EINVAL
+    # the polar entry point is the polar form
+    a = A.acopf_pattern_host(g)
+    b = A.acopf_pattern_host_form(g, A.ACOPF_POLAR)
+    for x, y in zip(a[1:], b[1:]):
+        np.testing.assert_array_equal(x, y)

@@ -1,0 +1,237 @@
+"""GPU parity of the power-balance-cartesian representation: the HIP path
+(through the C ABI) against the cartesian CPU oracle, under the same
+row-scaled relative rule (tol 1e-12) as the polar path, with CSR patterns
+bit-exact.  Covers the single-net entry points on irregular grids (shunts,
+parallel branches, phase shifters, a star bus, no generators, one bus,
+isolated buses, several tiles with a ragged tail), the products (VJP, HVP,
+JVP), N-1 children, batches (bitwise equal to the plain path), and the
+rejections (mixed representations in one batch, drawn iterates)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from oracle import cartesian as OC
+from paper_2203_10587_amd import synth as S
+from tests.parity import assert_close, log
+from tests.test_gpu_parity import small_cases
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dev(a):
+    return _torch().as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def nan(n):
+    torch = _torch()
+    return torch.full((int(n),), np.nan, dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def oracle_ref(g, it, w_f=None, w_c=None):
+    mdl = O.prepare(g)
+    out = OC.evaluate(mdl, it.x, it.sigma, it.lam)
+    ref = {"mdl": mdl, "out": out, "scale": OC.scales(mdl, it.x, out)}
+    if w_c is not None:
+        ref["u"] = OC.vjp(mdl, it.x, w_f, w_c)
+        ref["u_scale"] = OC.vjp_scale(mdl, it.x, w_f, w_c)
+    return ref
+
+
+def compare(tag, gpu, ref):
+    out, sc = ref["out"], ref["scale"]
+    r = {"f": assert_close(tag + ".f", [gpu["f"]], [out["f"]], [sc["f"]])}
+    for k in ("grad_f", "c", "jac_val", "hess_val"):
+        r[k] = assert_close(f"{tag}.{k}", gpu[k], out[k], sc[k])
+    if "u" in gpu:
+        r["u"] = assert_close(tag + ".u", gpu["u"], ref["u"], ref["u_scale"])
+    return r
+
+
+def gpu_eval(A, net, it, w_f=None, w_c=None, separate=True):
+    x, lam = dev(it.x), dev(it.lam)
+    f, gf, c, jv, hv = nan(1), nan(net.n), nan(net.m), nan(net.nnz_jac), nan(net.nnz_hess)
+    if separate:
+        A.acopf_eval_f_g(net, x, f, gf, c)
+        A.acopf_eval_jac(net, x, jv)
+        A.acopf_eval_hess(net, x, it.sigma, lam, hv)
+    else:
+        A.acopf_eval_all(net, x, it.sigma, lam, f, gf, c, jv, hv)
+    out = {"f": float(host(f)[0]), "grad_f": host(gf), "c": host(c), "jac_val": host(jv),
+           "hess_val": host(hv)}
+    if w_c is not None:
+        u = nan(net.n)
+        A.acopf_vjp(net, x, w_f, dev(w_c), u)
+        out["u"] = host(u)
+    _torch().cuda.synchronize()
+    return out
+
+
+def check_pattern(A, net, mdl):
+    got = A.acopf_pattern(net)
+    for a, b in zip(got, OC.pattern(mdl)):
+        np.testing.assert_array_equal(a, b)
+
+
+def products(A, net, g, it, d):
+    """H d and J d on the GPU against the oracle's matrices (full symmetric
+    H), with the scales of the polar product tests."""
+    hv, jv = nan(net.n), nan(net.m)
+    A.acopf_hvp(net, dev(it.x), it.sigma, dev(it.lam), dev(d), hv)
+    A.acopf_jvp(net, dev(it.x), dev(d), jv)
+    mdl = O.prepare(g)
+    H = OC.hessian_matrix(mdl, it.x, it.sigma, it.lam)
+    J = OC.jacobian_matrix(mdl, it.x)
+    out = OC.evaluate(mdl, it.x)
+    sj = OC.scales(mdl, it.x, out)["jac_val"]
+    jp, jc, _, _ = OC.pattern(mdl)
+    rows = np.repeat(np.arange(len(jp) - 1), np.diff(jp))
+    jscale = np.bincount(rows, weights=sj * np.abs(d[jc]), minlength=len(jp) - 1)
+    assert_close("jvp", host(jv), J @ d, jscale)
+    Habs = abs(H).tocsr()
+    rowmax = Habs.max(axis=1).toarray().ravel()
+    hscale = rowmax * ((Habs > 0).astype(float) @ np.abs(d))
+    assert_close("hvp", host(hv), H @ d, hscale)
+
+
+@pytest.mark.parametrize("name,g", list(small_cases()), ids=lambda v: v if isinstance(v, str) else "")
+def test_cartesian_plain_parity(gpu_lib, name, g):
+    from paper_2203_10587_amd import acopf as A
+    log(f"[cartesian parity] {name} nb={g.nbus} nl={g.nbranch} ng={g.ngen}")
+    rng = np.random.default_rng(23)
+    it = S.draw_iterate_cartesian(g, rng, sigma=0.61)
+    w_c = rng.standard_normal(g.m + g.nbus)
+    ref = oracle_ref(g, it, 1.7, w_c)
+    net = A.acopf_net_create_form(g, A.ACOPF_CARTESIAN)
+    assert A.acopf_net_form(net) == A.ACOPF_CARTESIAN
+    assert (net.n, net.m) == (g.n, g.m + g.nbus)
+    check_pattern(A, net, ref["mdl"])
+    out = gpu_eval(A, net, it, 1.7, w_c)
+    r = compare(name, out, ref)
+    log(f"   worst error / tolerance: {max(r.values()):.3e}")
+    fused = gpu_eval(A, net, it, separate=False)
+    for k in ("grad_f", "c", "jac_val", "hess_val"):
+        np.testing.assert_array_equal(fused[k], out[k], err_msg=k)
+    assert fused["f"] == out["f"]
+    if g.nbus > 1:
+        products(A, net, g, it, rng.standard_normal(g.n))
+
+
+def test_cartesian_outage_parity(gpu_lib):
+    """N-1 children of a cartesian base keep its representation; removals of
+    parallel branches keep the shared slots."""
+    from paper_2203_10587_amd import acopf as A
+    g = S.random_grid(60, 95, 20, seed=5, parallel=3)
+    base = A.acopf_net_create_form(g, A.ACOPF_CARTESIAN)
+    pairs = {}
+    for l in range(g.nbranch):
+        pairs.setdefault(frozenset((int(g.br_from[l]), int(g.br_to[l]))), []).append(l)
+    par = [l for ls in pairs.values() if len(ls) > 1 for l in ls]
+    for l in sorted(set([0, g.nbranch - 1, g.nbranch // 2] + par[:3])):
+        log(f"[cartesian outage] branch {l}")
+        g2 = S.remove_branch(g, l)
+        rng = np.random.default_rng(100 + l)
+        it = S.draw_iterate_cartesian(g2, rng, sigma=0.8)
+        w_c = rng.standard_normal(g2.m + g2.nbus)
+        ref = oracle_ref(g2, it, 0.5, w_c)
+        child = A.acopf_net_create_outage(base, l)
+        assert A.acopf_net_form(child) == A.ACOPF_CARTESIAN
+        check_pattern(A, child, ref["mdl"])
+        compare(f"outage-{l}", gpu_eval(A, child, it, 0.5, w_c), ref)
+        products(A, child, g2, it, rng.standard_normal(g2.n))
+        child.close()
+
+
+def test_cartesian_2000_bus_parity(gpu_lib):
+    """The 2,000-bus / 3,000-branch grid of the N-1 workload, one instance."""
+    from paper_2203_10587_amd import acopf as A
+    g = S.rgg_grid(2000, 3000, seed=7)
+    rng = np.random.default_rng(4)
+    it = S.draw_iterate_cartesian(g, rng, sigma=1.0)
+    w_c = rng.standard_normal(g.m + g.nbus)
+    ref = oracle_ref(g, it, 0.9, w_c)
+    net = A.acopf_net_create_form(g, A.ACOPF_CARTESIAN)
+    r = compare("rgg2000", gpu_eval(A, net, it, 0.9, w_c), ref)
+    log(f"[cartesian 2000] worst error / tolerance: {max(r.values()):.3e}")
+
+
+def test_cartesian_batch_bitwise_and_parity(gpu_lib):
+    """A batch of a cartesian base and N-1 children: every instance equals the
+    plain path bit for bit (every tile size) and the oracle within tolerance;
+    the batched products equal the plain ones."""
+    torch = _torch()
+    from paper_2203_10587_amd import acopf as A
+    g = S.rgg_grid(700, 910, seed=11)
+    base = A.acopf_net_create_form(g, A.ACOPF_CARTESIAN)
+    outs = [3, 77, 400, g.nbranch - 1]
+    nets = [base] + [A.acopf_net_create_outage(base, l) for l in outs]
+    grids = [g] + [S.remove_branch(g, l) for l in outs]
+    rng = np.random.default_rng(8)
+    its = [S.draw_iterate_cartesian(x, rng, sigma=0.5 + 0.1 * k) for k, x in enumerate(grids)]
+    plain = [gpu_eval(A, n, it) for n, it in zip(nets, its)]
+    for tile_be in (64, 128, 256, 512):
+        b = A.acopf_batch_create(nets, tile_be=tile_be)
+        nx, nc = int(b.x_off[-1]), int(b.c_off[-1])
+        x, lam = np.empty(nx), np.empty(nc)
+        for k, it in enumerate(its):
+            x[b.x_off[k]:b.x_off[k + 1]] = it.x
+            lam[b.c_off[k]:b.c_off[k + 1]] = it.lam
+        X, L = dev(x), dev(lam)
+        sig = dev([it.sigma for it in its])
+        f, gf, c = nan(b.count), nan(nx), nan(nc)
+        jv, hv = nan(b.j_off[-1]), nan(b.h_off[-1])
+        A.acopf_batch_eval(b, X, sig, L, f, gf, c, jv, hv, A.ACOPF_ALL)
+        torch.cuda.synchronize()
+        for k in range(b.count):
+            s = lambda t, o: host(t)[int(o[k]):int(o[k + 1])]
+            got = {"grad_f": s(gf, b.x_off), "c": s(c, b.c_off), "jac_val": s(jv, b.j_off),
+                   "hess_val": s(hv, b.h_off)}
+            for key, v in got.items():
+                np.testing.assert_array_equal(v, plain[k][key], err_msg=f"{tile_be} {k} {key}")
+            assert float(host(f)[k]) == plain[k]["f"]
+        if tile_be == 256:
+            for k in range(b.count):
+                compare(f"batch-{k}", plain[k], oracle_ref(grids[k], its[k]))
+            d = rng.standard_normal(nx)
+            ho, jo = nan(nx), nan(nc)
+            A.acopf_batch_hvp(b, X, sig, L, dev(d), ho)
+            A.acopf_batch_jvp(b, X, dev(d), jo)
+            torch.cuda.synchronize()
+            for k in range(b.count):
+                hk, jk = nan(nets[k].n), nan(nets[k].m)
+                dk = dev(d[b.x_off[k]:b.x_off[k + 1]])
+                A.acopf_hvp(nets[k], dev(its[k].x), its[k].sigma, dev(its[k].lam), dk, hk)
+                A.acopf_jvp(nets[k], dev(its[k].x), dk, jk)
+                np.testing.assert_array_equal(host(ho)[b.x_off[k]:b.x_off[k + 1]], host(hk))
+                np.testing.assert_array_equal(host(jo)[b.c_off[k]:b.c_off[k + 1]], host(jk))
+        b.close()
+
+
+def test_cartesian_rejections(gpu_lib):
+    """One representation per batch; drawn iterates only for polar."""
+    torch = _torch()
+    from paper_2203_10587_amd import acopf as A
+    g = S.random_grid(12, 20, 5, seed=1, parallel=2)
+    cart = A.acopf_net_create_form(g, A.ACOPF_CARTESIAN)
+    pol = A.acopf_net_create(g)
+    assert A.acopf_net_form(pol) == A.ACOPF_POLAR
+    with pytest.raises(A.AcopfError) as ei:
+        A.acopf_batch_create([cart, pol])
+    assert ei.value.code == A.ACOPF_EINVAL
+    with pytest.raises(A.AcopfError):
+        A.acopf_net_create_form(g, 7)
+    b = A.acopf_batch_create([cart])
+    seeds = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(A.AcopfError):
+        A.acopf_batch_draw_iterates(b, 0, 1, seeds, (0.0, 1.0, -1.0, 1.0), nan(g.n),
+                                    nan(g.m + g.nbus))
+    b.close()
