@@ -107,7 +107,7 @@ typedef struct {
 } acopf_net_desc;
 
 typedef struct {
-  int64_t n;         /* variables: 2 nbus + 2 ngen                         */
+  int64_t n;         /* 2 nbus + 2 ngen (+ nbus per slack block)           */
   int64_t m;         /* 2 nbus + 2 (live branches) (+ nbus, cartesian)     */
   int64_t nnz_jac;   /* Jacobian pattern entries                           */
   int64_t nnz_hess;  /* lower-Hessian pattern entries                      */
@@ -170,6 +170,45 @@ int acopf_pattern_host(const acopf_net_desc* desc, int32_t outage, acopf_dims* d
  * an N-1 child keeps its base's form; a batch needs one form throughout, and
  * acopf_batch_draw_iterates serves only the polar one (EINVAL otherwise). */
 enum { ACOPF_POLAR = 0, ACOPF_CARTESIAN = 1 };
+
+/* Feasibility slack variables (paper: OPFLOW section, the formulation
+ * features beside the standard ACOPF: load loss and power imbalance).  The
+ * paper gives no equations; the model evaluated here:
+ *   ACOPF_SLACK_IMBALANCE  four variables per bus, dP+ and dP- in the bus's
+ *                          active balance row, dQ+ and dQ- in its reactive
+ *                          row; "+" supplies power (coefficient -1, as
+ *                          generation), "-" absorbs it (+1, as load);
+ *   ACOPF_SLACK_LOADLOSS   two per bus, Pl and Ql, the shed part of the
+ *                          bus load (coefficient -1: Pd - Pl remains).
+ * Each enabled block holds nb variables; the blocks follow Qg in x in the
+ * order dP+, dP-, dQ+, dQ-, Pl, Ql, so n = 2 nb + 2 ng + ns nb with
+ * ns in {0, 2, 4, 6}.  Each slack s adds c2 (B s)^2 + c1 (B s) to f
+ * (B = base_mva; (c2, c1) = (imb_c2, imb_c1) or (loss_c2, loss_c1)).  The
+ * bounds (s >= 0, Pl <= Pd) are the solver's.  Patterns: each balance row
+ * gains its slack columns after its generator columns, in block order; H
+ * gains one diagonal entry per slack column (explicit zeros kept), after
+ * the (empty) Qg rows.  Slacks combine with either representation; N-1
+ * children inherit them; acopf_batch_draw_iterates refuses nets with them. */
+enum { ACOPF_SLACK_IMBALANCE = 1u, ACOPF_SLACK_LOADLOSS = 2u };
+
+/* Options of a net; a zero-initialised struct is the polar model without
+ * slacks (what acopf_net_create builds). */
+typedef struct {
+  int32_t form;            /* ACOPF_POLAR or ACOPF_CARTESIAN                   */
+  uint32_t slacks;         /* ACOPF_SLACK_* bits                               */
+  double imb_c2, imb_c1;   /* penalty per imbalance variable, $/MW^2h, $/MWh   */
+  double loss_c2, loss_c1; /* penalty per load-loss variable                   */
+} acopf_net_opts;
+
+/* acopf_net_create with options (NULL: the defaults).  EINVAL for an unknown
+ * form or slack bit or a non-finite penalty. */
+int acopf_net_create_opts(const acopf_net_desc* desc, const acopf_net_opts* opts,
+                          acopf_net* out);
+
+/* acopf_pattern_host with options (NULL: the defaults). */
+int acopf_pattern_host_opts(const acopf_net_desc* desc, const acopf_net_opts* opts,
+                            int32_t outage, acopf_dims* dims, int32_t* jac_rowptr,
+                            int32_t* jac_col, int32_t* hess_rowptr, int32_t* hess_col);
 
 /* acopf_net_create in the representation `form` (EINVAL for another value). */
 int acopf_net_create_form(const acopf_net_desc* desc, int32_t form, acopf_net* out);

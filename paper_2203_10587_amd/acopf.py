@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(PKG, "libacopf.so")
 ACOPF_OK, ACOPF_EINVAL, ACOPF_ENOMEM, ACOPF_EHIP, ACOPF_EBUDGET, ACOPF_ESTATE = 0, -1, -2, -3, -4, -5
 ACOPF_F, ACOPF_GRADF, ACOPF_C, ACOPF_J, ACOPF_H, ACOPF_ALL = 1, 2, 4, 8, 16, 31
 ACOPF_POLAR, ACOPF_CARTESIAN = 0, 1
+ACOPF_SLACK_IMBALANCE, ACOPF_SLACK_LOADLOSS = 1, 2
 
 _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)
@@ -47,6 +48,18 @@ class acopf_dims(C.Structure):
                 ("ngen", C.c_int32), ("outage", C.c_int32)]
 
 
+class acopf_net_opts(C.Structure):
+    _fields_ = [("form", C.c_int32), ("slacks", C.c_uint32), ("imb_c2", C.c_double),
+                ("imb_c1", C.c_double), ("loss_c2", C.c_double), ("loss_c1", C.c_double)]
+
+
+def net_opts(form: int = ACOPF_POLAR, slacks: int = 0, imb_cost=(0.0, 0.0),
+             loss_cost=(0.0, 0.0)) -> acopf_net_opts:
+    """acopf_net_opts from Python values; costs are (c2, c1) per MW."""
+    return acopf_net_opts(int(form), int(slacks), float(imb_cost[0]), float(imb_cost[1]),
+                          float(loss_cost[0]), float(loss_cost[1]))
+
+
 class acopf_sched(C.Structure):
     _fields_ = [("tile_be", C.c_int32), ("grid_mult", C.c_int32), ("xcd_group", C.c_int32),
                 ("no_graph", C.c_int32)]
@@ -62,6 +75,11 @@ _SIGS = {
     "acopf_net_create_form": (C.c_int, [C.POINTER(acopf_net_desc), C.c_int32,
                                         C.POINTER(C.c_void_p)]),
     "acopf_net_form": (C.c_int, [C.c_void_p, _i32p]),
+    "acopf_net_create_opts": (C.c_int, [C.POINTER(acopf_net_desc), C.POINTER(acopf_net_opts),
+                                        C.POINTER(C.c_void_p)]),
+    "acopf_pattern_host_opts": (C.c_int, [C.POINTER(acopf_net_desc), C.POINTER(acopf_net_opts),
+                                          C.c_int32, C.POINTER(acopf_dims), _i32p, _i32p, _i32p,
+                                          _i32p]),
     "acopf_net_create_outage": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "acopf_net_destroy": (C.c_int, [C.c_void_p]),
     "acopf_dims_get": (C.c_int, [C.c_void_p, C.POINTER(acopf_dims)]),
@@ -236,6 +254,16 @@ def acopf_net_create_form(grid, form: int) -> Net:
     return Net(h, _dims(h))
 
 
+def acopf_net_create_opts(grid, opts: Optional[acopf_net_opts] = None) -> Net:
+    """A net with options (representation, slack blocks and their penalties);
+    None gives the polar model without slacks."""
+    d = _Desc(grid)
+    h = C.c_void_p()
+    _check(lib().acopf_net_create_opts(C.byref(d.desc), C.byref(opts) if opts is not None else None,
+                                       C.byref(h)))
+    return Net(h, _dims(h))
+
+
 def acopf_net_form(net: Net) -> int:
     out = C.c_int32()
     _check(lib().acopf_net_form(net.handle, C.byref(out)))
@@ -265,6 +293,22 @@ def acopf_pattern(net: Net):
 
 def acopf_pattern_host(grid, outage: int = -1):
     return acopf_pattern_host_form(grid, ACOPF_POLAR, outage)
+
+
+def acopf_pattern_host_opts(grid, opts: Optional[acopf_net_opts] = None, outage: int = -1):
+    d = _Desc(grid)
+    o = C.byref(opts) if opts is not None else None
+    dims = acopf_dims()
+    _check(lib().acopf_pattern_host_opts(C.byref(d.desc), o, int(outage), C.byref(dims),
+                                         None, None, None, None))
+    jp = np.empty(dims.m + 1, np.int32)
+    jc = np.empty(dims.nnz_jac, np.int32)
+    hp = np.empty(dims.n + 1, np.int32)
+    hc = np.empty(dims.nnz_hess, np.int32)
+    _check(lib().acopf_pattern_host_opts(C.byref(d.desc), o, int(outage), None,
+                                         jp.ctypes.data_as(_i32p), jc.ctypes.data_as(_i32p),
+                                         hp.ctypes.data_as(_i32p), hc.ctypes.data_as(_i32p)))
+    return dims, jp, jc, hp, hc
 
 
 def acopf_pattern_host_form(grid, form: int, outage: int = -1):

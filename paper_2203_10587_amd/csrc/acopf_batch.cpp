@@ -442,6 +442,8 @@ int acopf_batch_draw_iterates(acopf_batch b, int32_t first, int32_t count, const
     return fail(ACOPF_EINVAL, "instance window out of range");
   if (count > 65535) return fail(ACOPF_EINVAL, "at most 65535 instances per draw");
   if (b->form != ACOPF_POLAR) return fail(ACOPF_EINVAL, "iterates are drawn for the polar representation only");
+  for (acopf_net n : b->nets)
+    if (n->base->topo.sl.ns) return fail(ACOPF_EINVAL, "iterates are not drawn for nets with slack variables");
   int cur = 0;
   hipError_t e = hipGetDevice(&cur);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

@@ -32,8 +32,46 @@ int hip_fail(hipError_t e, const char* what) {
 
 static bool finite(double v) { return std::isfinite(v); }
 
-int build_topology(const acopf_net_desc* d, Topology* T) {
+// Representation and slack blocks of the options (nullptr: polar, none).
+static int apply_opts(const acopf_net_opts* o, Topology* T) {
+  T->form = ACOPF_POLAR;
+  T->sl = SlackDev{};
+  if (!o) return ACOPF_OK;
+  if (o->form != ACOPF_POLAR && o->form != ACOPF_CARTESIAN)
+    return fail(ACOPF_EINVAL, "form must be ACOPF_POLAR or ACOPF_CARTESIAN");
+  if (o->slacks & ~unsigned(ACOPF_SLACK_IMBALANCE | ACOPF_SLACK_LOADLOSS))
+    return fail(ACOPF_EINVAL, "unknown bits in slacks");
+  if (!finite(o->imb_c2) || !finite(o->imb_c1) || !finite(o->loss_c2) || !finite(o->loss_c1))
+    return fail(ACOPF_EINVAL, "non-finite slack penalty");
+  T->form = o->form;
+  SlackDev& s = T->sl;
+  auto add = [&](int row, double coef, double c2, double c1) {
+    s.row[s.ns] = row;
+    s.coef[s.ns] = coef;
+    s.c2[s.ns] = c2;
+    s.c1[s.ns] = c1;
+    ++s.ns;
+  };
+  if (o->slacks & ACOPF_SLACK_IMBALANCE) {
+    add(0, -1.0, o->imb_c2, o->imb_c1);  // dP+: supplies power
+    add(0, 1.0, o->imb_c2, o->imb_c1);   // dP-: absorbs it
+    add(1, -1.0, o->imb_c2, o->imb_c1);  // dQ+
+    add(1, 1.0, o->imb_c2, o->imb_c1);   // dQ-
+  }
+  if (o->slacks & ACOPF_SLACK_LOADLOSS) {
+    add(0, -1.0, o->loss_c2, o->loss_c1);  // Pl: shed active load
+    add(1, -1.0, o->loss_c2, o->loss_c1);  // Ql
+  }
+  s.nsp = s.ns / 2;
+  return ACOPF_OK;
+}
+
+int build_topology(const acopf_net_desc* d, const acopf_net_opts* o, Topology* T) {
   if (!d) return fail(ACOPF_EINVAL, "null network description");
+  {
+    const int rc = apply_opts(o, T);
+    if (rc) return rc;
+  }
   if (d->nbus < 1) return fail(ACOPF_EINVAL, "nbus must be >= 1");
   if (d->nbranch < 0 || d->ngen < 0) return fail(ACOPF_EINVAL, "negative nbranch or ngen");
   if (!(d->base_mva > 0.0) || !finite(d->base_mva)) return fail(ACOPF_EINVAL, "base_mva must be > 0");
@@ -157,23 +195,26 @@ int build_topology(const acopf_net_desc* d, Topology* T) {
     jpv[i] = jp;
     htv[i] = ht;
     hvv[i] = hvsum;
-    jp += 2 * a + g;
+    jp += 2 * a + g + T->sl.nsp;
     ht += below + 1;
     hvsum += a + below + 1;
   }
   jpv[nb] = jp;
   htv[nb] = ht;
   hvv[nb] = hvsum;
+  const int64_t nslk = int64_t(T->sl.ns) * nb;
   const int64_t jflow = 2 * jp, nnzj = jflow + 8 * int64_t(nl);
-  const int64_t hpg = ht + hvsum, nnzh = hpg + ng;
-  if (nnzj >= INT_MAX || nnzh >= INT_MAX) return fail(ACOPF_EINVAL, "pattern exceeds 2^31 entries");
+  const int64_t hpg = ht + hvsum, nnzh = hpg + ng + nslk;
+  if (nnzj + (T->form == ACOPF_CARTESIAN ? 2 * int64_t(nb) : 0) >= INT_MAX || nnzh >= INT_MAX ||
+      2 * int64_t(nb) + 2 * int64_t(ng) + nslk >= INT_MAX)
+    return fail(ACOPF_EINVAL, "pattern exceeds 2^31 entries");
   for (int i = 0; i <= nb; ++i)
     T->rows[i] = make_int4(int(jpv[i]), int(jp + jpv[i]), int(htv[i]), int(ht + hvv[i]));
   T->jflow = int(jflow);
   T->hpg = int(hpg);
   T->nnz_jac = nnzj;
   T->nnz_hess = nnzh;
-  T->nchunks = std::max(1, (ng + kGenChunk - 1) / kGenChunk);
+  T->nchunks = std::max(1, int((ng + nslk + kGenChunk - 1) / kGenChunk));
   return ACOPF_OK;
 }
 
@@ -196,7 +237,7 @@ int outage_info(const Topology& T, int32_t l, int32_t* p, int32_t* q, int32_t* r
 void fill_dims(const Topology& T, int32_t outage, int32_t rm, acopf_dims* d) {
   const int live = T.nl - (outage >= 0 ? 1 : 0);
   const bool cart = T.form == ACOPF_CARTESIAN;
-  d->n = 2 * int64_t(T.nb) + 2 * int64_t(T.ng);
+  d->n = 2 * int64_t(T.nb) + 2 * int64_t(T.ng) + int64_t(T.sl.ns) * T.nb;
   d->m = 2 * int64_t(T.nb) + 2 * int64_t(live) + (cart ? T.nb : 0);
   d->nnz_jac = T.nnz_jac - (outage >= 0 ? 8 + 8 * rm : 0) + (cart ? 2 * int64_t(T.nb) : 0);
   d->nnz_hess = T.nnz_hess - (outage >= 0 ? 4 * rm : 0);
@@ -235,6 +276,8 @@ void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,
       for (int j : S[i]) jc->push_back(nb + j);
       for (int g = T.gen_ptr[i]; g < T.gen_ptr[i + 1]; ++g)
         jc->push_back(2 * nb + (blk ? ng : 0) + T.gen_list[g]);
+      for (int k = 0; k < T.sl.ns; ++k)  // slack columns of this row, blocks in order
+        if (T.sl.row[k] == blk) jc->push_back(2 * nb + 2 * ng + k * nb + i);
       jp->push_back(int32_t(jc->size()));
     }
   }
@@ -274,6 +317,10 @@ void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,
     hp->push_back(int32_t(hc->size()));
   }
   for (int k = 0; k < ng; ++k) hp->push_back(int32_t(hc->size()));
+  for (int q = 0; q < T.sl.ns * nb; ++q) {  // slack rows: the diagonal
+    hc->push_back(2 * nb + 2 * ng + q);
+    hp->push_back(int32_t(hc->size()));
+  }
 }
 
 // Position of bus j in the ascending set {i} u N(i).
@@ -432,7 +479,7 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
     const int d = T.be_ptr[i + 1] - T.be_ptr[i];
     // staged entries of the bus: J P and Q rows, H theta row, H v row
     const int a = T.acnt[i].x, lo = T.acnt[i].y, g = T.gen_ptr[i + 1] - T.gen_ptr[i];
-    const int st = 2 * (2 * a + g) + (lo + 1) + (a + lo + 1);
+    const int st = 2 * (2 * a + g + T.sl.nsp) + (lo + 1) + (a + lo + 1);
     if (d > caps.be || st > caps.stage)
       return fail(ACOPF_EINVAL, "bus " + std::to_string(i) + " has " + std::to_string(d) +
                                     " branch ends and " + std::to_string(st) +
@@ -455,7 +502,7 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
     Tile tl{};
     tl.kind_aux = (c << 2) | TILE_GEN;
     tl.a0 = c * kGenChunk;
-    tl.a1 = std::min(T.ng, (c + 1) * kGenChunk);
+    tl.a1 = std::min(T.ng + T.sl.ns * T.nb, (c + 1) * kGenChunk);
     S->tiles.push_back(tl);
   }
   S->counts[1] = int(S->tiles.size()) - S->counts[0];
@@ -559,6 +606,7 @@ int upload_base(Base* B) {
   nd.jflow = T.jflow;
   nd.hpg = T.hpg;
   nd.qoff = T.rows[0].y - T.rows[0].x;
+  nd.sl = T.sl;
   B->d_tiles = static_cast<Tile*>(at(9));
   B->d_work = static_cast<WorkItem*>(at(10));
   B->d_net = static_cast<NetDev*>(at(13));
@@ -584,26 +632,34 @@ const char* acopf_last_error(void) { return t_err.c_str(); }
 
 int acopf_version(void) { return 10000; }
 
-static bool form_ok(int32_t form) { return form == ACOPF_POLAR || form == ACOPF_CARTESIAN; }
+static acopf_net_opts form_opts(int32_t form) {
+  acopf_net_opts o{};
+  o.form = form;
+  return o;
+}
 
 int acopf_pattern_host(const acopf_net_desc* desc, int32_t outage, acopf_dims* dims,
                        int32_t* jac_rowptr, int32_t* jac_col, int32_t* hess_rowptr,
                        int32_t* hess_col) {
-  return acopf_pattern_host_form(desc, ACOPF_POLAR, outage, dims, jac_rowptr, jac_col,
-                                 hess_rowptr, hess_col);
+  return acopf_pattern_host_opts(desc, nullptr, outage, dims, jac_rowptr, jac_col, hess_rowptr,
+                                 hess_col);
 }
 
 int acopf_pattern_host_form(const acopf_net_desc* desc, int32_t form, int32_t outage,
                             acopf_dims* dims, int32_t* jac_rowptr, int32_t* jac_col,
                             int32_t* hess_rowptr, int32_t* hess_col) {
-  if (!form_ok(form)) return fail(ACOPF_EINVAL, "form must be ACOPF_POLAR or ACOPF_CARTESIAN");
+  const acopf_net_opts o = form_opts(form);
+  return acopf_pattern_host_opts(desc, &o, outage, dims, jac_rowptr, jac_col, hess_rowptr,
+                                 hess_col);
+}
+
+int acopf_pattern_host_opts(const acopf_net_desc* desc, const acopf_net_opts* opts,
+                            int32_t outage, acopf_dims* dims, int32_t* jac_rowptr,
+                            int32_t* jac_col, int32_t* hess_rowptr, int32_t* hess_col) {
   try {
     Topology T;
-    int rc = build_topology(desc, &T);
+    int rc = build_topology(desc, opts, &T);
     if (rc) return rc;
-    T.form = form;
-    if (form == ACOPF_CARTESIAN && 2 * int64_t(T.nb) + T.nnz_jac >= INT_MAX)
-      return fail(ACOPF_EINVAL, "pattern exceeds 2^31 entries");
     int32_t p = -1, q = -1, rm = 0;
     if (outage >= 0) {
       rc = outage_info(T, outage, &p, &q, &rm);
@@ -634,20 +690,22 @@ int acopf_pattern_host_form(const acopf_net_desc* desc, int32_t form, int32_t ou
 }
 
 int acopf_net_create(const acopf_net_desc* desc, acopf_net* out) {
-  return acopf_net_create_form(desc, ACOPF_POLAR, out);
+  return acopf_net_create_opts(desc, nullptr, out);
 }
 
 int acopf_net_create_form(const acopf_net_desc* desc, int32_t form, acopf_net* out) {
+  const acopf_net_opts o = form_opts(form);
+  return acopf_net_create_opts(desc, &o, out);
+}
+
+int acopf_net_create_opts(const acopf_net_desc* desc, const acopf_net_opts* opts,
+                          acopf_net* out) {
   if (!out) return fail(ACOPF_EINVAL, "null output handle");
   *out = nullptr;
-  if (!form_ok(form)) return fail(ACOPF_EINVAL, "form must be ACOPF_POLAR or ACOPF_CARTESIAN");
   try {
     auto B = std::make_shared<Base>();
-    int rc = build_topology(desc, &B->topo);
+    int rc = build_topology(desc, opts, &B->topo);
     if (rc) return rc;
-    B->topo.form = form;
-    if (form == ACOPF_CARTESIAN && 2 * int64_t(B->topo.nb) + B->topo.nnz_jac >= INT_MAX)
-      return fail(ACOPF_EINVAL, "pattern exceeds 2^31 entries");
     rc = upload_base(B.get());
     if (rc) return rc;
     std::unique_ptr<acopf_net_s> net(new acopf_net_s());

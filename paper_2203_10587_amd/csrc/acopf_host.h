@@ -15,6 +15,7 @@ namespace acopf {
 struct Topology {
   int32_t nb = 0, nl = 0, ng = 0, nchunks = 1;
   int32_t form = ACOPF_POLAR;  // ACOPF_POLAR or ACOPF_CARTESIAN
+  SlackDev sl{};               // slack blocks (their columns follow Qg)
   double base = 100.0;
   std::vector<int2> ft;
   std::vector<BranchY> y;
@@ -69,7 +70,7 @@ namespace acopf {
 extern thread_local std::string t_err;
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
-int build_topology(const acopf_net_desc* d, Topology* T);
+int build_topology(const acopf_net_desc* d, const acopf_net_opts* o, Topology* T);
 int outage_info(const Topology& T, int32_t l, int32_t* p, int32_t* q, int32_t* rm);
 void fill_dims(const Topology& T, int32_t outage, int32_t rm, acopf_dims* d);
 void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,

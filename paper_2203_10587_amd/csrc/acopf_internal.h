@@ -17,7 +17,8 @@
 //             after another, the workgroup stores the row segments with
 //             consecutive lanes on consecutive entries.  The tile also writes
 //             the flow-limit rows of the branches whose from-bus it owns.
-//   gen tile  a fixed chunk of generators: f, grad f, the Pg diagonal of H
+//   gen tile  a fixed chunk of cost items (the generators, then the slack
+//             variables of a net that has them): f, grad f, the Pg diagonal of H
 #pragma once
 
 #include <cstdint>
@@ -63,6 +64,17 @@ struct WorkItem {
   int32_t jhi, hvhi, hthi, ahi;
 };
 
+// Feasibility slack blocks of a network (at most 6: dP+, dP-, dQ+, dQ-, Pl,
+// Ql), each nb variables after Qg.  Block k: balance row row[k] (0 active,
+// 1 reactive) with coefficient coef[k], penalty c2[k] (B s)^2 + c1[k] B s.
+// nsp blocks go to each active row (the same number to each reactive row).
+constexpr int kMaxSlack = 6;
+struct SlackDev {
+  int32_t ns, nsp;
+  int32_t row[kMaxSlack];
+  double coef[kMaxSlack], c2[kMaxSlack], c1[kMaxSlack];
+};
+
 // Admittances of one branch (pi model, from-side ideal transformer).
 struct BranchY {
   double gff, bff, gft, bft, gtf, btf, gtt, btt;
@@ -85,6 +97,7 @@ struct NetDev {
   int32_t jflow;            // base start of the flow rows in J
   int32_t hpg;              // base start of the Pg rows in H
   int32_t qoff;             // J Q row of a bus minus its P row
+  SlackDev sl;              // slack blocks (sl.ns = 0: none)
 };
 
 // One evaluation instance.  Offsets index the packed buffers of Bufs.  An

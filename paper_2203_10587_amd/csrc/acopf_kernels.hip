@@ -813,6 +813,10 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
           cbP = (bd.z * vi * vi - pg) + bd.x;
           cbQ = (-bd.w * vi * vi - qg) + bd.y;
         }
+        for (int k = 0; k < N.sl.ns; ++k) {  // slack blocks: +-1 in their row
+          const double t = N.sl.coef[k] * x[2 * nb + 2 * N.ng + k * nb + i];
+          if (N.sl.row[k] == 0) cbP += t; else cbQ += t;
+        }
       }
     }
     if constexpr (R::V) {
@@ -847,6 +851,10 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       } else {
         jvP = 2.0 * bd.z * vi * dir[nb + i] - dpg;
         jvQ = -2.0 * bd.w * vi * dir[nb + i] - dqg;
+      }
+      for (int k = 0; k < N.sl.ns; ++k) {
+        const double t = N.sl.coef[k] * dir[2 * nb + 2 * N.ng + k * nb + i];
+        if (N.sl.row[k] == 0) jvP += t; else jvQ += t;
       }
     }
   }
@@ -898,6 +906,13 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       for (int g = 0; g < ngb; ++g) {
         stg[sP + rw.x + 2 * ac.x + g] = -1.0;
         stg[sQ + rw.x + 2 * ac.x + g] = -1.0;
+      }
+      // slack columns after the generators, blocks in order within each row
+      for (int k = 0, qp = 0, qq = 0; k < N.sl.ns; ++k) {
+        if (N.sl.row[k] == 0)
+          stg[sP + rw.x + 2 * ac.x + ngb + qp++] = N.sl.coef[k];
+        else
+          stg[sQ + rw.x + 2 * ac.x + ngb + qq++] = N.sl.coef[k];
       }
     }
   }
@@ -979,7 +994,9 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
 
 // ---------------------------------------------------------------------------
 // gen tile: objective, its gradient, the Pg diagonal of H, the Pg/Qg part of
-// the VJP, and this chunk's fixed-tree partial sum of the cost
+// the VJP, and this chunk's fixed-tree partial sum of the cost.  Its items
+// are the generators, then (if the net has them) the slack variables, each
+// with its own penalty term, gradient, H diagonal and VJP/HVP entries.
 
 template <unsigned WHAT, int WG>
 __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k0, int k1,
@@ -1002,7 +1019,23 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
   for (int t = tid; t < kGenChunk; t += WG) {
     const int k = k0 + t;
     double term = 0.0;
-    if (k < k1) {
+    if (k < k1 && k >= ng) {  // slack variable j of block s at bus i
+      const int j = k - ng, s = j / nb, i = j - s * nb;
+      const int col = 2 * nb + 2 * ng + j;
+      const double c2 = N.sl.c2[s], c1 = N.sl.c1[s];
+      const double p = Bm * x[col];
+      const double grad = Bm * fma(2.0 * c2, p, c1);
+      if (gradf) put(&gradf[col], grad);
+      if (hess) put(&hess[hpg + k], sigma * (2.0 * c2 * Bm * Bm));
+      if constexpr (DO_V) {
+        const double* w = B.wc + I.co;
+        put(&B.u[I.xo + col], fma(wf, grad, N.sl.coef[s] * w[N.sl.row[s] * nb + i]));
+      }
+      if constexpr (DO_HV) {
+        put(&B.out[I.xo + col], sigma * (2.0 * c2 * Bm * Bm) * B.dir[I.xo + col]);
+      }
+      if (fout) term = fma(c2, p, c1) * p;
+    } else if (k < k1) {
       const double pg = x[2 * nb + k];
       const double c2 = N.gen_c2[k], c1 = N.gen_c1[k];
       const double p = Bm * pg;

@@ -1,12 +1,16 @@
 // Host-only check of the bus-tile work lists: every position a work item or a
 // bus lane stores must hold the column the CSR pattern puts there, and every
 // Jacobian and Hessian entry before the flow and generator blocks must be
-// stored exactly once per evaluation.  Compiled by tests/test_tiler.py.
+// stored exactly once per evaluation, and the gen tiles must cover every
+// cost item (generators, then slack variables) once.  Compiled by
+// tests/test_tiler.py.
 #include "acopf_host.cpp"
 #include <cstdio>
-extern "C" int tile_check(const acopf_net_desc* d, int tile_be) {
+extern "C" int tile_check(const acopf_net_desc* d, int tile_be, unsigned slacks) {
   Topology T;
-  if (build_topology(d, &T)) {
+  acopf_net_opts o{};
+  o.slacks = slacks;
+  if (build_topology(d, &o, &T)) {
     printf("topology: %s\n", t_err.c_str());
     return 1;
   }
@@ -75,6 +79,20 @@ extern "C" int tile_check(const acopf_net_desc* d, int tile_be) {
         jcnt[pg]++;
         jcnt[pg + qoff]++;
       }
+      // slack columns after the generators: the P-row blocks, then (at
+      // +qoff) the Q-row blocks, each in block order
+      for (int r = 0; r < 2; ++r) {
+        int q = 0;
+        for (int k = 0; k < T.sl.ns; ++k) {
+          if (T.sl.row[k] != r) continue;
+          const int ps = rw.x + 2 * a + g + q + (r ? qoff : 0);
+          chk(jc[ps] == 2 * nb + 2 * T.ng + k * nb + i, "J slack", i, ps);
+          chk(ps < jp[(r ? nb : 0) + i + 1], "J slack row", i, ps);
+          jcnt[ps]++;
+          ++q;
+        }
+        chk(q == T.sl.nsp, "slacks per row", i, q);
+      }
       chk(hc[rw.z + blw] == i && hc[rw.w + blw] == i && hc[rw.w + a + blw] == nb + i, "H diag", i, rw.z);
       hcnt[rw.z + blw]++;
       hcnt[rw.w + blw]++;
@@ -83,6 +101,17 @@ extern "C" int tile_check(const acopf_net_desc* d, int tile_be) {
   }
   for (int p = 0; p < T.jflow; ++p) chk(jcnt[p] == 1, "J coverage", p, jcnt[p]);
   for (int p = 0; p < T.hpg; ++p) chk(hcnt[p] == 1, "H coverage", p, hcnt[p]);
+  {
+    int next = 0;
+    for (int ti = S.counts[0]; ti < S.counts[0] + S.counts[1]; ++ti) {
+      const Tile& tl = S.tiles[ti];
+      chk(tl.a0 == next && tl.a1 - tl.a0 <= kGenChunk, "gen tile items", tl.a0, tl.a1);
+      chk((tl.kind_aux >> 2) == ti - S.counts[0], "gen tile chunk", ti, tl.kind_aux);
+      next = tl.a1;
+    }
+    chk(next == T.ng + T.sl.ns * nb, "gen tiles end", next, T.ng + T.sl.ns * nb);
+    chk(S.counts[1] == T.nchunks, "gen tile count", S.counts[1], T.nchunks);
+  }
   if (bad) {
     printf("tile_be %d: %d tiles, %zu work items, %d failures\n", tile_be, S.counts[0],
            S.work.size(), bad);

@@ -140,3 +140,38 @@ def test_form_validation():
     b = A.acopf_pattern_host_form(g, A.ACOPF_POLAR)
     for x, y in zip(a[1:], b[1:]):
         np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("slacks", [1, 2, 3])
+@pytest.mark.parametrize("cart", [False, True])
+def test_host_pattern_slacks_bit_exact(slacks, cart):
+    """Slack blocks: each balance row gains its slack columns after the
+    generators; H gains one diagonal entry per slack column."""
+    from oracle import slacks as OS
+    for name, g in _grids():
+        if name not in ("ring9", "rand30", "nogen", "isolated"):
+            continue
+        spec = OS.Spec(imbalance=bool(slacks & 1), loadloss=bool(slacks & 2), cartesian=cart)
+        opts = A.net_opts(A.ACOPF_CARTESIAN if cart else A.ACOPF_POLAR, slacks)
+        dims, jp, jc, hp, hc = A.acopf_pattern_host_opts(g, opts)
+        for a, b in zip((jp, jc, hp, hc), OS.pattern(O.prepare(g), spec)):
+            np.testing.assert_array_equal(a, b)
+        ns = len(OS.kinds(spec))
+        assert (dims.n, dims.m) == (g.n + ns * g.nbus, g.m + (g.nbus if cart else 0))
+        if g.nbranch:
+            l = g.nbranch // 2
+            dims, jp, jc, hp, hc = A.acopf_pattern_host_opts(g, opts, l)
+            for a, b in zip((jp, jc, hp, hc), OS.pattern(O.prepare(S.remove_branch(g, l)), spec)):
+                np.testing.assert_array_equal(a, b)
+
+
+def test_opts_validation():
+    g = S.config0(0)[0]
+    for bad in (A.net_opts(3, 0), A.net_opts(0, 4), A.net_opts(0, 1, (float("nan"), 0.0))):
+        with pytest.raises(A.AcopfError) as ei:
+            A.acopf_pattern_host_opts(g, bad)
+        assert ei.value.code == A.ACOPF_EINVAL
+    a = A.acopf_pattern_host(g)
+    b = A.acopf_pattern_host_opts(g, None)
+    for x, y in zip(a[1:], b[1:]):
+        np.testing.assert_array_equal(x, y)

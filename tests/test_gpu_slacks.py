@@ -1,0 +1,251 @@
+"""GPU parity of the feasibility slack variables (load loss, power
+imbalance): the HIP path through the C ABI against the slack oracle, in both
+representations, under the row-scaled relative rule (tol 1e-12) with CSR
+patterns bit-exact.  Single nets on irregular grids, the products (VJP, HVP,
+JVP), N-1 children, batches (bitwise equal to the plain path at every tile
+size), the 2,000-bus grid, and the refusal to draw iterates."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import slacks as OS
+from paper_2203_10587_amd import synth as S
+from tests.parity import assert_close, log
+from tests.test_gpu_parity import small_cases
+
+pytestmark = pytest.mark.gpu
+
+COSTS = dict(imb_cost=(0.4, 30.0), loss_cost=(1.5, 90.0))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dev(a):
+    return _torch().as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def nan(n):
+    torch = _torch()
+    return torch.full((int(n),), np.nan, dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def spec_of(slacks, cart):
+    return OS.Spec(imbalance=bool(slacks & 1), loadloss=bool(slacks & 2), cartesian=cart, **COSTS)
+
+
+def make_net(A, g, slacks, cart):
+    opts = A.net_opts(A.ACOPF_CARTESIAN if cart else A.ACOPF_POLAR, slacks, COSTS["imb_cost"],
+                      COSTS["loss_cost"])
+    return A.acopf_net_create_opts(g, opts)
+
+
+class It:
+    def __init__(self, x, lam, sigma):
+        self.x, self.lam, self.sigma = x, lam, sigma
+
+
+def draw(g, spec, rng, sigma=1.0):
+    """Base iterate of the representation, slacks U(0, 0.3), lambda N(0,1)."""
+    base = S.draw_iterate_cartesian(g, rng, sigma) if spec.cartesian else S.draw_iterate(g, rng, sigma)
+    ns = len(OS.kinds(spec)) * g.nbus
+    x = np.concatenate([base.x, rng.uniform(0.0, 0.3, ns)])
+    m = g.m + (g.nbus if spec.cartesian else 0)
+    return It(x, rng.standard_normal(m), sigma)
+
+
+def oracle_ref(g, spec, it, w_f=None, w_c=None):
+    mdl = O.prepare(g)
+    out = OS.evaluate(mdl, spec, it.x, it.sigma, it.lam)
+    ref = {"mdl": mdl, "out": out, "scale": OS.scales(mdl, spec, it.x, out)}
+    if w_c is not None:
+        ref["u"] = OS.vjp(mdl, spec, it.x, w_f, w_c)
+        ref["u_scale"] = OS.vjp_scale(mdl, spec, it.x, w_f, w_c)
+    return ref
+
+
+def compare(tag, gpu, ref):
+    out, sc = ref["out"], ref["scale"]
+    r = {"f": assert_close(tag + ".f", [gpu["f"]], [out["f"]], [sc["f"]])}
+    for k in ("grad_f", "c", "jac_val", "hess_val"):
+        r[k] = assert_close(f"{tag}.{k}", gpu[k], out[k], sc[k])
+    if "u" in gpu:
+        r["u"] = assert_close(tag + ".u", gpu["u"], ref["u"], ref["u_scale"])
+    return r
+
+
+def gpu_eval(A, net, it, w_f=None, w_c=None, separate=True):
+    x, lam = dev(it.x), dev(it.lam)
+    f, gf, c, jv, hv = nan(1), nan(net.n), nan(net.m), nan(net.nnz_jac), nan(net.nnz_hess)
+    if separate:
+        A.acopf_eval_f_g(net, x, f, gf, c)
+        A.acopf_eval_jac(net, x, jv)
+        A.acopf_eval_hess(net, x, it.sigma, lam, hv)
+    else:
+        A.acopf_eval_all(net, x, it.sigma, lam, f, gf, c, jv, hv)
+    out = {"f": float(host(f)[0]), "grad_f": host(gf), "c": host(c), "jac_val": host(jv),
+           "hess_val": host(hv)}
+    if w_c is not None:
+        u = nan(net.n)
+        A.acopf_vjp(net, x, w_f, dev(w_c), u)
+        out["u"] = host(u)
+    _torch().cuda.synchronize()
+    return out
+
+
+def products(A, net, g, spec, it, d):
+    hv, jv = nan(net.n), nan(net.m)
+    A.acopf_hvp(net, dev(it.x), it.sigma, dev(it.lam), dev(d), hv)
+    A.acopf_jvp(net, dev(it.x), dev(d), jv)
+    mdl = O.prepare(g)
+    H = OS.hessian_matrix(mdl, spec, it.x, it.sigma, it.lam)
+    J = OS.jacobian_matrix(mdl, spec, it.x)
+    out = OS.evaluate(mdl, spec, it.x)
+    sj = OS.scales(mdl, spec, it.x, out)["jac_val"]
+    jp, jc, _, _ = OS.pattern(mdl, spec)
+    rows = np.repeat(np.arange(len(jp) - 1), np.diff(jp))
+    jscale = np.bincount(rows, weights=sj * np.abs(d[jc]), minlength=len(jp) - 1)
+    assert_close("jvp", host(jv), J @ d, jscale)
+    Habs = abs(H).tocsr()
+    rowmax = Habs.max(axis=1).toarray().ravel()
+    hscale = rowmax * ((Habs > 0).astype(float) @ np.abs(d))
+    assert_close("hvp", host(hv), H @ d, hscale)
+
+
+CASES = [(name, g, sl, cart) for (name, g), (sl, cart) in
+         zip(list(small_cases()), [(3, False), (1, True), (2, False), (3, True), (3, False),
+                                   (1, False), (2, True), (3, False), (3, True)])]
+
+
+@pytest.mark.parametrize("name,g,slacks,cart", CASES,
+                         ids=[f"{c[0]}-s{c[2]}-{'cart' if c[3] else 'polar'}" for c in CASES])
+def test_slack_plain_parity(gpu_lib, name, g, slacks, cart):
+    from paper_2203_10587_amd import acopf as A
+    log(f"[slack parity] {name} slacks={slacks} cart={cart} nb={g.nbus}")
+    spec = spec_of(slacks, cart)
+    rng = np.random.default_rng(31)
+    it = draw(g, spec, rng, 0.7)
+    w_c = rng.standard_normal(len(it.lam))
+    ref = oracle_ref(g, spec, it, 1.2, w_c)
+    net = make_net(A, g, slacks, cart)
+    assert net.n == len(it.x) and net.m == len(it.lam)
+    for a, b in zip(A.acopf_pattern(net), OS.pattern(ref["mdl"], spec)):
+        np.testing.assert_array_equal(a, b)
+    out = gpu_eval(A, net, it, 1.2, w_c)
+    r = compare(name, out, ref)
+    log(f"   worst error / tolerance: {max(r.values()):.3e}")
+    fused = gpu_eval(A, net, it, separate=False)
+    for k in ("grad_f", "c", "jac_val", "hess_val"):
+        np.testing.assert_array_equal(fused[k], out[k], err_msg=k)
+    assert fused["f"] == out["f"]
+    products(A, net, g, spec, it, rng.standard_normal(net.n))
+
+
+@pytest.mark.parametrize("cart", [False, True])
+def test_slack_outage_parity(gpu_lib, cart):
+    from paper_2203_10587_amd import acopf as A
+    g = S.random_grid(60, 95, 20, seed=5, parallel=3)
+    spec = spec_of(3, cart)
+    base = make_net(A, g, 3, cart)
+    pairs = {}
+    for l in range(g.nbranch):
+        pairs.setdefault(frozenset((int(g.br_from[l]), int(g.br_to[l]))), []).append(l)
+    par = [l for ls in pairs.values() if len(ls) > 1 for l in ls]
+    for l in sorted(set([0, g.nbranch - 1] + par[:2])):
+        log(f"[slack outage] cart={cart} branch {l}")
+        g2 = S.remove_branch(g, l)
+        rng = np.random.default_rng(200 + l)
+        it = draw(g2, spec, rng, 0.9)
+        w_c = rng.standard_normal(len(it.lam))
+        ref = oracle_ref(g2, spec, it, 0.6, w_c)
+        child = A.acopf_net_create_outage(base, l)
+        for a, b in zip(A.acopf_pattern(child), OS.pattern(ref["mdl"], spec)):
+            np.testing.assert_array_equal(a, b)
+        compare(f"outage-{l}", gpu_eval(A, child, it, 0.6, w_c), ref)
+        products(A, child, g2, spec, it, rng.standard_normal(child.n))
+        child.close()
+
+
+def test_slack_2000_bus_parity(gpu_lib):
+    from paper_2203_10587_amd import acopf as A
+    g = S.rgg_grid(2000, 3000, seed=7)
+    spec = spec_of(3, False)
+    rng = np.random.default_rng(5)
+    it = draw(g, spec, rng)
+    w_c = rng.standard_normal(len(it.lam))
+    ref = oracle_ref(g, spec, it, 0.9, w_c)
+    net = make_net(A, g, 3, False)
+    r = compare("rgg2000", gpu_eval(A, net, it, 0.9, w_c), ref)
+    log(f"[slack 2000] worst error / tolerance: {max(r.values()):.3e}")
+
+
+@pytest.mark.parametrize("cart", [False, True])
+def test_slack_batch_bitwise(gpu_lib, cart):
+    """A slack base and N-1 children in one batch: bitwise equal to the plain
+    path at every tile size, with the batched products equal to the plain
+    ones; f, whose reduction tree now spans generators and slacks, too."""
+    torch = _torch()
+    from paper_2203_10587_amd import acopf as A
+    g = S.rgg_grid(700, 910, seed=11)
+    spec = spec_of(3, cart)
+    base = make_net(A, g, 3, cart)
+    outs = [3, 400, g.nbranch - 1]
+    nets = [base] + [A.acopf_net_create_outage(base, l) for l in outs]
+    grids = [g] + [S.remove_branch(g, l) for l in outs]
+    rng = np.random.default_rng(9)
+    its = [draw(x, spec, rng, 0.5 + 0.1 * k) for k, x in enumerate(grids)]
+    plain = [gpu_eval(A, n, it) for n, it in zip(nets, its)]
+    compare("batch-base", plain[0], oracle_ref(g, spec, its[0]))
+    for tile_be in (64, 128, 256, 512):
+        b = A.acopf_batch_create(nets, tile_be=tile_be)
+        nx, nc = int(b.x_off[-1]), int(b.c_off[-1])
+        x, lam = np.empty(nx), np.empty(nc)
+        for k, it in enumerate(its):
+            x[b.x_off[k]:b.x_off[k + 1]] = it.x
+            lam[b.c_off[k]:b.c_off[k + 1]] = it.lam
+        X, L = dev(x), dev(lam)
+        sig = dev([it.sigma for it in its])
+        f, gf, c = nan(b.count), nan(nx), nan(nc)
+        jv, hv = nan(b.j_off[-1]), nan(b.h_off[-1])
+        A.acopf_batch_eval(b, X, sig, L, f, gf, c, jv, hv, A.ACOPF_ALL)
+        torch.cuda.synchronize()
+        for k in range(b.count):
+            s = lambda t, o: host(t)[int(o[k]):int(o[k + 1])]
+            got = {"grad_f": s(gf, b.x_off), "c": s(c, b.c_off), "jac_val": s(jv, b.j_off),
+                   "hess_val": s(hv, b.h_off)}
+            for key, v in got.items():
+                np.testing.assert_array_equal(v, plain[k][key], err_msg=f"{tile_be} {k} {key}")
+            assert float(host(f)[k]) == plain[k]["f"]
+        if tile_be == 256:
+            d = rng.standard_normal(nx)
+            ho, jo = nan(nx), nan(nc)
+            A.acopf_batch_hvp(b, X, sig, L, dev(d), ho)
+            A.acopf_batch_jvp(b, X, dev(d), jo)
+            torch.cuda.synchronize()
+            for k in range(b.count):
+                hk, jk = nan(nets[k].n), nan(nets[k].m)
+                dk = dev(d[b.x_off[k]:b.x_off[k + 1]])
+                A.acopf_hvp(nets[k], dev(its[k].x), its[k].sigma, dev(its[k].lam), dk, hk)
+                A.acopf_jvp(nets[k], dev(its[k].x), dk, jk)
+                np.testing.assert_array_equal(host(ho)[b.x_off[k]:b.x_off[k + 1]], host(hk))
+                np.testing.assert_array_equal(host(jo)[b.c_off[k]:b.c_off[k + 1]], host(jk))
+        b.close()
+
+
+def test_slack_draw_refused(gpu_lib):
+    torch = _torch()
+    from paper_2203_10587_amd import acopf as A
+    g = S.random_grid(12, 20, 5, seed=1, parallel=2)
+    net = make_net(A, g, 2, False)
+    b = A.acopf_batch_create([net])
+    seeds = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(A.AcopfError) as ei:
+        A.acopf_batch_draw_iterates(b, 0, 1, seeds, (0.0, 1.0, -1.0, 1.0), nan(net.n), nan(net.m))
+    assert ei.value.code == A.ACOPF_EINVAL
+    b.close()

@@ -30,7 +30,7 @@ def checker(tmp_path_factory):
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     lib = C.CDLL(out)
-    lib.tile_check.argtypes = [C.POINTER(A.acopf_net_desc), C.c_int]
+    lib.tile_check.argtypes = [C.POINTER(A.acopf_net_desc), C.c_int, C.c_uint]
     return lib
 
 
@@ -46,4 +46,15 @@ GRIDS = {
 @pytest.mark.parametrize("tile_be", [64, 128, 256, 512])
 def test_positions_and_coverage(checker, name, tile_be):
     d = A._Desc(GRIDS[name]())
-    assert checker.tile_check(C.byref(d.desc), tile_be) == 0
+    assert checker.tile_check(C.byref(d.desc), tile_be, 0) == 0
+
+
+@pytest.mark.parametrize("slacks", [1, 2, 3])
+@pytest.mark.parametrize("tile_be", [64, 256, 512])
+def test_positions_with_slacks(checker, slacks, tile_be):
+    """Slack columns (imbalance 1, load loss 2, both 3) lengthen the balance
+    rows: every position still holds its pattern column, and the gen tiles
+    cover the generators and the slack variables once."""
+    for name in ("parallel60", "rgg2000"):
+        d = A._Desc(GRIDS[name]())
+        assert checker.tile_check(C.byref(d.desc), tile_be, slacks) == 0, name
