@@ -64,18 +64,20 @@ def count(w):
     return len(w["iterates"])
 
 
-def algorithmic_bytes(w, form=0):
+def algorithmic_bytes(w, opts=None):
     """Bytes the method must move per full evaluation of the batch: inputs
     x (8n), lambda (8m), sigma (8); outputs 8 (1 + n + m + nnzJ + nnzH); the
     network primitives (56 B per branch, 32 B per bus, 28 B per generator)
-    counted once per distinct network.  `form` selects the representation
-    (the cartesian one has nb more rows and 2 nb more Jacobian entries)."""
+    counted once per distinct network.  `opts` (net options) selects the
+    model variant, whose sizes differ: the cartesian representation has nb
+    more rows and 2 nb more Jacobian entries, each slack block nb more
+    variables, Jacobian and Hessian entries."""
     from paper_2203_10587_amd import acopf as A
     tot = 0
     nets = set()
     for k in range(count(w)):
         g = w["base"] if w["kind"] == "outage" else w["grids"][k]
-        d, *_ = A.acopf_pattern_host_form(g, form, int(w["outages"][k]) if w["kind"] == "outage" else -1)
+        d, *_ = A.acopf_pattern_host_opts(g, opts, int(w["outages"][k]) if w["kind"] == "outage" else -1)
         tot += 8 * d.n + 8 * d.m + 8 + 8 * (1 + d.n + d.m + d.nnz_jac + d.nnz_hess)
         key = id(g)
         if key not in nets:
@@ -161,6 +163,67 @@ def served(seconds: float, rate: float = 2000.0, budget_gb: float = 8.0, log_pro
     return st
 
 
+def variant_bench(A, w, sched, sigma, nbus_total, args, dev, stream, opts, label):
+    """The workload's batch built with other net options, timed like the
+    headline step (same schedule, steps and warmup; all outputs)."""
+    import torch
+    from paper_2203_10587_amd import synth as S
+    K = count(w)
+    if w["kind"] == "outage":
+        vbase = A.acopf_net_create_opts(w["base"], opts)
+        vnets = [A.acopf_net_create_outage(vbase, int(l)) for l in w["outages"]]
+    else:
+        vbase = None
+        vnets = [A.acopf_net_create_opts(g, opts) for g in w["grids"]]
+    vb = A.acopf_batch_create(vnets, **sched)
+    rng = np.random.default_rng(2203)
+    nblk = ((4 if opts.slacks & A.ACOPF_SLACK_IMBALANCE else 0)
+            + (2 if opts.slacks & A.ACOPF_SLACK_LOADLOSS else 0))
+    vx = torch.empty(int(vb.x_off[-1]), dtype=torch.float64)
+    vl = torch.empty(int(vb.c_off[-1]), dtype=torch.float64)
+    for k in range(K):
+        g = instance_grid(w, k)
+        if opts.form == A.ACOPF_CARTESIAN:
+            it = S.draw_iterate_cartesian(g, rng, w["iterates"][k].sigma)
+            xk, lk = it.x, it.lam
+        else:
+            xk, lk = w["iterates"][k].x, w["iterates"][k].lam
+        ns = nblk * g.nbus
+        vx[vb.x_off[k]:vb.x_off[k + 1]] = torch.from_numpy(
+            np.concatenate([xk, rng.uniform(0.0, 0.05, ns)]))
+        vl[vb.c_off[k]:vb.c_off[k + 1]] = torch.from_numpy(lk)
+    vx, vl = vx.to(dev), vl.to(dev)
+    outs = [torch.empty(n, dtype=torch.float64, device=dev)
+            for n in (K, int(vb.x_off[-1]), int(vb.c_off[-1]), int(vb.j_off[-1]),
+                      int(vb.h_off[-1]))]
+
+    def vstep():
+        A.acopf_batch_eval(vb, vx, sigma, vl, *outs, A.ACOPF_ALL, stream)
+
+    for _ in range(args.warmup):
+        vstep()
+    s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s_.record(stream)
+    for _ in range(args.steps):
+        vstep()
+    e_.record(stream)
+    torch.cuda.synchronize()
+    ms = s_.elapsed_time(e_) / args.steps
+    alg = algorithmic_bytes(w, opts)
+    res = {"model": label, "ms_per_step": ms, "value": nbus_total / (ms / 1e3),
+           "unit": "bus-evals/s", "algorithmic_bytes": alg,
+           "achieved_GBps": alg / (ms / 1e3) / 1e9, "frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    log(f"[bench] {label}: {ms:.4f} ms/step, {res['value']:.4e} bus-evals/s, frac {res['frac']:.3f}")
+    del outs, vx, vl
+    vb.close()
+    for n in vnets:
+        n.close()
+    if vbase is not None:
+        vbase.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,8 +235,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-cartesian", dest="cartesian", action="store_false",
-                    help="skip timing the workload in the power-balance-cartesian representation")
+    ap.add_argument("--no-variants", dest="variants", action="store_false",
+                    help="skip timing the workload in the cartesian representation and with slacks")
     ap.add_argument("--tile-be", type=int, default=0)
     ap.add_argument("--grid-mult", type=int, default=-1)
     ap.add_argument("--xcd", type=int, default=-1)
@@ -336,55 +399,17 @@ def main():
         log(f"[bench] coupled: {cp.rows} rows in {cms * 1e3:.1f} us")
         cp.close()
 
-    # the same workload in the power-balance-cartesian representation: its own
-    # nets and batch, seeded iterates x = [e; f; Pg; Qg], all outputs
-    cart = None
-    if args.cartesian:
-        from paper_2203_10587_amd import synth as S
-        if w["kind"] == "outage":
-            cbase = A.acopf_net_create_form(w["base"], A.ACOPF_CARTESIAN)
-            cnets = [A.acopf_net_create_outage(cbase, int(l)) for l in w["outages"]]
-        else:
-            cnets = [A.acopf_net_create_form(g, A.ACOPF_CARTESIAN) for g in w["grids"]]
-        cb = A.acopf_batch_create(cnets, **sched)
-        rng = np.random.default_rng(2203)
-        cx = torch.empty(int(cb.x_off[-1]), dtype=torch.float64)
-        cl = torch.empty(int(cb.c_off[-1]), dtype=torch.float64)
-        for k in range(K):
-            it = S.draw_iterate_cartesian(instance_grid(w, k), rng, w["iterates"][k].sigma)
-            cx[cb.x_off[k]:cb.x_off[k + 1]] = torch.from_numpy(it.x)
-            cl[cb.c_off[k]:cb.c_off[k + 1]] = torch.from_numpy(it.lam)
-        cx, cl = cx.to(dev), cl.to(dev)
-        co = [torch.empty(n, dtype=torch.float64, device=dev)
-              for n in (K, int(cb.x_off[-1]), int(cb.c_off[-1]), int(cb.j_off[-1]),
-                        int(cb.h_off[-1]))]
-
-        def cstep():
-            A.acopf_batch_eval(cb, cx, sigma, cl, *co, A.ACOPF_ALL, stream)
-
-        for _ in range(args.warmup):
-            cstep()
-        cs_, ce_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        cs_.record(stream)
-        for _ in range(args.steps):
-            cstep()
-        ce_.record(stream)
-        torch.cuda.synchronize()
-        cms = cs_.elapsed_time(ce_) / args.steps
-        calg = algorithmic_bytes(w, A.ACOPF_CARTESIAN)
-        cart = {"form": "power-balance-cartesian", "ms_per_step": cms,
-                "value": nbus_total / (cms / 1e3), "unit": "bus-evals/s",
-                "algorithmic_bytes": calg, "achieved_GBps": calg / (cms / 1e3) / 1e9,
-                "frac": calg / (cms / 1e3) / 1e9 / HBM_PEAK_GBS}
-        log(f"[bench] cartesian: {cms:.4f} ms/step, {cart['value']:.4e} bus-evals/s, "
-            f"frac {cart['frac']:.3f}")
-        del co, cx, cl
-        cb.close()
-        for n in cnets:
-            n.close()
-        if w["kind"] == "outage":
-            cbase.close()
+    # the same workload in the other model variants: the power-balance-cartesian
+    # representation, and the polar one with both slack blocks (load loss and
+    # power imbalance); each has its own nets, batch and seeded iterates
+    cart = slk = None
+    if args.variants:
+        cart = variant_bench(A, w, sched, sigma, nbus_total, args, dev, stream,
+                             A.net_opts(A.ACOPF_CARTESIAN), "power-balance-cartesian")
+        slk = variant_bench(A, w, sched, sigma, nbus_total, args, dev, stream,
+                            A.net_opts(A.ACOPF_POLAR, A.ACOPF_SLACK_IMBALANCE | A.ACOPF_SLACK_LOADLOSS,
+                                       (0.0, 1000.0), (0.0, 1e4)),
+                            "polar + load loss + power imbalance")
 
     # plain path: the same kernels, one instance per launch, into the same buffers
     L = A.lib()
@@ -445,6 +470,7 @@ def main():
         "plain": plain,
         "coupled": coupled,
         "cartesian": cart,
+        "slacks": slk,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": alg, "kernel_ms": avg_ms},

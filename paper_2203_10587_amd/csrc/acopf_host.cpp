@@ -214,7 +214,9 @@ int build_topology(const acopf_net_desc* d, const acopf_net_opts* o, Topology* T
   T->hpg = int(hpg);
   T->nnz_jac = nnzj;
   T->nnz_hess = nnzh;
-  T->nchunks = std::max(1, int((ng + nslk + kGenChunk - 1) / kGenChunk));
+  T->gchunks = int((ng + kGenChunk - 1) / kGenChunk);
+  constexpr int64_t kSlackChunk = int64_t(kGenChunk) * kSlackPerSlot;
+  T->nchunks = std::max(1, T->gchunks + int((nslk + kSlackChunk - 1) / kSlackChunk));
   return ACOPF_OK;
 }
 
@@ -498,11 +500,20 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
   close(b0, T.nb);
   if (tiler_error) return fail(ACOPF_EINVAL, "internal: work item positions outside the tile");
   S->counts[0] = int(S->tiles.size());
+  // generator chunks of kGenChunk items, then slack chunks of kGenChunk *
+  // kSlackPerSlot items (item k >= ng is slack variable k - ng)
+  const int nitems = T.ng + T.sl.ns * T.nb;
   for (int c = 0; c < T.nchunks; ++c) {
     Tile tl{};
     tl.kind_aux = (c << 2) | TILE_GEN;
-    tl.a0 = c * kGenChunk;
-    tl.a1 = std::min(T.ng + T.sl.ns * T.nb, (c + 1) * kGenChunk);
+    if (c < T.gchunks) {
+      tl.a0 = c * kGenChunk;
+      tl.a1 = std::min(T.ng, (c + 1) * kGenChunk);
+    } else {
+      const int span = kGenChunk * kSlackPerSlot;
+      tl.a0 = std::min(nitems, T.ng + (c - T.gchunks) * span);
+      tl.a1 = std::min(nitems, tl.a0 + span);
+    }
     S->tiles.push_back(tl);
   }
   S->counts[1] = int(S->tiles.size()) - S->counts[0];

@@ -14,6 +14,7 @@ namespace acopf {
 // Host copy of a base network and everything derived from it.
 struct Topology {
   int32_t nb = 0, nl = 0, ng = 0, nchunks = 1;
+  int32_t gchunks = 0;  // generator chunks; slack chunks follow up to nchunks
   int32_t form = ACOPF_POLAR;  // ACOPF_POLAR or ACOPF_CARTESIAN
   SlackDev sl{};               // slack blocks (their columns follow Qg)
   double base = 100.0;

@@ -27,6 +27,7 @@
 namespace acopf {
 
 constexpr int kGenChunk = 256;   // generators per gen tile; fixes the f reduction tree
+constexpr int kSlackPerSlot = 8; // slack items per reduction slot: a slack chunk holds 2048
 constexpr uint32_t kNoSlot = 0xFFFFu;
 
 enum TileKind : int32_t { TILE_BUS = 1, TILE_GEN = 2 };

@@ -1016,47 +1016,53 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
   const double sigma = B.sigma ? B.sigma[I.k] : B.sigma_v;
   const double wf = B.wf ? B.wf[I.k] : B.wf_v;
   const int hpg = N.hpg - 4 * I.out_rm;
+  // a slack chunk gives each reduction slot kSlackPerSlot items, summed in
+  // item order; a generator chunk one
+  const int per = k0 >= ng ? kSlackPerSlot : 1;
   for (int t = tid; t < kGenChunk; t += WG) {
-    const int k = k0 + t;
     double term = 0.0;
-    if (k < k1 && k >= ng) {  // slack variable j of block s at bus i
-      const int j = k - ng, s = j / nb, i = j - s * nb;
-      const int col = 2 * nb + 2 * ng + j;
-      const double c2 = N.sl.c2[s], c1 = N.sl.c1[s];
-      const double p = Bm * x[col];
-      const double grad = Bm * fma(2.0 * c2, p, c1);
-      if (gradf) put(&gradf[col], grad);
-      if (hess) put(&hess[hpg + k], sigma * (2.0 * c2 * Bm * Bm));
-      if constexpr (DO_V) {
-        const double* w = B.wc + I.co;
-        put(&B.u[I.xo + col], fma(wf, grad, N.sl.coef[s] * w[N.sl.row[s] * nb + i]));
+    for (int r = 0; r < per; ++r) {
+      const int k = k0 + t + r * kGenChunk;
+      if (k >= k1) break;
+      if (k >= ng) {  // slack variable j of block s at bus i
+        const int j = k - ng, s = j / nb, i = j - s * nb;
+        const int col = 2 * nb + 2 * ng + j;
+        const double c2 = N.sl.c2[s], c1 = N.sl.c1[s];
+        const double p = Bm * x[col];
+        const double grad = Bm * fma(2.0 * c2, p, c1);
+        if (gradf) put(&gradf[col], grad);
+        if (hess) put(&hess[hpg + k], sigma * (2.0 * c2 * Bm * Bm));
+        if constexpr (DO_V) {
+          const double* w = B.wc + I.co;
+          put(&B.u[I.xo + col], fma(wf, grad, N.sl.coef[s] * w[N.sl.row[s] * nb + i]));
+        }
+        if constexpr (DO_HV) {
+          put(&B.out[I.xo + col], sigma * (2.0 * c2 * Bm * Bm) * B.dir[I.xo + col]);
+        }
+        if (fout) term += fma(c2, p, c1) * p;
+      } else {
+        const double pg = x[2 * nb + k];
+        const double c2 = N.gen_c2[k], c1 = N.gen_c1[k];
+        const double p = Bm * pg;
+        const double grad = Bm * fma(2.0 * c2, p, c1);
+        if (gradf) {
+          put(&gradf[2 * nb + k], grad);
+          put(&gradf[2 * nb + ng + k], 0.0);
+        }
+        if (hess) put(&hess[hpg + k], sigma * (2.0 * c2 * Bm * Bm));
+        if constexpr (DO_V) {
+          const double* w = B.wc + I.co;
+          const int bus = N.gen_bus[k];
+          put(&B.u[I.xo + 2 * nb + k], fma(wf, grad, -w[bus]));
+          put(&B.u[I.xo + 2 * nb + ng + k], -w[nb + bus]);
+        }
+        if constexpr (DO_HV) {
+          double* o = B.out + I.xo;
+          put(&o[2 * nb + k], sigma * (2.0 * c2 * Bm * Bm) * B.dir[I.xo + 2 * nb + k]);
+          put(&o[2 * nb + ng + k], 0.0);
+        }
+        if (fout) term = fma(fma(c2, p, c1), p, N.gen_c0[k]);
       }
-      if constexpr (DO_HV) {
-        put(&B.out[I.xo + col], sigma * (2.0 * c2 * Bm * Bm) * B.dir[I.xo + col]);
-      }
-      if (fout) term = fma(c2, p, c1) * p;
-    } else if (k < k1) {
-      const double pg = x[2 * nb + k];
-      const double c2 = N.gen_c2[k], c1 = N.gen_c1[k];
-      const double p = Bm * pg;
-      const double grad = Bm * fma(2.0 * c2, p, c1);
-      if (gradf) {
-        put(&gradf[2 * nb + k], grad);
-        put(&gradf[2 * nb + ng + k], 0.0);
-      }
-      if (hess) put(&hess[hpg + k], sigma * (2.0 * c2 * Bm * Bm));
-      if constexpr (DO_V) {
-        const double* w = B.wc + I.co;
-        const int bus = N.gen_bus[k];
-        put(&B.u[I.xo + 2 * nb + k], fma(wf, grad, -w[bus]));
-        put(&B.u[I.xo + 2 * nb + ng + k], -w[nb + bus]);
-      }
-      if constexpr (DO_HV) {
-        double* o = B.out + I.xo;
-        put(&o[2 * nb + k], sigma * (2.0 * c2 * Bm * Bm) * B.dir[I.xo + 2 * nb + k]);
-        put(&o[2 * nb + ng + k], 0.0);
-      }
-      if (fout) term = fma(fma(c2, p, c1), p, N.gen_c0[k]);
     }
     if (fout) smem[t] = term;
   }
