@@ -64,6 +64,39 @@ def count(w):
     return len(w["iterates"])
 
 
+# model variants: the polar representation (headline), the power-balance-
+# cartesian one, and the polar one with both feasibility slack blocks
+MODELS = ("polar", "cartesian", "slacks")
+LABELS = {"polar": "power-balance-polar", "cartesian": "power-balance-cartesian",
+          "slacks": "polar + load loss + power imbalance"}
+IMB_COST, LOSS_COST = (0.0, 1000.0), (0.0, 10000.0)   # (c2, c1) per MW
+
+
+def model_opts(A, model):
+    if model == "cartesian":
+        return A.net_opts(A.ACOPF_CARTESIAN)
+    if model == "slacks":
+        return A.net_opts(A.ACOPF_POLAR, A.ACOPF_SLACK_IMBALANCE | A.ACOPF_SLACK_LOADLOSS,
+                          IMB_COST, LOSS_COST)
+    return None
+
+
+def model_iterate(w, k, model):
+    """(x, lambda, sigma) of instance k for a model: the workload's polar
+    iterate; for cartesian a seeded draw x = [e; f; Pg; Qg]; for slacks the
+    polar iterate followed by six blocks of slacks U(0, 0.05)."""
+    it = w["iterates"][k]
+    if model == "polar":
+        return it.x, it.lam, it.sigma
+    from paper_2203_10587_amd import synth as S
+    rng = np.random.default_rng([2203, k])
+    g = instance_grid(w, k)
+    if model == "cartesian":
+        c = S.draw_iterate_cartesian(g, rng, it.sigma)
+        return c.x, c.lam, it.sigma
+    return np.concatenate([it.x, rng.uniform(0.0, 0.05, 6 * g.nbus)]), it.lam, it.sigma
+
+
 def algorithmic_bytes(w, opts=None):
     """Bytes the method must move per full evaluation of the batch: inputs
     x (8n), lambda (8m), sigma (8); outputs 8 (1 + n + m + nnzJ + nnzH); the
@@ -90,8 +123,14 @@ def algorithmic_bytes(w, opts=None):
 # CPU baseline: the oracle as it stands, single thread, bounded sample
 
 
-def cpu_baseline(w, budget_s=15.0):
+def cpu_baseline(w, model="polar", budget_s=15.0):
     import oracle as O
+    from oracle import cartesian as OC
+    from oracle import slacks as OS
+    spec = OS.Spec(imbalance=True, loadloss=True, imb_cost=IMB_COST, loss_cost=LOSS_COST)
+    run = {"polar": lambda mdl, x, s, l: O.evaluate(mdl, x, s, l),
+           "cartesian": lambda mdl, x, s, l: OC.evaluate(mdl, x, s, l),
+           "slacks": lambda mdl, x, s, l: OS.evaluate(mdl, spec, x, s, l)}[model]
     prepared = []
     k = 0
     t_eval = 0.0
@@ -101,21 +140,27 @@ def cpu_baseline(w, budget_s=15.0):
     while k < n_inst and (t_eval < budget_s or k < 2):
         idx = int(order[k])
         g = instance_grid(w, idx)
-        it = w["iterates"][idx]
+        x, lam, sigma = model_iterate(w, idx, model)
         mdl = O.prepare(g)                      # Y_bus and patterns: not timed
         t0 = time.perf_counter()
-        O.evaluate(mdl, it.x, it.sigma, it.lam)
+        run(mdl, x, sigma, lam)
         t_eval += time.perf_counter() - t0
         buses += g.nbus
         k += 1
         prepared.append(idx)
     return {"value": buses / t_eval, "unit": "bus-evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{k} of {n_inst} instances of {w['name']}, full f, grad f, c, J, H "
+            "sample": f"{k} of {n_inst} instances of {w['name']} ({LABELS[model]}), "
+                      f"full f, grad f, c, J, H "
                       f"(NumPy/SciPy FP64, one thread; Y_bus and pattern build untimed), "
                       f"{t_eval:.1f} s of evaluation"}
 
 
 # ---------------------------------------------------------------------------
+
+
+def traffic_key(w, model):
+    """Entry of profiles/traffic.json for a workload in a model."""
+    return w["name"] if model == "polar" else f"{w['name']}_{model}"
 
 
 def load_traffic(kernel_name, workload):
@@ -163,35 +208,35 @@ def served(seconds: float, rate: float = 2000.0, budget_gb: float = 8.0, log_pro
     return st
 
 
-def variant_bench(A, w, sched, sigma, nbus_total, args, dev, stream, opts, label):
-    """The workload's batch built with other net options, timed like the
-    headline step (same schedule, steps and warmup; all outputs)."""
-    import torch
-    from paper_2203_10587_amd import synth as S
-    K = count(w)
+def make_nets(A, w, model):
+    """(base or None, one net per instance) of the workload for a model."""
+    opts = model_opts(A, model)
     if w["kind"] == "outage":
-        vbase = A.acopf_net_create_opts(w["base"], opts)
-        vnets = [A.acopf_net_create_outage(vbase, int(l)) for l in w["outages"]]
-    else:
-        vbase = None
-        vnets = [A.acopf_net_create_opts(g, opts) for g in w["grids"]]
+        base = A.acopf_net_create_opts(w["base"], opts)
+        return base, [A.acopf_net_create_outage(base, int(l)) for l in w["outages"]]
+    return None, [A.acopf_net_create_opts(g, opts) for g in w["grids"]]
+
+
+def packed_inputs(w, batch, model):
+    """Host x and lambda of every instance packed at the batch's offsets."""
+    import torch
+    x = torch.empty(int(batch.x_off[-1]), dtype=torch.float64)
+    lam = torch.empty(int(batch.c_off[-1]), dtype=torch.float64)
+    for k in range(count(w)):
+        xk, lk, _ = model_iterate(w, k, model)
+        x[batch.x_off[k]:batch.x_off[k + 1]] = torch.from_numpy(np.ascontiguousarray(xk))
+        lam[batch.c_off[k]:batch.c_off[k + 1]] = torch.from_numpy(np.ascontiguousarray(lk))
+    return x, lam
+
+
+def variant_bench(A, w, model, sched, sigma, nbus_total, args, dev, stream):
+    """The workload in another model, timed like the headline step (same
+    schedule, steps and warmup; all outputs)."""
+    import torch
+    K = count(w)
+    vbase, vnets = make_nets(A, w, model)
     vb = A.acopf_batch_create(vnets, **sched)
-    rng = np.random.default_rng(2203)
-    nblk = ((4 if opts.slacks & A.ACOPF_SLACK_IMBALANCE else 0)
-            + (2 if opts.slacks & A.ACOPF_SLACK_LOADLOSS else 0))
-    vx = torch.empty(int(vb.x_off[-1]), dtype=torch.float64)
-    vl = torch.empty(int(vb.c_off[-1]), dtype=torch.float64)
-    for k in range(K):
-        g = instance_grid(w, k)
-        if opts.form == A.ACOPF_CARTESIAN:
-            it = S.draw_iterate_cartesian(g, rng, w["iterates"][k].sigma)
-            xk, lk = it.x, it.lam
-        else:
-            xk, lk = w["iterates"][k].x, w["iterates"][k].lam
-        ns = nblk * g.nbus
-        vx[vb.x_off[k]:vb.x_off[k + 1]] = torch.from_numpy(
-            np.concatenate([xk, rng.uniform(0.0, 0.05, ns)]))
-        vl[vb.c_off[k]:vb.c_off[k + 1]] = torch.from_numpy(lk)
+    vx, vl = packed_inputs(w, vb, model)
     vx, vl = vx.to(dev), vl.to(dev)
     outs = [torch.empty(n, dtype=torch.float64, device=dev)
             for n in (K, int(vb.x_off[-1]), int(vb.c_off[-1]), int(vb.j_off[-1]),
@@ -210,10 +255,12 @@ def variant_bench(A, w, sched, sigma, nbus_total, args, dev, stream, opts, label
     e_.record(stream)
     torch.cuda.synchronize()
     ms = s_.elapsed_time(e_) / args.steps
-    alg = algorithmic_bytes(w, opts)
-    res = {"model": label, "ms_per_step": ms, "value": nbus_total / (ms / 1e3),
+    alg = algorithmic_bytes(w, model_opts(A, model))
+    label = LABELS[model]
+    res = {"formulation": label, "ms_per_step": ms, "value": nbus_total / (ms / 1e3),
            "unit": "bus-evals/s", "algorithmic_bytes": alg,
-           "achieved_GBps": alg / (ms / 1e3) / 1e9, "frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+           "achieved_GBps": alg / (ms / 1e3) / 1e9, "frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+           "traffic": load_traffic("k_eval_all", traffic_key(w, model))}
     log(f"[bench] {label}: {ms:.4f} ms/step, {res['value']:.4e} bus-evals/s, frac {res['frac']:.3f}")
     del outs, vx, vl
     vb.close()
@@ -235,8 +282,11 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--model", default="polar", choices=list(MODELS),
+                    help="formulation of the timed step: polar (default), cartesian, or polar "
+                         "with load-loss and power-imbalance slacks")
     ap.add_argument("--no-variants", dest="variants", action="store_false",
-                    help="skip timing the workload in the cartesian representation and with slacks")
+                    help="skip timing the workload in the other formulations")
     ap.add_argument("--tile-be", type=int, default=0)
     ap.add_argument("--grid-mult", type=int, default=-1)
     ap.add_argument("--xcd", type=int, default=-1)
@@ -288,7 +338,7 @@ def main():
     t0 = time.time()
     w = {"c1": workload_c1, "c2": workload_c2, "c3": workload_c3}[args.workload]()
     log(f"[bench] workload {w['name']}: {count(w)} instances, generated in {time.time() - t0:.1f}s")
-    cpu = None if args.no_cpu else cpu_baseline(w)
+    cpu = None if args.no_cpu else cpu_baseline(w, args.model)
     if cpu:
         log(f"[bench] cpu oracle: {cpu['value']:.3e} bus-evals/s ({cpu['sample']})")
 
@@ -299,20 +349,12 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     K = count(w)
-    if w["kind"] == "outage":
-        base = A.acopf_net_create(w["base"])
-        nets = [A.acopf_net_create_outage(base, int(l)) for l in w["outages"]]
-    else:
-        nets = [A.acopf_net_create(g) for g in w["grids"]]
+    base, nets = make_nets(A, w, args.model)
     if args.autotune:
-        ts = torch.empty(K, dtype=torch.float64)
+        ts = torch.tensor([it.sigma for it in w["iterates"]], dtype=torch.float64)
         bx = A.acopf_batch_create(nets, **tune.DEFAULT)
         nx_, nc_ = int(bx.x_off[-1]), int(bx.c_off[-1])
-        xt, lt = torch.empty(nx_, dtype=torch.float64), torch.empty(nc_, dtype=torch.float64)
-        for k, it in enumerate(w["iterates"]):
-            xt[bx.x_off[k]:bx.x_off[k + 1]] = torch.from_numpy(it.x)
-            lt[bx.c_off[k]:bx.c_off[k + 1]] = torch.from_numpy(it.lam)
-            ts[k] = it.sigma
+        xt, lt = packed_inputs(w, bx, args.model)
         outs = [torch.empty(n, dtype=torch.float64, device=dev)
                 for n in (K, nx_, nc_, int(bx.j_off[-1]), int(bx.h_off[-1]))]
         bx.close()
@@ -332,11 +374,7 @@ def main():
     batch = A.acopf_batch_create(nets, **sched)
     nx, nc = int(batch.x_off[-1]), int(batch.c_off[-1])
     nj, nh = int(batch.j_off[-1]), int(batch.h_off[-1])
-    x = torch.empty(nx, dtype=torch.float64)
-    lam = torch.empty(nc, dtype=torch.float64)
-    for k, it in enumerate(w["iterates"]):
-        x[batch.x_off[k]:batch.x_off[k + 1]] = torch.from_numpy(it.x)
-        lam[batch.c_off[k]:batch.c_off[k + 1]] = torch.from_numpy(it.lam)
+    x, lam = packed_inputs(w, batch, args.model)
     x, lam = x.to(dev), lam.to(dev)
     sigma = torch.tensor([it.sigma for it in w["iterates"]], dtype=torch.float64, device=dev)
     f = torch.empty(K, dtype=torch.float64, device=dev)
@@ -402,14 +440,12 @@ def main():
     # the same workload in the other model variants: the power-balance-cartesian
     # representation, and the polar one with both slack blocks (load loss and
     # power imbalance); each has its own nets, batch and seeded iterates
-    cart = slk = None
+    variants = {}
     if args.variants:
-        cart = variant_bench(A, w, sched, sigma, nbus_total, args, dev, stream,
-                             A.net_opts(A.ACOPF_CARTESIAN), "power-balance-cartesian")
-        slk = variant_bench(A, w, sched, sigma, nbus_total, args, dev, stream,
-                            A.net_opts(A.ACOPF_POLAR, A.ACOPF_SLACK_IMBALANCE | A.ACOPF_SLACK_LOADLOSS,
-                                       (0.0, 1000.0), (0.0, 1e4)),
-                            "polar + load loss + power imbalance")
+        for mname in MODELS:
+            if mname != args.model:
+                variants[mname] = variant_bench(A, w, mname, sched, sigma, nbus_total, args, dev,
+                                                stream)
 
     # plain path: the same kernels, one instance per launch, into the same buffers
     L = A.lib()
@@ -455,22 +491,22 @@ def main():
         log(f"[bench] served: {serving['done']} requests, p50 {serving['p50_ms']:.3f} ms, "
             f"p99 {serving['p99_ms']:.3f} ms")
 
-    alg = algorithmic_bytes(w)
+    alg = algorithmic_bytes(w, model_opts(A, args.model))
     avg_ms = float(np.mean(lat))
     achieved = alg / (avg_ms / 1e3) / 1e9
-    traffic = load_traffic("k_eval_all", w["name"])
+    traffic = load_traffic("k_eval_all", traffic_key(w, args.model))
     out = {
         "metric": METRIC, "value": value, "unit": "bus-evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_ms / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w["name"], "instances": K, "buses_per_step": nbus_total,
+        "config": {"workload": w["name"], "formulation": LABELS[args.model], "instances": K,
+                   "buses_per_step": nbus_total,
                    "outputs": "f, grad_f, c, J, H", "schedule": sched},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "plain": plain,
         "coupled": coupled,
-        "cartesian": cart,
-        "slacks": slk,
+        "variants": variants or None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": alg, "kernel_ms": avg_ms},
