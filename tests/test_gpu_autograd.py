@@ -122,3 +122,22 @@ def test_double_backward(gpu_lib):
     x = torch.as_tensor(it.x, device="cuda").requires_grad_(True)
     assert torch.autograd.gradgradcheck(lambda z: AcopfEval.apply(z, net), (x,), eps=1e-6,
                                         atol=1e-5, rtol=1e-4)
+
+
+@pytest.mark.parametrize("form,slacks", [(1, 0), (0, 3), (1, 3)])
+def test_gradcheck_formulations(gpu_lib, form, slacks):
+    """gradcheck and gradgradcheck through the adjoint, HVP and JVP kernels in
+    the cartesian formulation and with slack blocks."""
+    import torch
+    from paper_2203_10587_amd import acopf as A
+    from paper_2203_10587_amd.autograd import AcopfEval
+    g = S.random_grid(12, 18, 4, seed=5, parallel=1)
+    rng = np.random.default_rng(6)
+    it = S.draw_iterate_cartesian(g, rng) if form else S.draw_iterate(g, rng)
+    net = A.acopf_net_create_opts(g, A.net_opts(form, slacks, (0.3, 20.0), (0.8, 50.0)))
+    xs = np.concatenate([it.x, rng.uniform(0.0, 0.2, net.n - len(it.x))])
+    x = torch.as_tensor(xs, device="cuda").requires_grad_(True)
+    log(f"[gradcheck] form={form} slacks={slacks} n={net.n} m={net.m}")
+    fn = lambda z: AcopfEval.apply(z, net)
+    assert torch.autograd.gradcheck(fn, (x,), eps=1e-6, atol=1e-6, rtol=1e-5)
+    assert torch.autograd.gradgradcheck(fn, (x,), eps=1e-6, atol=1e-5, rtol=1e-4)
