@@ -284,10 +284,12 @@ def jacobian_matrix(mdl: Model, x) -> sp.csr_matrix:
     return J
 
 
-def _branch_local_hessians(mdl: Model, x, lam):
+def _branch_local_hessians(mdl: Model, x, lam, magnitude: bool = False):
     """Per branch, the 4x4 Hessian of its share of lambda'c in the local
     variables z = (theta_f, theta_t, v_f, v_t), by the complex product rule
-    on S_f = V_f conj(I_f), S_t = V_t conj(I_t)."""
+    on S_f = V_f conj(I_f), S_t = V_t conj(I_t).  With magnitude=True, the
+    same sum with every term replaced by its absolute value (the companion
+    of the parity rule's Hessian scale)."""
     g = mdl.grid
     nb, nl = mdl.nb, mdl.nl
     th, v, _, _ = _split(mdl, x)
@@ -332,6 +334,13 @@ def _branch_local_hessians(mdl: Model, x, lam):
         P, Q = S.real, S.imag
         dP, dQ = dS.real, dS.imag
         d2P, d2Q = d2S.real, d2S.imag
+        if magnitude:
+            a = np.abs
+            return (a(lp)[:, None, None] * a(d2P) + a(lq)[:, None, None] * a(d2Q)
+                    + 2.0 * a(mu)[:, None, None] * (a(dP[:, :, None] * dP[:, None, :])
+                                                    + a(dQ[:, :, None] * dQ[:, None, :])
+                                                    + a(P)[:, None, None] * a(d2P)
+                                                    + a(Q)[:, None, None] * a(d2Q)))
         Hb = lp[:, None, None] * d2P + lq[:, None, None] * d2Q
         # mu * Hessian of (P^2 + Q^2)
         Hh = 2.0 * (dP[:, :, None] * dP[:, None, :] + dQ[:, :, None] * dQ[:, None, :]
@@ -343,19 +352,26 @@ def _branch_local_hessians(mdl: Model, x, lam):
     return H, idx
 
 
-def hessian_matrix(mdl: Model, x, sigma, lam) -> sp.csr_matrix:
-    """Full symmetric Hessian of L = sigma f + lambda'c (sparse)."""
+def hessian_matrix(mdl: Model, x, sigma, lam, magnitude: bool = False) -> sp.csr_matrix:
+    """Full symmetric Hessian of L = sigma f + lambda'c (sparse).  With
+    magnitude=True, each entry is instead the sum of the absolute values of
+    the terms it adds up (its rounding companion)."""
     g = mdl.grid
     nb, ng, n = mdl.nb, mdl.ng, mdl.n
-    Hl, idx = _branch_local_hessians(mdl, x, lam)
+    Hl, idx = _branch_local_hessians(mdl, x, lam, magnitude)
     rows = np.repeat(idx, 4, axis=1).reshape(-1)
     cols = np.tile(idx, (1, 4)).reshape(-1)
     vals = Hl.reshape(-1)
     # bus shunts: lambda_P Gs v^2 - lambda_Q Bs v^2
-    sh = 2.0 * (lam[:nb] * g.bus_gs - lam[nb:2 * nb] * g.bus_bs)
+    if magnitude:
+        sh = 2.0 * (np.abs(lam[:nb] * g.bus_gs) + np.abs(lam[nb:2 * nb] * g.bus_bs))
+    else:
+        sh = 2.0 * (lam[:nb] * g.bus_gs - lam[nb:2 * nb] * g.bus_bs)
     # cost: sigma * 2 c2 B^2 on (Pg_k, Pg_k)
     B = g.base_mva
     cost = sigma * 2.0 * g.gen_c2 * B * B
+    if magnitude:
+        cost = np.abs(cost)
     rows = np.concatenate([rows, nb + np.arange(nb), 2 * nb + np.arange(ng)])
     cols = np.concatenate([cols, nb + np.arange(nb), 2 * nb + np.arange(ng)])
     vals = np.concatenate([vals, sh, cost])
@@ -427,12 +443,19 @@ def vjp_scale(mdl: Model, x, w_f, w_c):
     return abs(w_f) * np.abs(grad) + Sj.T @ np.abs(w_c)
 
 
-def scales(mdl: Model, x, out):
+def scales(mdl: Model, x, out, sigma=None, lam=None):
     """Per-entry scales for the row-scaled relative parity rule:
-    |gpu - oracle| <= tol * max(|oracle|, scale)."""
+    |gpu - oracle| <= tol * max(|oracle|, scale).  A Hessian entry's scale is
+    its row's largest |entry| and, given the sigma and lambda it was
+    evaluated with, at least the sum of the absolute values of the terms it
+    adds up: an entry whose terms cancel is rounded relative to the terms."""
     _, _, fs = objective(mdl, x)
     s = {"f": fs, "c": constraint_scales(mdl, x), "grad_f": np.abs(out["grad_f"]),
          "jac_val": jacobian_row_scales(mdl, x, out["jac_val"])}
     if "hess_val" in out:
         s["hess_val"] = _row_absmax(mdl.hess_rowptr, out["hess_val"])
+        if lam is not None:
+            Hm = hessian_matrix(mdl, x, sigma, lam, magnitude=True)
+            s["hess_val"] = np.maximum(s["hess_val"],
+                                       _values_at(Hm, mdl.hess_rowptr, mdl.hess_col))
     return s

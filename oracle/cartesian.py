@@ -94,8 +94,10 @@ def jacobian_matrix(mdl, x) -> sp.csr_matrix:
     ], format="csr")
 
 
-def hessian_matrix(mdl, x, sigma, lam) -> sp.csr_matrix:
-    """Full symmetric Hessian of L = sigma f + lambda'c."""
+def hessian_matrix(mdl, x, sigma, lam, magnitude: bool = False) -> sp.csr_matrix:
+    """Full symmetric Hessian of L = sigma f + lambda'c.  With
+    magnitude=True, each entry is instead the sum of the absolute values of
+    the terms it adds up (its rounding companion)."""
     g = mdl.grid
     nb, nl, ng, n = mdl.nb, mdl.nl, mdl.ng, mdl.n
     e, f_ = _split(mdl, x)
@@ -127,6 +129,13 @@ def hessian_matrix(mdl, x, sigma, lam) -> sp.csr_matrix:
         Pv, Qv = S.real, S.imag
         dP, dQ = dS.real, dS.imag
         d2P, d2Q = d2S.real, d2S.imag
+        if magnitude:
+            a = np.abs
+            return (a(lp)[:, None, None] * a(d2P) + a(lq)[:, None, None] * a(d2Q)
+                    + 2.0 * a(mu)[:, None, None] * (a(dP[:, :, None] * dP[:, None, :])
+                                                    + a(dQ[:, :, None] * dQ[:, None, :])
+                                                    + a(Pv)[:, None, None] * a(d2P)
+                                                    + a(Qv)[:, None, None] * a(d2Q)))
         Hb = lp[:, None, None] * d2P + lq[:, None, None] * d2Q
         Hh = 2.0 * (dP[:, :, None] * dP[:, None, :] + dQ[:, :, None] * dQ[:, None, :]
                     + Pv[:, None, None] * d2P + Qv[:, None, None] * d2Q)
@@ -142,6 +151,9 @@ def hessian_matrix(mdl, x, sigma, lam) -> sp.csr_matrix:
     d = 2.0 * (lP * g.bus_gs - lQ * g.bus_bs) + 2.0 * lV
     B = g.base_mva
     cost = sigma * 2.0 * g.gen_c2 * B * B
+    if magnitude:
+        d = 2.0 * (np.abs(lP * g.bus_gs) + np.abs(lQ * g.bus_bs)) + 2.0 * np.abs(lV)
+        cost = np.abs(cost)
     ar = np.arange(nb)
     rows = np.concatenate([rows, ar, nb + ar, 2 * nb + np.arange(ng)])
     cols = np.concatenate([cols, ar, nb + ar, 2 * nb + np.arange(ng)])
@@ -184,11 +196,12 @@ def _companions(mdl, x):
     return v, af, at, df, dt
 
 
-def scales(mdl, x, out):
+def scales(mdl, x, out, sigma=None, lam=None):
     """Per-entry scales of the parity rule, as for polar: balance rows by the
     absolute products they sum, flow rows h + 2(|P|+|Q|) a + eps a^2,
     magnitude rows their value, J and H rows by their largest entry (J flow
-    rows add 2 a d)."""
+    rows add 2 a d); given sigma and lambda, an H entry's scale is at least
+    the sum of the absolute values of its terms."""
     g = mdl.grid
     nb, nl = mdl.nb, mdl.nl
     c, Sf, St, _ = constraints(mdl, x)
@@ -210,6 +223,9 @@ def scales(mdl, x, out):
          "jac_val": sj + np.repeat(extra, np.diff(jp))}
     if "hess_val" in out:
         s["hess_val"] = P._row_absmax(hp, out["hess_val"])
+        if lam is not None:
+            Hm = hessian_matrix(mdl, x, sigma, lam, magnitude=True)
+            s["hess_val"] = np.maximum(s["hess_val"], P._values_at(Hm, hp, mdl.hess_col))
     return s
 
 

@@ -130,13 +130,15 @@ def jacobian_matrix(mdl, spec, x) -> sp.csr_matrix:
                      format="csr")
 
 
-def hessian_matrix(mdl, spec, x, sigma, lam) -> sp.csr_matrix:
-    """Full symmetric Hessian of sigma f + lam' c."""
+def hessian_matrix(mdl, spec, x, sigma, lam, magnitude: bool = False) -> sp.csr_matrix:
+    """Full symmetric Hessian of sigma f + lam' c (with magnitude=True, the
+    base representation's sum of absolute terms per entry)."""
     xb, s = split(mdl, spec, x)
     _, m0 = base_sizes(mdl, spec)
-    Hb = _base(spec).hessian_matrix(mdl, xb, sigma, np.asarray(lam)[:m0])
+    Hb = _base(spec).hessian_matrix(mdl, xb, sigma, np.asarray(lam)[:m0], magnitude=magnitude)
     _, _, d2 = _penalty(mdl, spec, s)
-    return sp.block_diag([Hb, sp.diags(sigma * d2)], format="csr")
+    d = np.abs(sigma * d2) if magnitude else sigma * d2
+    return sp.block_diag([Hb, sp.diags(d)], format="csr")
 
 
 def pattern(mdl, spec):
@@ -169,10 +171,11 @@ def vjp(mdl, spec, x, w_f, w_c):
     return w_f * grad + jacobian_matrix(mdl, spec, x).T @ w_c
 
 
-def scales(mdl, spec, x, out):
+def scales(mdl, spec, x, out, sigma=None, lam=None):
     """The base representation's scales, widened by the slack terms: the
     balance rows by |S| |s|, J rows by their +-1 entries, f by the
-    penalty terms' magnitudes."""
+    penalty terms' magnitudes; H entries, given sigma and lambda, at least
+    the sum of the absolute values of their terms."""
     xb, s = split(mdl, spec, x)
     base = _base(spec)
     jpb, jcb, _, _ = base_pattern(mdl, spec)
@@ -190,6 +193,9 @@ def scales(mdl, spec, x, out):
            "jac_val": np.repeat(np.maximum(row_b, row_s), np.diff(jp))}
     if "hess_val" in out:
         res["hess_val"] = P._row_absmax(hp, out["hess_val"])
+        if lam is not None:
+            Hm = hessian_matrix(mdl, spec, x, sigma, lam, magnitude=True)
+            res["hess_val"] = np.maximum(res["hess_val"], P._values_at(Hm, hp, pattern(mdl, spec)[3]))
     return res
 
 

@@ -34,7 +34,7 @@ def assert_close(name, gpu, orc, scale, tol=TOL):
 def oracle_all(grid, it, w_f=None, w_c=None):
     mdl = O.prepare(grid)
     out = O.evaluate(mdl, it.x, it.sigma, it.lam)
-    sc = O.scales(mdl, it.x, out)
+    sc = O.scales(mdl, it.x, out, it.sigma, it.lam)
     res = {"mdl": mdl, "out": out, "scale": sc}
     if w_c is not None:
         res["u"] = O.vjp(mdl, it.x, w_f, w_c)

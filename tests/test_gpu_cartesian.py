@@ -40,7 +40,7 @@ def host(t):
 def oracle_ref(g, it, w_f=None, w_c=None):
     mdl = O.prepare(g)
     out = OC.evaluate(mdl, it.x, it.sigma, it.lam)
-    ref = {"mdl": mdl, "out": out, "scale": OC.scales(mdl, it.x, out)}
+    ref = {"mdl": mdl, "out": out, "scale": OC.scales(mdl, it.x, out, it.sigma, it.lam)}
     if w_c is not None:
         ref["u"] = OC.vjp(mdl, it.x, w_f, w_c)
         ref["u_scale"] = OC.vjp_scale(mdl, it.x, w_f, w_c)
@@ -235,3 +235,25 @@ def test_cartesian_rejections(gpu_lib):
         A.acopf_batch_draw_iterates(b, 0, 1, seeds, (0.0, 1.0, -1.0, 1.0), nan(g.n),
                                     nan(g.m + g.nbus))
     b.close()
+
+
+def test_cartesian_full_size(gpu_lib):
+    """The 1,000-outage workload in the cartesian formulation, in the launch
+    configuration the benchmark times: sampled instances against the oracle
+    and bit for bit against the plain path."""
+    from paper_2203_10587_amd import acopf as A
+    from tests import fullsize
+
+    def draw(k, g2, it):
+        c = S.draw_iterate_cartesian(g2, np.random.default_rng([2203, k]), it.sigma)
+        return c.x, c.lam, c.sigma
+
+    out, keep, nets, b, base = fullsize.run(A, A.net_opts(A.ACOPF_CARTESIAN), draw)
+    for k, (g2, x, lam, sigma) in keep.items():
+        log(f"[cartesian full size] instance {k}")
+        it = S.Iterate(x=x, lam=lam, sigma=sigma)
+        compare(f"full-{k}", out[k], oracle_ref(g2, it))
+        p = gpu_eval(A, nets[k], it)
+        for key in ("grad_f", "c", "jac_val", "hess_val"):
+            np.testing.assert_array_equal(out[k][key], p[key], err_msg=f"{k} {key}")
+        assert out[k]["f"] == p["f"]

@@ -111,7 +111,7 @@ def _check_assembled(A, b, cp, models, its, x, links, name):
     sj, sh = [], []
     for m, it in zip(models, its):
         o = O.evaluate(m, it.x, it.sigma, it.lam)
-        sc = O.scales(m, it.x, o)
+        sc = O.scales(m, it.x, o, it.sigma, it.lam)
         sj.append(sc["jac_val"])
         sh.append(sc["hess_val"])
     sj.append(np.zeros(Jc.nnz))

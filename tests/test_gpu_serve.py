@@ -60,7 +60,7 @@ def test_served_equals_alone_and_oracle(gpu_lib):
         np.testing.assert_allclose(got["lam"], lam, rtol=1e-14, atol=1e-14)
         mdl = O.prepare(g)
         out = O.evaluate(mdl, x, 1.0, lam)
-        ref = {"mdl": mdl, "out": out, "scale": O.scales(mdl, x, out)}
+        ref = {"mdl": mdl, "out": out, "scale": O.scales(mdl, x, out, 1.0, lam)}
         compare_outputs(f"served-{r.rid}", {k: got[k] for k in ("f", "grad_f", "c", "jac_val", "hess_val")}, ref)
 
 

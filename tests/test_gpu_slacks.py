@@ -63,7 +63,7 @@ def draw(g, spec, rng, sigma=1.0):
 def oracle_ref(g, spec, it, w_f=None, w_c=None):
     mdl = O.prepare(g)
     out = OS.evaluate(mdl, spec, it.x, it.sigma, it.lam)
-    ref = {"mdl": mdl, "out": out, "scale": OS.scales(mdl, spec, it.x, out)}
+    ref = {"mdl": mdl, "out": out, "scale": OS.scales(mdl, spec, it.x, out, it.sigma, it.lam)}
     if w_c is not None:
         ref["u"] = OS.vjp(mdl, spec, it.x, w_f, w_c)
         ref["u_scale"] = OS.vjp_scale(mdl, spec, it.x, w_f, w_c)
@@ -249,3 +249,27 @@ def test_slack_draw_refused(gpu_lib):
         A.acopf_batch_draw_iterates(b, 0, 1, seeds, (0.0, 1.0, -1.0, 1.0), nan(net.n), nan(net.m))
     assert ei.value.code == A.ACOPF_EINVAL
     b.close()
+
+
+def test_slack_full_size(gpu_lib):
+    """The 1,000-outage workload with both slack blocks, in the launch
+    configuration the benchmark times: sampled instances against the oracle
+    and bit for bit against the plain path."""
+    from paper_2203_10587_amd import acopf as A
+    from tests import fullsize
+    spec = spec_of(3, False)
+
+    def draw(k, g2, it):
+        s = np.random.default_rng([2203, k]).uniform(0.0, 0.05, 6 * g2.nbus)
+        return np.concatenate([it.x, s]), it.lam, it.sigma
+
+    opts = A.net_opts(A.ACOPF_POLAR, 3, COSTS["imb_cost"], COSTS["loss_cost"])
+    out, keep, nets, b, base = fullsize.run(A, opts, draw)
+    for k, (g2, x, lam, sigma) in keep.items():
+        log(f"[slack full size] instance {k}")
+        it = It(x, lam, sigma)
+        compare(f"full-{k}", out[k], oracle_ref(g2, spec, it))
+        p = gpu_eval(A, nets[k], it)
+        for key in ("grad_f", "c", "jac_val", "hess_val"):
+            np.testing.assert_array_equal(out[k][key], p[key], err_msg=f"{k} {key}")
+        assert out[k]["f"] == p["f"]

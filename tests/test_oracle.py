@@ -422,12 +422,36 @@ def test_planted_hessian_mistake_is_caught(monkeypatch):
     mdl = O.prepare(g)
     orig = O.acopf_oracle._branch_local_hessians
 
-    def broken(mdl_, x, lam):
+    def broken(mdl_, x, lam, magnitude=False):
         lam2 = lam.copy()
         lam2[2 * mdl_.nb:] = 0.0
-        return orig(mdl_, x, lam2)
+        return orig(mdl_, x, lam2, magnitude)
 
     monkeypatch.setattr(O.acopf_oracle, "_branch_local_hessians", broken)
     H = O.hessian_matrix(mdl, it.x, it.sigma, it.lam).toarray()
     Hr = R.dense_hessian(g, it.x, it.sigma, it.lam)
     assert np.abs(H - Hr).max() > 1e-3
+
+
+@pytest.mark.parametrize("cart", [False, True])
+def test_hessian_magnitude_companion(cart):
+    """The rounding companion of the Hessian scale (each entry's sum of
+    absolute terms): at least the entry's magnitude everywhere, equal to it
+    on the cost diagonal (one term per entry), and unchanged when every
+    multiplier changes sign (which negates the network part of H)."""
+    from oracle import cartesian as OC
+    g = S.random_grid(14, 22, 5, seed=3, parallel=2)
+    mdl = O.prepare(g)
+    rng = np.random.default_rng(4)
+    it = S.draw_iterate_cartesian(g, rng) if cart else S.draw_iterate(g, rng)
+    lam = rng.standard_normal(mdl.m + (g.nbus if cart else 0))
+    mod = OC if cart else O
+    H = mod.hessian_matrix(mdl, it.x, 0.7, lam).toarray()
+    M = mod.hessian_matrix(mdl, it.x, 0.7, lam, magnitude=True).toarray()
+    assert np.all(M >= np.abs(H) * (1 - 1e-14) - 1e-300)
+    nb = g.nbus
+    k = 2 * nb + np.arange(g.ngen)
+    np.testing.assert_allclose(M[k, k], np.abs(H[k, k]), rtol=1e-15)
+    # flipping every multiplier's sign negates H but leaves M unchanged
+    M2 = mod.hessian_matrix(mdl, it.x, 0.7, -lam, magnitude=True).toarray()
+    np.testing.assert_allclose(M2[:2 * nb, :2 * nb], M[:2 * nb, :2 * nb], rtol=1e-14)
