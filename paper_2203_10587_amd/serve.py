@@ -1,8 +1,11 @@
 """Continuous-batching evaluation server.
 
-Requests name a resident grid and carry a seed; the device draws the
-request's iterate and multipliers from the seed and evaluates f, grad f, c,
-J and H into a slot of that grid's pool.  The scheduler
+Requests name a resident grid and either carry their own iterate (x, lambda,
+sigma: a solver's request) or a seed, from which the device draws the
+iterate and multipliers (the synthetic served workload).  Each is evaluated
+(f, grad f, c, J and H) into a slot of that grid's pool; with keep_results
+the finished request holds device copies of its outputs (a future: poll
+Request.status, read Request.result).  The scheduler
 
   - keeps each grid's network resident on the device and one slot pool per
     grid (the instance slots of one batch handle);
@@ -41,6 +44,8 @@ class Request:
     slot: int = -1
     status: str = "queued"     # queued | running | done | failed | rejected
     error: str = ""
+    inputs: Optional[tuple] = None   # (x, lam, sigma) given by the caller, else drawn
+    result: Optional[dict] = None    # device outputs once done (keep_results)
 
     @property
     def latency(self) -> float:
@@ -69,11 +74,21 @@ class Executor:
     def slot_bytes(self, grid: int) -> int:
         raise NotImplementedError
 
-    def launch(self, grid: int, first: int, seeds: Sequence[int]):
-        """Enqueue draw + evaluation of slots [first, first + len(seeds))."""
+    def launch(self, grid: int, first: int, seeds: Sequence[int], inputs=None):
+        """Enqueue draw + evaluation of slots [first, first + len(seeds));
+        inputs (if given) holds, per slot, None or the request's own
+        (x, lam, sigma)."""
         raise NotImplementedError
 
     def done(self, handle) -> bool:
+        raise NotImplementedError
+
+    def check_inputs(self, grid: int, x, lam) -> None:
+        """Raise ValueError unless (x, lam) fit the grid."""
+        raise TypeError("this executor evaluates drawn iterates only")
+
+    def collect(self, grid: int, slot: int) -> dict:
+        """The outputs of a finished slot, kept apart from the pool."""
         raise NotImplementedError
 
 
@@ -108,8 +123,10 @@ class _Pool:
 
 class Server:
     def __init__(self, executor: Executor, budget_bytes: int = 8 << 30, max_window: int = 64,
-                 timeout_s: float = 10.0, clock: Callable[[], float] = time.perf_counter):
+                 timeout_s: float = 10.0, clock: Callable[[], float] = time.perf_counter,
+                 keep_results: bool = False):
         self.ex = executor
+        self.keep_results = bool(keep_results)
         self.budget = int(budget_bytes)
         self.max_window = int(max_window)
         self.timeout = float(timeout_s)
@@ -124,13 +141,27 @@ class Server:
         self._rr = 0
 
     # -- intake ---------------------------------------------------------------
-    def submit(self, grid: int, seed: int, t_arrive: Optional[float] = None) -> Request:
+    def submit(self, grid: int, seed: int = 0, t_arrive: Optional[float] = None, x=None,
+               lam=None, sigma: float = 1.0) -> Request:
+        """Queue one evaluation of `grid`: at the caller's iterate (x, lam,
+        sigma) if x is given, else at the iterate drawn from `seed`."""
         r = Request(rid=len(self.requests), grid=grid, seed=int(seed),
                     t_arrive=self.clock() if t_arrive is None else float(t_arrive))
         self.requests.append(r)
         if grid not in self.pools:
             r.status, r.error = "rejected", "unknown grid"
-        elif self.ex.slot_bytes(grid) > self.budget:
+            return r
+        if (x is None) != (lam is None):
+            r.status, r.error = "rejected", "x and lam go together"
+            return r
+        if x is not None:
+            try:
+                self.ex.check_inputs(grid, x, lam)
+            except (ValueError, TypeError, AttributeError) as exc:
+                r.status, r.error = "rejected", f"inputs: {exc}"
+                return r
+            r.inputs = (x, lam, float(sigma))
+        if self.ex.slot_bytes(grid) > self.budget:
             r.status, r.error = "rejected", "request exceeds the HBM budget"
         else:
             self.queues[grid].append(r)
@@ -145,7 +176,12 @@ class Server:
                 if w.handle is not None and self.ex.done(w.handle):
                     if w.reqs and w.reqs[0].status == "running":
                         for r in w.reqs:
+                            if self.keep_results:
+                                # copied on the grid's stream before the slot
+                                # can be reused by a later window there
+                                r.result = self.ex.collect(g, r.slot)
                             r.t_done, r.status = now, "done"
+                            r.inputs = None  # copied into the slot long ago
                     self.pools[g].free(w.first, len(w.reqs))
                     self.bytes_in_flight -= w.nbytes
                     n += 1
@@ -178,7 +214,11 @@ class Server:
                 first, k = got
                 reqs = [q.popleft() for _ in range(k)]
                 try:
-                    h = self.ex.launch(g, first, [r.seed for r in reqs])
+                    seeds = [r.seed for r in reqs]
+                    if any(r.inputs is not None for r in reqs):
+                        h = self.ex.launch(g, first, seeds, [r.inputs for r in reqs])
+                    else:
+                        h = self.ex.launch(g, first, seeds)
                 except Exception as exc:  # a failed launch fails its window only
                     pool.free(first, k)
                     for r in reqs:
@@ -293,18 +333,41 @@ class GpuExecutor(Executor):
     def slot_bytes(self, grid):
         return self.pool[grid]["slot_bytes"]
 
-    def launch(self, grid, first, seeds):
+    def check_inputs(self, grid, x, lam):
+        net = self.pool[grid]["net"]
+        if len(x) != net.n or len(lam) != net.m:
+            raise ValueError(f"grid {grid} takes x of {net.n} and lam of {net.m} entries")
+
+    def launch(self, grid, first, seeds, inputs=None):
+        """Draw the window's iterates from the seeds, overwrite the slots whose
+        request brought its own (x, lam, sigma), evaluate; returns the
+        completion event."""
         import torch
         P = self.pool[grid]
         k = len(seeds)
         P["pinned"][first:first + k] = torch.tensor([s & ((1 << 63) - 1) for s in seeds],
                                                     dtype=torch.int64)
         st = P["stream"]
+        caller = torch.cuda.current_stream()
         with torch.cuda.stream(st):
             P["seeds"][first:first + k].copy_(P["pinned"][first:first + k], non_blocking=True)
             b, B = P["batch"], P["bufs"]
             self.A.acopf_batch_draw_iterates(b, first, k, P["seeds"], P["bounds"], B["x"],
                                              B["lam"], st)
+            B["sigma"][first:first + k].fill_(1.0)
+            for i, inp in enumerate(inputs or ()):
+                if inp is None:
+                    continue
+                s = first + i
+                x, lam, sigma = inp
+                on_device = any(isinstance(t, torch.Tensor) and t.is_cuda for t in (x, lam))
+                if on_device:
+                    st.wait_stream(caller)  # work that produced the caller's tensors
+                B["x"][int(b.x_off[s]):int(b.x_off[s + 1])].copy_(
+                    torch.as_tensor(x, dtype=torch.float64), non_blocking=True)
+                B["lam"][int(b.c_off[s]):int(b.c_off[s + 1])].copy_(
+                    torch.as_tensor(lam, dtype=torch.float64), non_blocking=True)
+                B["sigma"][s:s + 1].fill_(sigma)
             self.A.acopf_batch_eval_range(b, first, k, B["x"], B["sigma"], B["lam"], B["f"],
                                           B["gf"], B["c"], B["jac"], B["hess"],
                                           self.A.ACOPF_ALL, st)
@@ -314,6 +377,18 @@ class GpuExecutor(Executor):
 
     def done(self, handle):
         return handle.query()
+
+    def collect(self, grid, slot):
+        """Device copies of one slot's outputs, enqueued on the grid's stream
+        (so later windows there cannot overwrite them first)."""
+        import torch
+        P = self.pool[grid]
+        b, B = P["batch"], P["bufs"]
+        sl = lambda t, o: t[int(o[slot]):int(o[slot + 1])].clone()
+        with torch.cuda.stream(P["stream"]):
+            return {"f": B["f"][slot:slot + 1].clone(), "grad_f": sl(B["gf"], b.x_off),
+                    "c": sl(B["c"], b.c_off), "jac_val": sl(B["jac"], b.j_off),
+                    "hess_val": sl(B["hess"], b.h_off)}
 
     def fetch(self, grid, slot):
         """Host copies of one slot's outputs (tests)."""

@@ -76,3 +76,49 @@ def test_poisson_run_small(gpu_lib):
     assert st["done"] == len(tr) and st["failed"] == 0
     assert srv.peak_bytes <= budget
     assert np.isfinite(st["p99_ms"]) and st["p50_ms"] <= st["p99_ms"]
+
+
+def test_caller_iterates_with_results(gpu_lib):
+    """A solver's requests: its own (x, lam, sigma), as host arrays and as
+    device tensors, mixed with seeded requests in the same windows; with
+    keep_results each request's device outputs match the oracle at its
+    iterate and survive the reuse of its slot by later requests."""
+    import torch
+    from paper_2203_10587_amd.serve import GpuExecutor, Server
+    grids = _grids()
+    ex = GpuExecutor(grids, [4, 4, 4])
+    srv = Server(ex, budget_bytes=1 << 30, max_window=4, keep_results=True)
+    rng = np.random.default_rng(11)
+    own = []
+    for k in range(9):
+        g = k % 3
+        it = S.draw_iterate(grids[g], rng, sigma=0.5 + 0.25 * k)
+        if k % 2:
+            x, lam = torch.as_tensor(it.x, device="cuda"), torch.as_tensor(it.lam, device="cuda")
+        else:
+            x, lam = it.x, it.lam
+        own.append((srv.submit(g, x=x, lam=lam, sigma=it.sigma), it))
+        srv.submit(g, seed=int(rng.integers(0, 2 ** 62)))
+    bad = srv.submit(0, x=np.zeros(3), lam=np.zeros(3))
+    assert bad.status == "rejected"
+    while not srv.idle():
+        srv.step()
+    torch.cuda.synchronize()
+    # more traffic through the same slots; the kept results must not change
+    kept = {r.rid: {k: v.cpu().numpy().copy() for k, v in r.result.items()} for r, _ in own}
+    for k in range(12):
+        srv.submit(k % 3, seed=k)
+    while not srv.idle():
+        srv.step()
+    torch.cuda.synchronize()
+    for r, it in own:
+        assert r.status == "done", r.error
+        log(f"[served own iterate] request {r.rid} grid {r.grid}")
+        got = {k: v.cpu().numpy() for k, v in r.result.items()}
+        for k in got:
+            np.testing.assert_array_equal(got[k], kept[r.rid][k], err_msg=k)
+        got["f"] = float(got["f"][0])
+        mdl = O.prepare(grids[r.grid])
+        out = O.evaluate(mdl, it.x, it.sigma, it.lam)
+        ref = {"mdl": mdl, "out": out, "scale": O.scales(mdl, it.x, out, it.sigma, it.lam)}
+        compare_outputs(f"own-{r.rid}", got, ref)

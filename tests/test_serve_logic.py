@@ -177,3 +177,55 @@ def test_poisson_trace_shape():
     assert ts == sorted(ts) and 0 <= ts[0] and ts[-1] <= 2.0
     assert {g for _, g, _ in tr} == {0, 1, 2, 3}
     assert tr == poisson_trace(2000.0, 2.0, 4, seed=1)
+
+
+class InputExecutor(FakeExecutor):
+    """A fake that takes caller iterates (x of n = 3, lam of m = 2 entries)
+    and 'evaluates' f = sum(x) * sigma into a slot store."""
+
+    def __init__(self, clock, **kw):
+        super().__init__(clock, **kw)
+        self.inputs_seen = []
+        self.slots = {}
+
+    def check_inputs(self, g, x, lam):
+        if len(x) != 3 or len(lam) != 2:
+            raise ValueError("x takes 3 and lam 2 entries")
+
+    def launch(self, g, first, seeds, inputs=None):
+        self.inputs_seen.append((first, inputs))
+        for i, s in enumerate(seeds):
+            inp = inputs[i] if inputs else None
+            self.slots[(g, first + i)] = (sum(inp[0]) * inp[2]) if inp else float(s)
+        return super().launch(g, first, seeds)
+
+    def collect(self, g, slot):
+        return {"f": self.slots[(g, slot)]}
+
+
+def test_caller_iterates_and_results():
+    """Requests with their own (x, lam, sigma) reach the executor slot by
+    slot beside seeded ones; wrong sizes are rejected at submit; with
+    keep_results every finished request holds its own outputs."""
+    clock = Clock()
+    ex = InputExecutor(clock)
+    srv = Server(ex, budget_bytes=10_000, clock=clock, keep_results=True)
+    a = srv.submit(0, seed=7)
+    b = srv.submit(0, x=[1.0, 2.0, 3.0], lam=[0.0, 0.0], sigma=2.0)
+    c = srv.submit(0, x=[1.0], lam=[0.0, 0.0])
+    d = srv.submit(0, x=[1.0, 1.0, 1.0])
+    assert c.status == "rejected" and "inputs" in c.error
+    assert d.status == "rejected" and "together" in d.error
+    drive(srv, clock)
+    assert a.status == b.status == "done"
+    assert a.result == {"f": 7.0} and b.result == {"f": 12.0}
+    assert b.inputs is None  # released once copied
+    first, inputs = ex.inputs_seen[0]
+    assert inputs[0] is None and inputs[1][2] == 2.0
+
+
+def test_seeded_only_executor_rejects_inputs():
+    clock = Clock()
+    srv = Server(FakeExecutor(clock), clock=clock)
+    r = srv.submit(0, x=[1.0], lam=[1.0])
+    assert r.status == "rejected"
