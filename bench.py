@@ -177,8 +177,9 @@ def cpu_pool_baseline(w, model="polar", budget_s=5.0, per_worker=12):
     order = np.random.default_rng(1).permutation(count(w))
     ctx = mp.get_context("fork")
     barrier = ctx.Manager().Barrier(P)
-    jobs = [(w, model, [int(i) for i in order[p * per_worker:(p + 1) * per_worker]], budget_s,
-             barrier) for p in range(P)]
+    n = len(order)  # instances dealt cyclically: every worker gets per_worker
+    jobs = [(w, model, [int(order[(p * per_worker + j) % n]) for j in range(per_worker)],
+             budget_s, barrier) for p in range(P)]
     with ctx.Pool(P) as pool:
         res = pool.map(_pool_worker, jobs)
     buses = sum(r[0] for r in res)
@@ -401,7 +402,7 @@ def main():
     t0 = time.time()
     w = {"c1": workload_c1, "c2": workload_c2, "c3": workload_c3}[args.workload]()
     log(f"[bench] workload {w['name']}: {count(w)} instances, generated in {time.time() - t0:.1f}s")
-    cpu = None if args.no_cpu else cpu_baseline(w, args.model)
+    cpu = None if (args.no_cpu or args.autotune) else cpu_baseline(w, args.model)
     if cpu:
         log(f"[bench] cpu oracle: {cpu['value']:.3e} bus-evals/s ({cpu['sample']})")
         cpu["pool"] = cpu_pool_baseline(w, args.model)
@@ -480,7 +481,7 @@ def main():
     # other instance to instance 0 (Pg of each generator), values and the
     # Jacobian's +-1 entries, timed like the batched step
     coupled = None
-    if K > 1:
+    if K > 1 and len({int(n.dims.ngen) for n in nets}) == 1:  # links need equal generator sets
         cp = A.acopf_couple_create(batch, list(range(1, K)), [0] * (K - 1))
         cc = torch.empty(cp.rows, dtype=torch.float64, device=dev)
         cj = torch.empty(cp.nnz, dtype=torch.float64, device=dev)

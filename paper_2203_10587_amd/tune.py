@@ -19,8 +19,9 @@ import os
 from typing import Dict, List, Sequence
 
 DEFAULT = {"tile_be": 256, "grid_mult": 0, "xcd_group": 1, "no_graph": 0}
-CANDIDATES = [{"tile_be": t, "grid_mult": g, "xcd_group": x, "no_graph": 0}
-              for t in (64, 128, 256, 512) for g in (0, 2, 4, 8) for x in (0, 1)]
+CANDIDATES = [{"tile_be": t, "grid_mult": g, "xcd_group": x, "no_graph": ng}
+              for t in (64, 128, 256, 512) for g in (0, 2, 4, 8) for x in (0, 1)
+              for ng in (0, 1)]
 
 
 def cache_path() -> str:
