@@ -42,6 +42,10 @@
  *     per-handle scratch for the deterministic reduction of f).
  * All results are deterministic: repeated calls, and the same instance
  * evaluated alone or inside any batch, give bitwise identical values.
+ *
+ * The header is plain C (C11 or C++); a caller compiled without hipcc
+ * defines __HIP_PLATFORM_AMD__, as HIP's own headers require, adds
+ * /opt/rocm/include to the include path and links libacopf.so.
  */
 #ifndef ACOPF_ABI_H_
 #define ACOPF_ABI_H_
