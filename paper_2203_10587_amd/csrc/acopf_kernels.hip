@@ -233,11 +233,6 @@ struct SegShift {
   }
 };
 
-template <int NR>
-__device__ __forceinline__ int place(int gp, const SegShift& sg, const int32_t (&r)[NR]) {
-  return sg.inside ? shifted(gp, r) : gp - sg.below;
-}
-
 // Sum over a parallel-branch group, left in its first lane: lanes
 // [lane, lane + g) hold the members' values, added in lane order.  Every
 // lane of the wave takes part (g = 0 or 1 leaves a lane's values as they
@@ -966,27 +961,30 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   // entries; an N-1 instance skips the removed positions and shifts the rest
   if constexpr (R::J || R::H) {
     __syncthreads();
-    const bool rm = I.out_rm != 0;
-    const SegShift shP(T.jP0, T.nP, I.rj), shQ(T.jQ0, T.nP, I.rj);
-    const SegShift shT(T.hT0, T.nT, I.rh), shV(T.hV0, T.nV, I.rh);
+    // one loop per segment: the whole segment moves by one constant unless a
+    // removed position falls inside it (then each entry is looked up)
+    auto seg = [&](double* out, int g0, int n, int s0, const auto& r) {
+      const SegShift sh(g0, n, r);
+      if (!sh.inside) {
+        double* o = out + (g0 - sh.below);
+        for (int k = tid; k < n; k += WG) put(&o[k], stg[s0 + k]);
+      } else {
+        for (int k = tid; k < n; k += WG) {
+          const int p = shifted(g0 + k, r);
+          if (p >= 0) put(&out[p], stg[s0 + k]);
+        }
+      }
+    };
     if constexpr (R::J) {
       if (jac) {
-        for (int k = tid; k < 2 * T.nP; k += WG) {
-          const bool q = k >= T.nP;
-          const int gp = q ? T.jQ0 + (k - T.nP) : T.jP0 + k;
-          const int p = rm ? place(gp, q ? shQ : shP, I.rj) : gp;
-          if (p >= 0) put(&jac[p], stg[k]);
-        }
+        seg(jac, T.jP0, T.nP, 0, I.rj);      // P rows
+        seg(jac, T.jQ0, T.nP, T.nP, I.rj);   // Q rows
       }
     }
     if constexpr (R::H) {
       if (hess) {
-        for (int k = tid; k < T.nT + T.nV; k += WG) {
-          const bool v = k >= T.nT;
-          const int gp = v ? T.hV0 + (k - T.nT) : T.hT0 + k;
-          const int p = rm ? place(gp, v ? shV : shT, I.rh) : gp;
-          if (p >= 0) put(&hess[p], stg[h0 + k]);
-        }
+        seg(hess, T.hT0, T.nT, h0, I.rh);          // theta rows
+        seg(hess, T.hV0, T.nV, h0 + T.nT, I.rh);   // v rows
       }
     }
   }
