@@ -8,7 +8,8 @@ it: the plain path (the same kernels, one instance per launch), per-step
 latency percentiles, the roofline of the batched kernel, and the CPU
 oracle timed on a bounded sample on this host.
 
-    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--workload c2|c1|c3]
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+                    [--workload n1|grid10k|uneven|served] [--model polar|cartesian|slacks]
 """
 import argparse
 import json
@@ -33,22 +34,22 @@ def log(*a):
 # workloads
 
 
-def workload_c2():
+def workload_n1():
     from paper_2203_10587_amd import synth as S
-    os_ = S.config2(0)
+    os_ = S.n1_security_set(0)
     return {"name": "n1_security_2000bus_x1000", "base": os_.base, "outages": os_.outages,
             "iterates": os_.iterates, "kind": "outage"}
 
 
-def workload_c1():
+def workload_grid10k():
     from paper_2203_10587_amd import synth as S
-    g, it = S.config1(0)
+    g, it = S.grid_10k(0)
     return {"name": "single_10000bus", "grids": [g], "iterates": [it], "kind": "grids"}
 
 
-def workload_c3():
+def workload_uneven():
     from paper_2203_10587_amd import synth as S
-    inst = S.config3(0)
+    inst = S.uneven_scenarios(0)
     return {"name": "uneven_scenarios_x512", "grids": [g for _, g, _ in inst],
             "iterates": [it for _, _, it in inst], "kind": "grids"}
 
@@ -252,7 +253,7 @@ def served(seconds: float, rate: float = 2000.0, budget_gb: float = 8.0, log_pro
     import torch
     from paper_2203_10587_amd import synth as S
     from paper_2203_10587_amd.serve import GpuExecutor, Server, poisson_trace
-    grids = S.config4_grids(0)
+    grids = S.served_grids(0)
     ex = GpuExecutor(grids, [512, 128, 48, 24])
     srv = Server(ex, budget_bytes=int(budget_gb * (1 << 30)), max_window=64, timeout_s=30.0)
     # warm the kernels and the allocator outside the timed trace
@@ -340,7 +341,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="n1", choices=["n1", "grid10k", "uneven", "served"],
+                    help="n1: 1,000 N-1 outages of a 2,000-bus grid (default); grid10k: one "
+                         "10,000-bus grid; uneven: 512 scenario grids of 200..25,000 buses; "
+                         "served: Poisson requests over four resident grids")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the served Poisson trace (the full served workload is 60 s)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -379,12 +383,12 @@ def main():
                           "GBps_read_plus_write": 2 * n * 8 / ms / 1e6}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
               "(instances would shard across GPUs with no exchange); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
-    if args.workload == "c4":
+    if args.workload == "served":
         import torch
         torch.cuda.set_device(0)
         st = served(args.serve_seconds, args.serve_rate)
@@ -400,7 +404,7 @@ def main():
         return
 
     t0 = time.time()
-    w = {"c1": workload_c1, "c2": workload_c2, "c3": workload_c3}[args.workload]()
+    w = {"grid10k": workload_grid10k, "n1": workload_n1, "uneven": workload_uneven}[args.workload]()
     log(f"[bench] workload {w['name']}: {count(w)} instances, generated in {time.time() - t0:.1f}s")
     cpu = None if (args.no_cpu or args.autotune) else cpu_baseline(w, args.model)
     if cpu:

@@ -318,12 +318,7 @@ def bridges(nb: int, f: np.ndarray, t: np.ndarray) -> np.ndarray:
 # the five workloads
 
 
-def config0(seed=0):
-    """9-bus ring, one instance."""
-    return ring9(seed)
-
-
-def config1(seed=0, nb: int = 10_000, nl: int = 13_000):
+def grid_10k(seed=0, nb: int = 10_000, nl: int = 13_000):
     """10,000-bus random geometric grid, 13,000 branches, one instance."""
     s_grid, s_it = _children(seed, 2)
     g = rgg_grid(nb, nl, s_grid)
@@ -337,7 +332,7 @@ class OutageSet:
     iterates: List[Iterate]      # per instance, sized for the N-1 network
 
 
-def config2(seed=0, nb: int = 2000, nl: int = 3000, count: int = 1000) -> OutageSet:
+def n1_security_set(seed=0, nb: int = 2000, nl: int = 3000, count: int = 1000) -> OutageSet:
     """N-1 security set: `count` distinct non-bridge single-branch outages of a
     2,000-bus / 3,000-branch base grid, each with its own iterate."""
     s_grid, s_pick, s_it = _children(seed, 3)
@@ -358,21 +353,21 @@ def config2(seed=0, nb: int = 2000, nl: int = 3000, count: int = 1000) -> Outage
     return OutageSet(base=g, outages=outs, iterates=its)
 
 
-def config2_instance(os_: OutageSet, k: int) -> Tuple[Grid, Iterate]:
+def n1_instance(os_: OutageSet, k: int) -> Tuple[Grid, Iterate]:
     return remove_branch(os_.base, int(os_.outages[k])), os_.iterates[k]
 
 
-def config3_sizes(seed=0, count: int = 512, lo: int = 200, hi: int = 25_000) -> np.ndarray:
+def uneven_scenario_sizes(seed=0, count: int = 512, lo: int = 200, hi: int = 25_000) -> np.ndarray:
     rng = _rng(_children(seed, 2)[0])
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), count))).astype(np.int64)
 
 
-def config3(seed=0, count: int = 512, lo: int = 200, hi: int = 25_000,
+def uneven_scenarios(seed=0, count: int = 512, lo: int = 200, hi: int = 25_000,
             only: Optional[Sequence[int]] = None) -> List[Tuple[int, Grid, Iterate]]:
     """Uneven scenarios: bus counts log-uniform in [lo, hi], branches 1.3x,
     loads scaled per instance by exp(N(0, 0.1^2)).  `only` restricts which
     instance indices are generated (each is independent of the others)."""
-    sizes = config3_sizes(seed, count, lo, hi)
+    sizes = uneven_scenario_sizes(seed, count, lo, hi)
     kids = _children(_children(seed, 2)[1], count)
     out = []
     for k in (range(count) if only is None else only):
@@ -386,7 +381,7 @@ def config3(seed=0, count: int = 512, lo: int = 200, hi: int = 25_000,
 SERVE_SIZES = (1_000, 10_000, 30_000, 70_000)
 
 
-def config4_grids(seed=0, sizes: Sequence[int] = SERVE_SIZES) -> List[Grid]:
+def served_grids(seed=0, sizes: Sequence[int] = SERVE_SIZES) -> List[Grid]:
     """The four resident grids of the served workload."""
     kids = _children(seed, len(sizes))
     return [rgg_grid(int(nb), None, kids[i]) for i, nb in enumerate(sizes)]

@@ -13,7 +13,7 @@ def run(A, opts, draw, samples=(0, 1, 499, 998, 999)):
     Returns (outputs per sampled k, grids, inputs, nets, batch)."""
     import torch
     from paper_2203_10587_amd import tune
-    os_ = S.config2(0)
+    os_ = S.n1_security_set(0)
     base = A.acopf_net_create_opts(os_.base, opts)
     nets = [A.acopf_net_create_outage(base, int(l)) for l in os_.outages]
     sched = tune.lookup_or_default(nets)
@@ -25,7 +25,7 @@ def run(A, opts, draw, samples=(0, 1, 499, 998, 999)):
     sig = np.empty(K)
     keep = {}
     for k in range(K):
-        g2, it = S.config2_instance(os_, k)
+        g2, it = S.n1_instance(os_, k)
         xk, lk, sk = draw(k, g2, it)
         x[b.x_off[k]:b.x_off[k + 1]] = xk
         lam[b.c_off[k]:b.c_off[k + 1]] = lk

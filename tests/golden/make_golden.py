@@ -20,7 +20,7 @@ from paper_2203_10587_amd import synth as S  # noqa: E402
 
 
 def main():
-    g, it = S.config0(0)
+    g, it = S.ring9(0)
     mdl = O.prepare(g)
     out = O.evaluate(mdl, it.x, it.sigma, it.lam)
     doc = {

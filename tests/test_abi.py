@@ -32,7 +32,7 @@ def test_library_exports_every_declared_function():
 
 
 def _grids():
-    yield "ring9", S.config0(0)[0]
+    yield "ring9", S.ring9(0)[0]
     yield "rand30", S.random_grid(30, 50, 11, seed=3, parallel=3)
     yield "star40", S.random_grid(40, 45, 6, seed=8, star=True, parallel=2)
     yield "rgg800", S.rgg_grid(800, 1040, seed=2)
@@ -89,7 +89,7 @@ def _bad(g, **kw):
     (lambda g: _bad(g, base_mva=0.0), "base_mva"),
 ])
 def test_validation_errors(mut, msg):
-    g = mut(S.config0(0)[0])
+    g = mut(S.ring9(0)[0])
     with pytest.raises(A.AcopfError) as ei:
         A.acopf_pattern_host(g)
     assert ei.value.code == A.ACOPF_EINVAL
@@ -97,7 +97,7 @@ def test_validation_errors(mut, msg):
 
 
 def test_outage_index_validation():
-    g = S.config0(0)[0]
+    g = S.ring9(0)[0]
     for bad in (-2, 12, 100):
         with pytest.raises(A.AcopfError):
             A.acopf_pattern_host(g, bad)
@@ -131,7 +131,7 @@ def test_host_pattern_cartesian_bit_exact(name, g):
 
 
 def test_form_validation():
-    g = S.config0(0)[0]
+    g = S.ring9(0)[0]
     with pytest.raises(A.AcopfError) as ei:
         A.acopf_pattern_host_form(g, 2)
     assert ei.value.code == A.ACOPF_EINVAL
@@ -166,7 +166,7 @@ def test_host_pattern_slacks_bit_exact(slacks, cart):
 
 
 def test_opts_validation():
-    g = S.config0(0)[0]
+    g = S.ring9(0)[0]
     for bad in (A.net_opts(3, 0), A.net_opts(0, 4), A.net_opts(0, 1, (float("nan"), 0.0))):
         with pytest.raises(A.AcopfError) as ei:
             A.acopf_pattern_host_opts(g, bad)

@@ -50,7 +50,7 @@ def test_batched_directional_fd(gpu_lib):
     import torch
     from paper_2203_10587_amd import acopf as A
     from paper_2203_10587_amd.autograd import AcopfBatchEval
-    inst = S.config3(0, count=12, lo=200, hi=25_000)
+    inst = S.uneven_scenarios(0, count=12, lo=200, hi=25_000)
     nets = [A.acopf_net_create(g) for _, g, _ in inst]
     b = A.acopf_batch_create(nets)
     K = len(nets)

@@ -83,7 +83,7 @@ def same(a, b, tag):
 
 @pytest.fixture(scope="module")
 def small_n1():
-    os_ = S.config2(0, nb=300, nl=450, count=40)
+    os_ = S.n1_security_set(0, nb=300, nl=450, count=40)
     rng = np.random.default_rng(5)
     w_c = [rng.standard_normal(it.lam.shape) for it in os_.iterates]
     w_f = rng.standard_normal(len(w_c))
@@ -110,7 +110,7 @@ def test_batch_equals_plain_and_oracle(gpu_lib, small_n1):
         ref_plain = plain(A, nets[k], os_.iterates[k], float(w_f[k]), w_c[k])
         same(got, ref_plain, f"inst{k}")
         if k % 8 == 0:
-            g2, it = S.config2_instance(os_, k)
+            g2, it = S.n1_instance(os_, k)
             compare_outputs(f"n1-{k}", got, oracle_all(g2, it, float(w_f[k]), w_c[k]))
 
 
@@ -188,24 +188,24 @@ def test_graph_replays_match_eager(gpu_lib, small_n1):
     same(G2.instance(5), ref[5], "second-buffers")
 
 
-def test_config2_full_size(gpu_lib):
+def test_n1_security_set_full_size(gpu_lib):
     """1,000 N-1 outages of the 2,000-bus grid in one launch: sampled
     instances against the oracle and against the plain path; the
     angle-reference property (theta-columns of every J row sum to zero) on
     all instances."""
     from paper_2203_10587_amd import acopf as A
     from paper_2203_10587_amd import tune
-    os_ = S.config2(0)
+    os_ = S.n1_security_set(0)
     base, nets = _nets(A, os_)
     b = A.acopf_batch_create(nets, **tune.lookup_or_default(nets))  # the benchmark's launch
     P = Packed(A, b, os_.iterates)
     P.eval()
     _t().cuda.synchronize()
     for k in (0, 1, 499, 998, 999):
-        log(f"[config2] oracle instance {k}")
-        g2, it = S.config2_instance(os_, k)
+        log(f"[n1_security_set] oracle instance {k}")
+        g2, it = S.n1_instance(os_, k)
         got = P.instance(k)
-        compare_outputs(f"c2-{k}", got, oracle_all(g2, it))
+        compare_outputs(f"n1-{k}", got, oracle_all(g2, it))
         same(got, plain(A, nets[k], it), f"c2 plain {k}")
     jv = P.jv.cpu().numpy()
     assert np.all(np.isfinite(jv)) and np.all(np.isfinite(P.hv.cpu().numpy()))
@@ -220,15 +220,15 @@ def test_config2_full_size(gpu_lib):
         assert np.all(np.abs(sums) <= 1e-12 * scale * 8), k
 
 
-def test_config3_uneven_subset(gpu_lib):
+def test_uneven_scenarios_subset(gpu_lib):
     """The uneven scenario workload: a 64-instance draw spanning the size
     range, batched with VJP; smallest, median and largest instances against
     the oracle."""
     from paper_2203_10587_amd import acopf as A
-    sizes = S.config3_sizes(0)
+    sizes = S.uneven_scenario_sizes(0)
     order = np.argsort(sizes)
     pick = sorted(set(order[::8].tolist()) | {int(order[0]), int(order[-1])})
-    inst = S.config3(0, only=pick)
+    inst = S.uneven_scenarios(0, only=pick)
     nets = [A.acopf_net_create(g) for _, g, _ in inst]
     rng = np.random.default_rng(9)
     w_c = [rng.standard_normal(g.m) for _, g, _ in inst]
@@ -242,5 +242,5 @@ def test_config3_uneven_subset(gpu_lib):
     chk = {int(np.argmin(sz)), int(np.argmax(sz)), int(np.argsort(sz)[len(sz) // 2])}
     for i in sorted(chk):
         k, g, it = inst[i]
-        log(f"[config3] instance {k} nb={g.nbus}")
+        log(f"[uneven_scenarios] instance {k} nb={g.nbus}")
         compare_outputs(f"c3-{k}", P.instance(i), oracle_all(g, it, float(w_f[i]), w_c[i]))

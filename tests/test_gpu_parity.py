@@ -55,7 +55,7 @@ def gpu_eval(A, net, it, w_f=None, w_c=None, separate=True):
 
 
 def small_cases():
-    yield "ring9", S.config0(0)[0]
+    yield "ring9", S.ring9(0)[0]
     yield "rand12_par", S.random_grid(12, 20, 5, seed=1, parallel=2)
     yield "rand60", S.random_grid(60, 95, 20, seed=5, parallel=3)
     yield "star120", S.random_grid(121, 125, 10, seed=8, star=True, parallel=1)
@@ -98,16 +98,16 @@ def test_plain_parity(gpu_lib, name, g):
     assert fused["f"] == out["f"]
 
 
-def test_config1_10k_parity(gpu_lib):
+def test_grid_10k_parity(gpu_lib):
     from paper_2203_10587_amd import acopf as A
-    g, it = S.config1(0)
-    log(f"[config1] nb={g.nbus} nl={g.nbranch}")
+    g, it = S.grid_10k(0)
+    log(f"[grid_10k] nb={g.nbus} nl={g.nbranch}")
     rng = np.random.default_rng(3)
     w_c = rng.standard_normal(g.m)
     ref = oracle_all(g, it, 0.9, w_c)
     net = A.acopf_net_create(g)
     out = gpu_eval(A, net, it, 0.9, w_c)
-    r = compare_outputs("config1", out, ref)
+    r = compare_outputs("grid_10k", out, ref)
     log(f"   worst error / tolerance: {max(r.values()):.3e}")
 
 

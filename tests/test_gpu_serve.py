@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _grids():
-    return [S.config0(0)[0], S.rgg_grid(300, 390, seed=3), S.rgg_grid(1200, 1560, seed=4)]
+    return [S.ring9(0)[0], S.rgg_grid(300, 390, seed=3), S.rgg_grid(1200, 1560, seed=4)]
 
 
 def _bounds(g):

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def small_grids():
     return [
-        ("ring9", S.config0(0)[0]),
+        ("ring9", S.ring9(0)[0]),
         ("rand12", S.random_grid(12, 20, 5, seed=1, parallel=2)),
         ("rand25", S.random_grid(25, 40, 9, seed=7, parallel=1)),
         ("star8", S.random_grid(8, 9, 3, seed=4, star=True, parallel=1)),
@@ -68,7 +68,7 @@ def test_line_charging_and_tap_closed_form():
 
 
 def test_objective_closed_form():
-    g = S.config0(0)[0]
+    g = S.ring9(0)[0]
     mdl = O.prepare(g)
     it = _it(g, 3)
     f, grad, _ = O.objective(mdl, it.x)
@@ -280,7 +280,7 @@ def test_newton_power_flow_on_ring9():
     3..8.  Newton on the 18 balance rows with the oracle's Jacobian columns
     must converge quadratically.  Loads are halved: the random ring at full
     load lies beyond its loadability limit and has no solution."""
-    g, _ = S.config0(0)
+    g, _ = S.ring9(0)
     g = S.scale_loads(g, 0.5)
     mdl = O.prepare(g)
     nb, ng = g.nbus, g.ngen
@@ -311,7 +311,7 @@ def test_newton_power_flow_on_ring9():
 
 
 def test_pattern_nnz_formulas():
-    for g in [S.config0(0)[0], S.random_grid(25, 40, 9, seed=7, parallel=1),
+    for g in [S.ring9(0)[0], S.random_grid(25, 40, 9, seed=7, parallel=1),
               S.rgg_grid(500, 650, seed=3)]:
         jp, jc, hp, hc = O.pattern(g)
         pairs = {frozenset((int(a), int(b))) for a, b in zip(g.br_from, g.br_to)}
@@ -326,7 +326,7 @@ def test_pattern_nnz_formulas():
 
 
 def test_config_sizes():
-    g, it = S.config0(0)
+    g, it = S.ring9(0)
     jp, _, hp, _ = O.pattern(g)
     assert (g.n, g.m, jp[-1], hp[-1]) == (24, 42, 234, 78)
 
@@ -347,7 +347,7 @@ def test_pattern_equals_structural_nonzeros(name, g):
 
 
 def test_outage_removes_rows_and_slots():
-    os_ = S.config2(0, nb=60, nl=90, count=5)
+    os_ = S.n1_security_set(0, nb=60, nl=90, count=5)
     base = O.pattern(os_.base)
     for k in range(5):
         l = int(os_.outages[k])
@@ -365,7 +365,7 @@ def test_outage_removes_rows_and_slots():
 def test_golden_ring9():
     with open(os.path.join(HERE, "golden", "ring9_seed0.json")) as fh:
         gold = json.load(fh)
-    g, it = S.config0(0)
+    g, it = S.ring9(0)
     mdl = O.prepare(g)
     out = O.evaluate(mdl, it.x, it.sigma, it.lam)
     np.testing.assert_array_equal(mdl.jac_rowptr, gold["jac_rowptr"])

@@ -18,7 +18,7 @@ def _simple(f, t):
 
 
 def test_ring9_structure():
-    g, it = S.config0(0)
+    g, it = S.ring9(0)
     assert (g.nbus, g.nbranch, g.ngen) == (9, 12, 3)
     assert list(g.gen_bus) == [0, 1, 2]
     assert np.all(g.bus_pd[:3] == 0) and np.all(g.bus_pd[3:] > 0)
@@ -42,8 +42,8 @@ def test_rgg_counts_and_structure():
     assert np.all(np.diff(key) > 0)
 
 
-def test_config1_sizes():
-    g, it = S.config1(0)
+def test_grid_10k_sizes():
+    g, it = S.grid_10k(0)
     assert (g.nbus, g.nbranch, g.ngen, int(np.sum(g.bus_pd > 0))) == (10000, 13000, 2500, 7000)
     assert int(np.sum(g.br_tap != 1.0)) == 2600
     assert it.x.shape == (25000,) and it.lam.shape == (46000,)
@@ -57,33 +57,33 @@ def test_bridges_brute_force():
         assert br[l] == (not _connected(g.nbus, g.br_from[keep], g.br_to[keep]))
 
 
-def test_config2_outages_are_non_bridges_and_distinct():
-    os_ = S.config2(0, nb=200, nl=300, count=50)
+def test_n1_outages_are_non_bridges_and_distinct():
+    os_ = S.n1_security_set(0, nb=200, nl=300, count=50)
     assert len(set(os_.outages.tolist())) == 50
     br = S.bridges(200, os_.base.br_from, os_.base.br_to)
     assert not np.any(br[os_.outages])
     for k in (0, 49):
-        g, it = S.config2_instance(os_, k)
+        g, it = S.n1_instance(os_, k)
         assert g.nbranch == 299 and it.lam.shape == (g.m,)
         assert _connected(200, g.br_from, g.br_to)
 
 
 def test_determinism_and_child_independence():
-    a = S.config3(7, count=6, lo=200, hi=400, only=[1, 4])
-    b = S.config3(7, count=6, lo=200, hi=400)
+    a = S.uneven_scenarios(7, count=6, lo=200, hi=400, only=[1, 4])
+    b = S.uneven_scenarios(7, count=6, lo=200, hi=400)
     for (k, ga, ia) in a:
         gb, ib = b[k][1], b[k][2]
         np.testing.assert_array_equal(ga.br_from, gb.br_from)
         np.testing.assert_array_equal(ia.x, ib.x)
         np.testing.assert_array_equal(ia.lam, ib.lam)
-    g1, i1 = S.config0(3)
-    g2, i2 = S.config0(3)
+    g1, i1 = S.ring9(3)
+    g2, i2 = S.ring9(3)
     np.testing.assert_array_equal(i1.lam, i2.lam)
     np.testing.assert_array_equal(g1.br_x, g2.br_x)
 
 
-def test_config3_size_distribution():
-    sz = S.config3_sizes(0)
+def test_uneven_scenario_size_distribution():
+    sz = S.uneven_scenario_sizes(0)
     assert len(sz) == 512 and sz.min() >= 200 and sz.max() <= 25000
     assert 2.3e6 < sz.sum() < 3.0e6
 
