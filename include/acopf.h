@@ -1,11 +1,15 @@
 /*
  * acopf.h -- C ABI of the MI355X (gfx950) ACOPF model-evaluation library.
  *
- * The library evaluates the polar power-balance ACOPF model at an
- * interior-point iterate, the work an interior-point solver repeats every
- * iteration (paper: OPFLOW section, compact statement min f(x) s.t. g(x) = 0,
- * h- <= h(x) <= h+, x- <= x <= x+, evaluated on the GPU with the data kept
- * resident there).  It computes, in FP64:
+ * The library evaluates the ACOPF model at an interior-point iterate, the
+ * work an interior-point solver repeats every iteration (paper: OPFLOW
+ * section, compact statement min f(x) s.t. g(x) = 0, h- <= h(x) <= h+,
+ * x- <= x <= x+, evaluated on the GPU with the data kept resident there).
+ * What follows describes the power-balance-polar form without slack
+ * variables, which acopf_net_create builds; the cartesian form and the
+ * feasibility slacks (acopf_net_create_opts) change x, c and the patterns as
+ * stated beside ACOPF_CARTESIAN and ACOPF_SLACK_* below.  It computes, in
+ * FP64:
  *   f       quadratic generator cost on MW:  sum_k c2 (B Pg)^2 + c1 B Pg + c0
  *   grad_f  dense, length n (zeros outside the Pg block)
  *   c       constraints [g^P (nb); g^Q (nb); h^f (nl); h^t (nl)]
@@ -13,6 +17,9 @@
  *   J       values of dc/dx on the fixed CSR pattern of acopf_pattern
  *   H       values of the lower triangle of sigma grad^2 f + sum lambda_r grad^2 c_r
  *   u       vector-Jacobian product  w_f grad f + J' w_c
+ *   H d, J d  Hessian- and Jacobian-vector products, neither matrix formed
+ * for one net, for a batch of nets in one launch, and for coupling rows that
+ * join instances of a batch.
  * Variables x = [theta (nb); v (nb); Pg (ng); Qg (ng)], n = 2 nb + 2 ng;
  * constraints and multipliers in the order of c, m = 2 nb + 2 nl.
  * Branch model: pi model, series admittance 1/(r + j x), charging b/2 at both

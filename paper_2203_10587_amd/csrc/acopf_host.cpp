@@ -641,7 +641,7 @@ extern "C" {
 
 const char* acopf_last_error(void) { return t_err.c_str(); }
 
-int acopf_version(void) { return 10000; }
+int acopf_version(void) { return 10300; }
 
 static acopf_net_opts form_opts(int32_t form) {
   acopf_net_opts o{};
