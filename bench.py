@@ -8,7 +8,7 @@ it: the plain path (the same kernels, one instance per launch), per-step
 latency percentiles, the roofline of the batched kernel, and the CPU
 oracle timed on a bounded sample on this host.
 
-    python bench.py [--gpus 1] [--steps 50] [--warmup 5]
+    python bench.py [--gpus 1] [--steps 50] [--warmup 50]
                     [--workload n1|grid10k|uneven|served] [--model polar|cartesian|slacks]
 """
 import argparse
@@ -340,7 +340,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=50,
+                    help="untimed steps first (the GPU needs ~10 ms of work to reach steady clocks)")
     ap.add_argument("--workload", default="n1", choices=["n1", "grid10k", "uneven", "served"],
                     help="n1: 1,000 N-1 outages of a 2,000-bus grid (default); grid10k: one "
                          "10,000-bus grid; uneven: 512 scenario grids of 200..25,000 buses; "
@@ -462,20 +463,27 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
+    # the timed region: K steps back to back between two events on the
+    # launch stream (throughput and the roofline's per-launch time)
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     start.record(stream)
     for k in range(args.steps):
-        ev[k][0].record(stream)
         step()
-        ev[k][1].record(stream)
     end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = start.elapsed_time(end)
+    # per-step latency (p50/p99) from K more steps, each between its own
+    # events (which serialise the stream, so they stay out of the timed region)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        step()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     value = nbus_total * args.steps / (total_ms / 1e3)
     log(f"[bench] batched: {total_ms / args.steps:.4f} ms/step, {value:.4e} bus-evals/s "
@@ -563,7 +571,7 @@ def main():
             f"p99 {serving['p99_ms']:.3f} ms")
 
     alg = algorithmic_bytes(w, model_opts(A, args.model))
-    avg_ms = float(np.mean(lat))
+    avg_ms = total_ms / args.steps  # per launch of the step, over the timed region
     achieved = alg / (avg_ms / 1e3) / 1e9
     traffic = load_traffic("k_eval_all", traffic_key(w, args.model))
     out = {

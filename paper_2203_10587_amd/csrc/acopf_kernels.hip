@@ -180,8 +180,14 @@ struct Rec {
   static constexpr bool JV = (WHAT & W_JVP) != 0;
   static constexpr int oC = 0;                   // P_e, Q_e
   static constexpr int oJ = oC + (C ? 2 : 0);    // dP_e/dth_e, dP_e/dv_e, dQ_e/dth_e, dQ_e/dv_e
-  static constexpr int oH = oJ + (J ? 4 : 0);    // d2/dth_e2, d2/dv_e dth_e, d2/dv_e2
-  static constexpr int oV = oH + (H ? 3 : 0);    // u_th_e, u_v_e
+  static constexpr int nCJ = oJ + (J ? 4 : 0);
+  // The fused variant walks the branches twice and lets the bus lanes
+  // consume the balance and Jacobian records between the walks, so the
+  // Hessian records of the second walk reuse their space.
+  static constexpr bool REUSE = H && nCJ > 0;
+  static constexpr int oH = REUSE ? 0 : nCJ;     // d2/dth_e2, d2/dv_e dth_e, d2/dv_e2
+  static constexpr int eH = oH + (H ? 3 : 0);
+  static constexpr int oV = eH > nCJ ? eH : nCJ; // u_th_e, u_v_e
   static constexpr int oHV = oV + (V ? 2 : 0);   // (H d)_th_e, (H d)_v_e
   static constexpr int oJV = oHV + (HV ? 2 : 0); // (J d) of P_e, of Q_e
   static constexpr int N = oJV + (JV ? 2 : 0);
@@ -292,12 +298,14 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   // A variant that forms both first and second derivatives walks the
   // branches twice (flows and Jacobian, then Hessian), recomputing the flows
   // from L2-resident inputs: the register peak is then the larger pass's,
-  // not their union, which keeps more waves resident.
+  // not their union, which keeps more waves resident.  The bus lanes consume
+  // the balance and Jacobian records between the two walks, so the Hessian
+  // records reuse their LDS and a tile holds more branch ends (fewer tiles).
   auto branch_pass = [&](auto parts) {
     constexpr unsigned P = decltype(parts)::value;
     constexpr bool pC = (P & W_C) != 0, pJ = (P & W_J) != 0, pH = (P & W_H) != 0;
     constexpr bool pV = (P & W_VJP) != 0, pHV = (P & W_HVP) != 0, pJV = (P & W_JVP) != 0;
-    constexpr bool FIRST = P == WHAT || (P & ~W_H) != 0;
+    constexpr bool FIRST = P == WHAT || (P & ~W_H) != 0 || R::REUSE;
     if constexpr (CART) {
     for (int k0 = 0; k0 < T.nw; k0 += WG) {
       const int k = k0 + tid;
@@ -739,9 +747,8 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
     }
     }
   };
-  if constexpr (R::H && (R::C || R::J)) {
-    branch_pass(std::integral_constant<unsigned, WHAT & ~W_H>{});
-    branch_pass(std::integral_constant<unsigned, W_H>{});
+  if constexpr (R::REUSE) {
+    branch_pass(std::integral_constant<unsigned, WHAT & ~W_H>{});  // the Hessian walk follows phase B's first part
   } else {
     branch_pass(std::integral_constant<unsigned, WHAT>{});
   }
@@ -911,6 +918,13 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       }
     }
   }
+  }
+  if constexpr (R::REUSE) {
+    __syncthreads();  // the balance and Jacobian records have been consumed
+    branch_pass(std::integral_constant<unsigned, W_H>{});
+    __syncthreads();
+  }
+  if (has_bus) {
   if constexpr (R::H) {
     if (hess) {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -1117,7 +1131,7 @@ hipError_t launch_caps(int tile_be, const Bufs& b, const InstOff* table, const I
   if (blocks <= 0) return hipSuccess;
   switch (tile_be) {
 #define ACOPF_CASE(C)                                                                      \
-  case C.be:                                                                               \
+  case C.cls:                                                                              \
     k_eval<WHAT, C.wg, C.be, C.nbus, C.stage><<<blocks, C.wg, 0, s>>>(b, table, one, tiles, ntiles); \
     break;
     ACOPF_CASE(kCaps64)

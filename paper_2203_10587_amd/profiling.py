@@ -82,12 +82,33 @@ def largest_grid_mean(per_dispatch: dict, skip_first: bool = True):
     return sum(vals) / len(vals), len(vals), gmax, name
 
 
+def _medians(d: str) -> dict:
+    """Median dispatch duration (ns) per kernel name from the kernel trace
+    (the average includes the first dispatches, which run before the GPU
+    has reached its steady clocks)."""
+    per = defaultdict(list)
+    try:
+        for r in _csv(d, "kernel_trace.csv"):
+            per[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    except FileNotFoundError:
+        return {}
+    out = {}
+    for k, v in per.items():
+        v.sort()
+        out[k] = v[len(v) // 2]
+    return out
+
+
 def cmd_stats(args):
     rows = _csv(args.dir, "kernel_stats.csv")
+    med = _medians(args.dir)
     lines = [f"# {args.title}", "", "Command:", "", "```", args.cmd, "```", "",
-             "| kernel | calls | avg us | min us | max us | share |", "|---|---|---|---|---|---|"]
+             "| kernel | calls | avg us | median us | min us | max us | share |",
+             "|---|---|---|---|---|---|---|"]
     for r in rows:
+        m = med.get(r["Name"])
         lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{'-' if m is None else f'{m / 1e3:.1f}'} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['Percentage']):.1f}% |")
     with open(args.out, "w") as fh:
