@@ -283,8 +283,8 @@ int acopf_eval_all(acopf_net net, const double* x, double sigma, const double* l
 /* Tile/schedule configuration chosen by the autotuner (or fixed by hand). */
 typedef struct {
   int32_t tile_be;    /* tile class 64, 128, 256 or 512: workgroups of
-                         64/128/256/256 threads holding up to 88/176/352/512
-                         branch ends and 44/88/176/256 buses per bus tile  */
+                         64/128/256/256 threads holding up to 110/220/440/512
+                         branch ends and 55/110/220/256 buses per bus tile */
   int32_t grid_mult;  /* workgroups per CU for the persistent grid; 0 = one
                          workgroup per tile (no persistence)               */
   int32_t xcd_group;  /* 1 = map each instance's tiles onto one XCD        */

@@ -442,8 +442,9 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
       k = k1;
     }
     // every stored position must lie in the tile's row segments
-    bool ok = e1 - e0 <= caps.be && b1 - b0 <= caps.nbus &&
-              2 * (r1.x - r0.x) + (r1.z - r0.z) + (r1.w - r0.w) <= caps.stage;
+    // the J segments and the H segments are staged one after the other
+    bool ok = e1 - e0 <= caps.be && b1 - b0 <= caps.nbus && 2 * (r1.x - r0.x) <= caps.stage &&
+              (r1.z - r0.z) + (r1.w - r0.w) <= caps.stage;
     for (size_t k = w0; ok && k < S->work.size(); ++k) {
       const WorkItem& w = S->work[k];
       if (w.l < 0) continue;
@@ -476,26 +477,30 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
     tl.hV0 = r0.w;
     S->tiles.push_back(tl);
   };
-  int b0 = 0, cur_be = 0, cur_st = 0;
+  // staged entries of a bus: its J P and Q rows, then (in the same space,
+  // after the J rows are stored) its H theta and v rows
+  int b0 = 0, cur_be = 0, cur_j = 0, cur_h = 0;
   for (int i = 0; i < T.nb; ++i) {
     const int d = T.be_ptr[i + 1] - T.be_ptr[i];
-    // staged entries of the bus: J P and Q rows, H theta row, H v row
     const int a = T.acnt[i].x, lo = T.acnt[i].y, g = T.gen_ptr[i + 1] - T.gen_ptr[i];
-    const int st = 2 * (2 * a + g + T.sl.nsp) + (lo + 1) + (a + lo + 1);
-    if (d > caps.be || st > caps.stage)
+    const int sj = 2 * (2 * a + g + T.sl.nsp), sh = (lo + 1) + (a + lo + 1);
+    if (d > caps.be || sj > caps.stage || sh > caps.stage)
       return fail(ACOPF_EINVAL, "bus " + std::to_string(i) + " has " + std::to_string(d) +
-                                    " branch ends and " + std::to_string(st) +
+                                    " branch ends and " + std::to_string(std::max(sj, sh)) +
                                     " row entries; a bus tile of this schedule holds at most " +
                                     std::to_string(caps.be) + " and " +
                                     std::to_string(caps.stage));
-    if (i > b0 && (cur_be + d > caps.be || cur_st + st > caps.stage || i - b0 >= caps.nbus)) {
+    if (i > b0 && (cur_be + d > caps.be || cur_j + sj > caps.stage || cur_h + sh > caps.stage ||
+                   i - b0 >= caps.nbus)) {
       close(b0, i);
       b0 = i;
       cur_be = 0;
-      cur_st = 0;
+      cur_j = 0;
+      cur_h = 0;
     }
     cur_be += d;
-    cur_st += st;
+    cur_j += sj;
+    cur_h += sh;
   }
   close(b0, T.nb);
   if (tiler_error) return fail(ACOPF_EINVAL, "internal: work item positions outside the tile");

@@ -147,18 +147,19 @@ enum : unsigned {
 // Tile capacities of one schedule class (the schedule's tile_be value):
 // workgroup size, branch ends per bus tile (LDS records), buses per bus tile
 // (one lane each) and entries of the tile's J and H row segments staged in
-// LDS (2 nP + nT + nV).  The fused variant needs 6 record doubles per end
-// plus the staged entries (about 8.5 per end on power grids); classes 64,
-// 128 and 256 are sized so that this stays within 160 KB of LDS at four
-// waves per SIMD (10, 20 and 40 KB per workgroup), class 512 admits buses
-// with up to 512 branch ends at lower occupancy.
+// LDS (the J rows, 2 nP, and afterwards the H rows, nT + nV, each within
+// it).  The fused variant needs 6 record doubles per end plus the staged
+// J rows (about 5.5 entries per end on power grids, the H rows about 3);
+// classes 64, 128 and 256 are sized so that this stays within 160 KB of LDS
+// at four waves per SIMD (10, 20 and 40 KB per workgroup), class 512 admits
+// buses with up to 512 branch ends at lower occupancy.
 struct TileCaps {
   int32_t cls, wg, be, nbus, stage;
 };
 
-constexpr TileCaps kCaps64 = {64, 64, 88, 44, 752};
-constexpr TileCaps kCaps128 = {128, 128, 176, 88, 1504};
-constexpr TileCaps kCaps256 = {256, 256, 352, 176, 2992};
+constexpr TileCaps kCaps64 = {64, 64, 110, 55, 616};
+constexpr TileCaps kCaps128 = {128, 128, 220, 110, 1232};
+constexpr TileCaps kCaps256 = {256, 256, 440, 220, 2464};
 constexpr TileCaps kCaps512 = {512, 256, 512, 256, 6144};
 constexpr int kMaxGroup = 64;  // parallel branches between one bus pair
 constexpr int kDefaultTileBe = 256;

@@ -280,7 +280,9 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   double* stg = smem + L::kRec;
   const int gmax = T.gmax;
   const int sP = -T.jP0, sQ = T.nP - T.jP0;
-  const int h0 = R::J ? 2 * T.nP : 0;
+  // the fused variant stores its J rows before it stages the H rows, in
+  // the same space
+  const int h0 = (R::J && !R::REUSE) ? 2 * T.nP : 0;
   const int sT = h0 - T.hT0, sV = h0 + T.nT - T.hV0;
   const double* x = B.x + I.xo;
   const double* mul = (R::H || R::HV) ? B.lam + I.co : (R::V ? B.wc + I.co : nullptr);
@@ -290,6 +292,22 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   double* jflow = (R::J && B.jac) ? B.jac + I.jo + (N.jflow - 8 * I.out_rm) : nullptr;
   double* jac = (R::J && B.jac) ? B.jac + I.jo : nullptr;
   double* hess = (R::H && B.hess) ? B.hess + I.ho : nullptr;
+  // Phase C's store of one staged row segment, consecutive lanes on
+  // consecutive entries: the whole segment moves by one constant unless a
+  // removed position of an N-1 instance falls inside it (then each entry is
+  // looked up).
+  auto seg = [&](double* out, int g0, int n, int s0, const auto& r) {
+    const SegShift sh(g0, n, r);
+    if (!sh.inside) {
+      double* o = out + (g0 - sh.below);
+      for (int k = tid; k < n; k += WG) put(&o[k], stg[s0 + k]);
+    } else {
+      for (int k = tid; k < n; k += WG) {
+        const int p = shifted(g0 + k, r);
+        if (p >= 0) put(&out[p], stg[s0 + k]);
+      }
+    }
+  };
 
   // ---- phase A (1): lane per branch touching the tile.  Off-diagonal
   // entries go to the staged rows; each end's own-bus share goes to its
@@ -920,7 +938,12 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   }
   }
   if constexpr (R::REUSE) {
-    __syncthreads();  // the balance and Jacobian records have been consumed
+    __syncthreads();  // balance and Jacobian records consumed, J rows complete
+    if (jac) {
+      seg(jac, T.jP0, T.nP, 0, I.rj);     // P rows
+      seg(jac, T.jQ0, T.nP, T.nP, I.rj);  // Q rows
+    }
+    __syncthreads();  // the records and the staged rows are free again
     branch_pass(std::integral_constant<unsigned, W_H>{});
     __syncthreads();
   }
@@ -975,21 +998,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   // entries; an N-1 instance skips the removed positions and shifts the rest
   if constexpr (R::J || R::H) {
     __syncthreads();
-    // one loop per segment: the whole segment moves by one constant unless a
-    // removed position falls inside it (then each entry is looked up)
-    auto seg = [&](double* out, int g0, int n, int s0, const auto& r) {
-      const SegShift sh(g0, n, r);
-      if (!sh.inside) {
-        double* o = out + (g0 - sh.below);
-        for (int k = tid; k < n; k += WG) put(&o[k], stg[s0 + k]);
-      } else {
-        for (int k = tid; k < n; k += WG) {
-          const int p = shifted(g0 + k, r);
-          if (p >= 0) put(&out[p], stg[s0 + k]);
-        }
-      }
-    };
-    if constexpr (R::J) {
+    if constexpr (R::J && !R::REUSE) {
       if (jac) {
         seg(jac, T.jP0, T.nP, 0, I.rj);      // P rows
         seg(jac, T.jQ0, T.nP, T.nP, I.rj);   // Q rows

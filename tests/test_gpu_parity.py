@@ -156,7 +156,7 @@ def test_outage_parity(gpu_lib):
 def test_tile_capacity_error(gpu_lib):
     """A bus with more branch ends than a bus tile holds is refused cleanly."""
     from paper_2203_10587_amd import acopf as A
-    g = S.random_grid(400, 400, 3, seed=1, star=True, parallel=1)
+    g = S.random_grid(600, 600, 3, seed=1, star=True, parallel=1)  # a 600-end star bus
     with pytest.raises(A.AcopfError) as ei:
         A.acopf_net_create(g)
     assert ei.value.code == A.ACOPF_EINVAL and "branch ends" in str(ei.value)
