@@ -49,6 +49,7 @@ struct acopf_batch_s {
   acopf::Tile* d_tiles_inst = nullptr;  // the same tiles, instance after instance
   std::vector<int32_t> inst_tile_off;   // count + 1
   int max_len = 0;                      // max n + m over instances
+  int max_chunks = 1;                   // f partials per instance, at most
   hipStream_t cap_stream = nullptr;
   std::list<std::pair<acopf::GraphKey, hipGraphExec_t>> graphs;  // most recent first
   std::atomic<int> refs{0};             // couplings built on this batch
@@ -107,7 +108,9 @@ hipError_t enqueue(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStre
   const InstOff none{};
   hipError_t e = launch_eval(variant, b->sched.tile_be, bufs, b->d_table, none, b->d_tiles,
                              b->ntiles, b->grid, s);
-  if (e == hipSuccess && bufs.f) e = launch_fsum(b->d_table, none, 0, b->count, bufs.fpart, bufs.f, s);
+  // a single-chunk instance has its f written by its generator tile
+  if (e == hipSuccess && bufs.f && b->max_chunks > 1)
+    e = launch_fsum(b->d_table, none, 0, b->count, bufs.fpart, bufs.f, s);
   return e;
 }
 
@@ -210,6 +213,7 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
       b->jo[k + 1] = b->jo[k] + d.nnz_jac;
       b->ho[k + 1] = b->ho[k] + d.nnz_hess;
       fpo[k + 1] = fpo[k] + nets[k]->base->topo.nchunks;
+      b->max_chunks = std::max(b->max_chunks, nets[k]->base->topo.nchunks);
     }
     // per-base schedule (outage children share their base's)
     struct PerBase {
@@ -429,7 +433,8 @@ int acopf_batch_eval_range(acopf_batch b, int32_t first, int32_t count, const do
   const unsigned variant = variant_of(what) | (b->form == ACOPF_CARTESIAN ? W_CART : 0u);
   e = launch_eval(variant, b->sched.tile_be, bufs, b->d_table, none, b->d_tiles_inst + t0,
                   t1 - t0, 0, stream);
-  if (e == hipSuccess && bufs.f) e = launch_fsum(b->d_table, none, first, count, bufs.fpart, bufs.f, stream);
+  if (e == hipSuccess && bufs.f && b->max_chunks > 1)
+    e = launch_fsum(b->d_table, none, first, count, bufs.fpart, bufs.f, stream);
   if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
   return ACOPF_OK;
 }

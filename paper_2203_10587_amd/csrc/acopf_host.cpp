@@ -214,7 +214,7 @@ int build_topology(const acopf_net_desc* d, const acopf_net_opts* o, Topology* T
   T->hpg = int(hpg);
   T->nnz_jac = nnzj;
   T->nnz_hess = nnzh;
-  T->gchunks = int((ng + kGenChunk - 1) / kGenChunk);
+  T->gchunks = int((ng + kGenChunk * kGenPerSlot - 1) / (kGenChunk * kGenPerSlot));
   constexpr int64_t kSlackChunk = int64_t(kGenChunk) * kSlackPerSlot;
   T->nchunks = std::max(1, T->gchunks + int((nslk + kSlackChunk - 1) / kSlackChunk));
   return ACOPF_OK;
@@ -505,15 +505,15 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
   close(b0, T.nb);
   if (tiler_error) return fail(ACOPF_EINVAL, "internal: work item positions outside the tile");
   S->counts[0] = int(S->tiles.size());
-  // generator chunks of kGenChunk items, then slack chunks of kGenChunk *
-  // kSlackPerSlot items (item k >= ng is slack variable k - ng)
+  // generator chunks of kGenChunk * kGenPerSlot items, then slack chunks of
+  // kGenChunk * kSlackPerSlot items (item k >= ng is slack variable k - ng)
   const int nitems = T.ng + T.sl.ns * T.nb;
   for (int c = 0; c < T.nchunks; ++c) {
     Tile tl{};
     tl.kind_aux = (c << 2) | TILE_GEN;
     if (c < T.gchunks) {
-      tl.a0 = c * kGenChunk;
-      tl.a1 = std::min(T.ng, (c + 1) * kGenChunk);
+      tl.a0 = c * kGenChunk * kGenPerSlot;
+      tl.a1 = std::min(T.ng, (c + 1) * kGenChunk * kGenPerSlot);
     } else {
       const int span = kGenChunk * kSlackPerSlot;
       tl.a0 = std::min(nitems, T.ng + (c - T.gchunks) * span);
@@ -872,7 +872,7 @@ static int run_plain(const acopf_net_s* net, unsigned variant, Bufs b, bool bus,
   const InstOff one = net_inst(net);
   if (B.topo.form == ACOPF_CARTESIAN) variant |= W_CART;
   hipError_t e = launch_eval(variant, kDefaultTileBe, b, nullptr, one, B.d_tiles + t0, t1 - t0, 0, s);
-  if (e == hipSuccess && b.f) e = launch_fsum(nullptr, one, 0, 1, b.fpart, b.f, s);
+  if (e == hipSuccess && b.f && B.topo.nchunks > 1) e = launch_fsum(nullptr, one, 0, 1, b.fpart, b.f, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return ACOPF_OK;
 }

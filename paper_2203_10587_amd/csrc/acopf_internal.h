@@ -17,6 +17,8 @@
 //             after another, the workgroup stores the row segments with
 //             consecutive lanes on consecutive entries.  The tile also writes
 //             the flow-limit rows of the branches whose from-bus it owns.
+//             A variant forming both J and H runs this twice in one tile:
+//             flows and J (records, rows, store), then H in the same LDS.
 //   gen tile  a fixed chunk of cost items (the generators, then the slack
 //             variables of a net that has them): f, grad f, the Pg diagonal of H
 #pragma once
@@ -26,7 +28,8 @@
 
 namespace acopf {
 
-constexpr int kGenChunk = 256;   // generators per gen tile; fixes the f reduction tree
+constexpr int kGenChunk = 256;   // reduction slots per gen tile; fixes the f reduction tree
+constexpr int kGenPerSlot = 4;   // generators per reduction slot: a generator chunk holds 1024
 constexpr int kSlackPerSlot = 8; // slack items per reduction slot: a slack chunk holds 2048
 constexpr uint32_t kNoSlot = 0xFFFFu;
 

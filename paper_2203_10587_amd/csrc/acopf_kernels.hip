@@ -1037,9 +1037,9 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
   const double sigma = B.sigma ? B.sigma[I.k] : B.sigma_v;
   const double wf = B.wf ? B.wf[I.k] : B.wf_v;
   const int hpg = N.hpg - 4 * I.out_rm;
-  // a slack chunk gives each reduction slot kSlackPerSlot items, summed in
-  // item order; a generator chunk one
-  const int per = k0 >= ng ? kSlackPerSlot : 1;
+  // each reduction slot sums its items in item order: kGenPerSlot
+  // generators, or kSlackPerSlot slack variables
+  const int per = k0 >= ng ? kSlackPerSlot : kGenPerSlot;
   for (int t = tid; t < kGenChunk; t += WG) {
     double term = 0.0;
     for (int r = 0; r < per; ++r) {
@@ -1082,7 +1082,7 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
           put(&o[2 * nb + k], sigma * (2.0 * c2 * Bm * Bm) * B.dir[I.xo + 2 * nb + k]);
           put(&o[2 * nb + ng + k], 0.0);
         }
-        if (fout) term = fma(fma(c2, p, c1), p, N.gen_c0[k]);
+        if (fout) term += fma(fma(c2, p, c1), p, N.gen_c0[k]);
       }
     }
     if (fout) smem[t] = term;
@@ -1094,12 +1094,19 @@ __device__ void gen_tile(const Bufs& B, const InstOff& I, const NetDev& N, int k
     for (int t = tid; t < s; t += WG) smem[t] = smem[t] + smem[t + s];
     __syncthreads();
   }
-  if (tid == 0) B.fpart[I.fpo + chunk] = smem[0];
+  if (tid == 0) {
+    if (N.nchunks == 1)
+      put(&B.f[I.k], smem[0]);  // the only partial is f (no k_fsum needed)
+    else
+      B.fpart[I.fpo + chunk] = smem[0];
+  }
 }
 
-// f of each instance: its chunk partials added in chunk order.  A kernel of
-// its own, enqueued after the evaluation on the same stream, so the
-// partials are visible without fences.
+// f of each instance with several chunks: its chunk partials added in chunk
+// order (a single-chunk instance has f written by its generator tile).  A
+// kernel of its own, enqueued after the evaluation on the same stream, so
+// the partials are visible without fences; the host skips it when no
+// instance has more than one chunk.
 __global__ __launch_bounds__(256) void k_fsum(const InstOff* __restrict__ table, InstOff one,
                                               int first, int count, const double* __restrict__ fpart,
                                               double* __restrict__ f) {
@@ -1107,6 +1114,7 @@ __global__ __launch_bounds__(256) void k_fsum(const InstOff* __restrict__ table,
   if (k >= first + count) return;
   const InstOff I = table ? table[k] : one;
   const int nch = I.net->nchunks;
+  if (nch == 1) return;
   double s = 0.0;
   for (int ch = 0; ch < nch; ++ch) s += fpart[I.fpo + ch];
   put(&f[I.k], s);

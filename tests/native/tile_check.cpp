@@ -106,7 +106,7 @@ extern "C" int tile_check(const acopf_net_desc* d, int tile_be, unsigned slacks)
     for (int ti = S.counts[0]; ti < S.counts[0] + S.counts[1]; ++ti) {
       const Tile& tl = S.tiles[ti];
       const bool slack = ti - S.counts[0] >= T.gchunks;
-      chk(tl.a0 == next && tl.a1 - tl.a0 <= kGenChunk * (slack ? kSlackPerSlot : 1),
+      chk(tl.a0 == next && tl.a1 - tl.a0 <= kGenChunk * (slack ? kSlackPerSlot : kGenPerSlot),
           "gen tile items", tl.a0, tl.a1);
       chk(slack ? tl.a0 >= T.ng : tl.a1 <= T.ng, "gen tile kind", tl.a0, tl.a1);
       chk((tl.kind_aux >> 2) == ti - S.counts[0], "gen tile chunk", ti, tl.kind_aux);

@@ -243,4 +243,9 @@ def test_uneven_scenarios_subset(gpu_lib):
     for i in sorted(chk):
         k, g, it = inst[i]
         log(f"[uneven_scenarios] instance {k} nb={g.nbus}")
-        compare_outputs(f"c3-{k}", P.instance(i), oracle_all(g, it, float(w_f[i]), w_c[i]))
+        compare_outputs(f"uneven-{k}", P.instance(i), oracle_all(g, it, float(w_f[i]), w_c[i]))
+    # f of every instance, one-chunk and several-chunk nets mixed in the
+    # batch, bit for bit against the plain path
+    fb = P.f.cpu().numpy()
+    for i, (k, g, it) in enumerate(inst):
+        assert fb[i] == plain(A, nets[i], it)["f"], (k, g.ngen)
