@@ -194,8 +194,9 @@ struct Rec {
 };
 
 // LDS of a bus tile, in doubles: the records, then the staged copy of the
-// tile's row segments (J P rows, J Q rows, H theta rows, H v rows, as far as
-// the variant forms them).
+// tile's row segments (J P rows and J Q rows, or H theta rows and H v rows;
+// the fused variant stages the H rows in the same space once its J rows are
+// stored).
 template <unsigned WHAT, int BE, int STAGE>
 struct Lds {
   static constexpr int kRec = Rec<WHAT>::N * BE;
