@@ -39,7 +39,8 @@ enum TileKind : int32_t { TILE_BUS = 1, TILE_GEN = 2 };
 // adjacency, work items [w0, w0 + nw), the largest parallel-branch group
 // among them (gmax), and the tile's row segments as base positions: J P rows
 // [jP0, jP0 + nP) (Q rows [jQ0, jQ0 + nP)), H theta rows [hT0, hT0 + nT),
-// H v rows [hV0, hV0 + nV).  Gen tile: generators [a0, a1);
+// H v rows [hV0, hV0 + nV).  Gen tile: cost items [a0, a1) (item k >= ng is
+// slack variable k - ng);
 // kind_aux = (chunk << 2) | kind.
 struct Tile {
   int32_t inst, kind_aux, a0, a1, e0, ne, w0, nw;
@@ -139,7 +140,7 @@ struct Bufs {
   double* u;
   const double* dir;        // direction of a Hessian- or Jacobian-vector product
   double* out;              // H dir (length n) or J dir (length m)
-  double* fpart;            // f partial sums, one per generator chunk
+  double* fpart;            // f partial sums, one per cost-item chunk
 };
 
 enum : unsigned {

@@ -24,11 +24,13 @@
 //            its balance rows.  No atomics: every sum has one owner and a
 //            fixed order, so results are bitwise reproducible whatever the
 //            tiling.
-//  gen tile  a fixed chunk of 256 generators: grad f, the Pg diagonal of H,
-//            the Pg/Qg part of the VJP and a fixed-tree partial sum of the
-//            cost; a second small kernel adds each instance's partials in
-//            chunk order into f (a kernel boundary instead of fences: an
-//            agent-scope release fence per chunk writes back the whole L2).
+//  gen tile  a fixed chunk of cost items (1024 generators or 2048 slack
+//            variables): grad f, the Pg (or slack) diagonal of H, those
+//            columns of the VJP and HVP, and a fixed-tree partial sum of the
+//            cost.  A net with one chunk has f written there; otherwise a
+//            second small kernel adds each instance's partials in chunk order
+//            (a kernel boundary instead of fences: an agent-scope release
+//            fence per chunk writes back the whole L2).
 //
 // The model (paper: OPFLOW section, power-balance-polar representation; the
 // formulation itself is the standard polar pi-model one the paper refers to):

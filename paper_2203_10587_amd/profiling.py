@@ -30,12 +30,39 @@ KERNEL_SOURCES = ["paper_2203_10587_amd/csrc/acopf_kernels.hip",
                   "paper_2203_10587_amd/csrc/acopf_internal.h"]
 
 
+def strip_comments(src: str) -> str:
+    """C/C++ source without its comments, with every run of white space
+    folded to one blank (string and character literals kept as they are)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            out.append(" ")
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_hash() -> str:
-    """Hash of the sources that define the evaluation kernel."""
+    """Hash of the sources that define the evaluation kernel, comments and
+    layout aside (so that a comment edit keeps the recorded counters)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as fh:
+            h.update(strip_comments(fh.read()).encode())
+            h.update(b"\0")
     return h.hexdigest()[:16]
 
 
