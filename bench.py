@@ -273,6 +273,68 @@ def served(seconds: float, rate: float = 2000.0, budget_gb: float = 8.0, log_pro
     return st
 
 
+def product_bytes(w, opts=None):
+    """Bytes each batched product must move per pass over the batch, with
+    the network primitives counted once per distinct network as in
+    algorithmic_bytes:
+      VJP  u = w_f grad f + J' w_c   reads x, w_c, w_f; writes u  (16 n + 8 m + 8)
+      HVP  H d                       reads x, lambda, sigma, d; writes H d  (24 n + 8 m + 8)
+      JVP  J d                       reads x, d; writes J d  (16 n + 8 m)"""
+    from paper_2203_10587_amd import acopf as A
+    tot = {"vjp": 0, "hvp": 0, "jvp": 0}
+    nets = set()
+    for k in range(count(w)):
+        g = w["base"] if w["kind"] == "outage" else w["grids"][k]
+        d, *_ = A.acopf_pattern_host_opts(g, opts, int(w["outages"][k]) if w["kind"] == "outage" else -1)
+        tot["vjp"] += 16 * d.n + 8 * d.m + 8
+        tot["hvp"] += 24 * d.n + 8 * d.m + 8
+        tot["jvp"] += 16 * d.n + 8 * d.m
+        if id(g) not in nets:
+            nets.add(id(g))
+            for key in tot:
+                tot[key] += 56 * g.nbranch + 32 * g.nbus + 28 * g.ngen
+    return tot
+
+
+def products_bench(A, w, model, batch, x, sigma, lam, nbus_total, steps, dev, stream):
+    """The batched VJP, HVP and JVP over the step's batch and iterates
+    (seeded directions and weights), each timed like the step: warm-up
+    launches, then `steps` launches back to back between two events."""
+    import torch
+    K = batch.count
+    nx, nc = int(batch.x_off[-1]), int(batch.c_off[-1])
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(20220321)
+    d = torch.randn(nx, dtype=torch.float64, device=dev, generator=gen)
+    wc = torch.randn(nc, dtype=torch.float64, device=dev, generator=gen)
+    wf = torch.ones(K, dtype=torch.float64, device=dev)
+    u = torch.empty(nx, dtype=torch.float64, device=dev)
+    hd = torch.empty(nx, dtype=torch.float64, device=dev)
+    jd = torch.empty(nc, dtype=torch.float64, device=dev)
+    calls = {"vjp": lambda: A.acopf_batch_vjp(batch, x, wf, wc, u, stream),
+             "hvp": lambda: A.acopf_batch_hvp(batch, x, sigma, lam, d, hd, stream),
+             "jvp": lambda: A.acopf_batch_jvp(batch, x, d, jd, stream)}
+    nbytes = product_bytes(w, model_opts(A, model))
+    out = {}
+    for name, call in calls.items():
+        for _ in range(max(10, steps // 2)):
+            call()
+        s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s_.record(stream)
+        for _ in range(steps):
+            call()
+        e_.record(stream)
+        torch.cuda.synchronize()
+        ms = s_.elapsed_time(e_) / steps
+        gbs = nbytes[name] / (ms / 1e3) / 1e9
+        out[name] = {"ms_per_step": ms, "value": nbus_total / (ms / 1e3), "unit": "bus-evals/s",
+                     "algorithmic_bytes": nbytes[name], "achieved_GBps": gbs,
+                     "frac": gbs / HBM_PEAK_GBS}
+        log(f"[bench] {name}: {ms:.4f} ms/step, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.3f} of peak)")
+    return out
+
+
 def make_nets(A, w, model):
     """(base or None, one net per instance) of the workload for a model."""
     opts = model_opts(A, model)
@@ -355,7 +417,8 @@ def main():
                     help="formulation of the timed step: polar (default), cartesian, or polar "
                          "with load-loss and power-imbalance slacks")
     ap.add_argument("--no-variants", dest="variants", action="store_false",
-                    help="skip timing the workload in the other formulations")
+                    help="skip timing the workload in the other formulations and the "
+                         "batched products (VJP, HVP, JVP)")
     ap.add_argument("--tile-be", type=int, default=0)
     ap.add_argument("--grid-mult", type=int, default=-1)
     ap.add_argument("--xcd", type=int, default=-1)
@@ -519,6 +582,12 @@ def main():
     # the same workload in the other model variants: the power-balance-cartesian
     # representation, and the polar one with both slack blocks (load loss and
     # power imbalance); each has its own nets, batch and seeded iterates
+    # the batched products over the same batch and iterates
+    products = None
+    if args.variants:
+        products = products_bench(A, w, args.model, batch, x, sigma, lam, nbus_total, args.steps,
+                                  dev, stream)
+
     variants = {}
     if args.variants:
         for mname in MODELS:
@@ -585,6 +654,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "plain": plain,
         "coupled": coupled,
+        "products": products,
         "variants": variants or None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

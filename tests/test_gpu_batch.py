@@ -220,6 +220,53 @@ def test_n1_security_set_full_size(gpu_lib):
         assert np.all(np.abs(sums) <= 1e-12 * scale * 8), k
 
 
+def test_n1_products_full_size(gpu_lib):
+    """The batched VJP, HVP and JVP over the 1,000 N-1 outages of the
+    2,000-bus grid in the benchmark's launch: sampled instances against the
+    oracle's gradient and matrices (H full and symmetric), with the rounding
+    scales of the single-instance product tests."""
+    torch = _t()
+    from paper_2203_10587_amd import acopf as A
+    from paper_2203_10587_amd import tune
+    os_ = S.n1_security_set(0)
+    base, nets = _nets(A, os_)
+    b = A.acopf_batch_create(nets, **tune.lookup_or_default(nets))
+    rng = np.random.default_rng(11)
+    K = len(nets)
+    w_c = [rng.standard_normal(it.lam.shape) for it in os_.iterates]
+    w_f = rng.standard_normal(K)
+    P = Packed(A, b, os_.iterates, w_f, w_c)
+    nx, nc = int(b.x_off[-1]), int(b.c_off[-1])
+    dh = rng.standard_normal(nx)
+    dt = torch.as_tensor(dh, device="cuda")
+    hd = torch.full((nx,), np.nan, dtype=torch.float64, device="cuda")
+    jd = torch.full((nc,), np.nan, dtype=torch.float64, device="cuda")
+    P.vjp()
+    A.acopf_batch_hvp(b, P.x, P.sigma, P.lam, dt, hd)
+    A.acopf_batch_jvp(b, P.x, dt, jd)
+    torch.cuda.synchronize()
+    u, hd, jd = P.u.cpu().numpy(), hd.cpu().numpy(), jd.cpu().numpy()
+    assert np.all(np.isfinite(u)) and np.all(np.isfinite(hd)) and np.all(np.isfinite(jd))
+    for k in (0, 1, 500, 999):
+        log(f"[n1_products] oracle instance {k}")
+        g2, it = S.n1_instance(os_, k)
+        mdl = O.prepare(g2)
+        xs, cs = slice(int(b.x_off[k]), int(b.x_off[k + 1])), slice(int(b.c_off[k]), int(b.c_off[k + 1]))
+        d = dh[xs]
+        out = O.evaluate(mdl, it.x, it.sigma, it.lam)
+        J = O.jacobian_matrix(mdl, it.x)
+        H = O.hessian_matrix(mdl, it.x, it.sigma, it.lam)
+        want_u = O.vjp(mdl, it.x, float(w_f[k]), w_c[k])
+        assert_close(f"vjp {k}", u[xs], want_u, O.vjp_scale(mdl, it.x, float(w_f[k]), w_c[k]))
+        sj = O.jacobian_row_scales(mdl, it.x, out["jac_val"])
+        rows = np.repeat(np.arange(mdl.m), np.diff(mdl.jac_rowptr))
+        jscale = np.bincount(rows, weights=sj * np.abs(d[mdl.jac_col]), minlength=mdl.m)
+        assert_close(f"jvp {k}", jd[cs], J @ d, jscale)
+        Habs = abs(H).tocsr()
+        rowmax = Habs.max(axis=1).toarray().ravel()
+        assert_close(f"hvp {k}", hd[xs], H @ d, rowmax * ((Habs > 0).astype(float) @ np.abs(d)))
+
+
 def test_uneven_scenarios_subset(gpu_lib):
     """The uneven scenario workload: a 64-instance draw spanning the size
     range, batched with VJP; smallest, median and largest instances against
