@@ -93,9 +93,11 @@ class Executor:
 
 
 class _Pool:
-    """Slot occupancy of one grid.  Windows take a contiguous run of free
-    slots starting at the rotating head (or at 0); slots of a window that
-    timed out stay occupied, since the device may still write them."""
+    """Slot occupancy of one grid.  A window takes the contiguous run of free
+    slots (at most the wanted number, not wrapping past the last slot) that
+    starts at the first free slot found from the rotating head onwards,
+    cyclically; it fails only when every slot is taken.  Slots of a window
+    that timed out stay occupied, since the device may still write them."""
 
     def __init__(self, capacity: int):
         self.capacity = int(capacity)
@@ -103,17 +105,20 @@ class _Pool:
         self.head = 0
 
     def alloc(self, want: int):
-        for start in (self.head, 0):
-            if start >= self.capacity:
+        cap = self.capacity
+        if want <= 0 or cap <= 0:
+            return None
+        for i in range(cap):
+            start = (self.head + i) % cap
+            if self.occ[start]:
                 continue
             run = 0
-            while run < want and start + run < self.capacity and not self.occ[start + run]:
+            while run < want and start + run < cap and not self.occ[start + run]:
                 run += 1
-            if run:
-                for k in range(start, start + run):
-                    self.occ[k] = True
-                self.head = start + run
-                return start, run
+            for k in range(start, start + run):
+                self.occ[k] = True
+            self.head = (start + run) % cap
+            return start, run
         return None
 
     def free(self, first: int, k: int):

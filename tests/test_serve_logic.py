@@ -229,3 +229,20 @@ def test_seeded_only_executor_rejects_inputs():
     srv = Server(FakeExecutor(clock), clock=clock)
     r = srv.submit(0, x=[1.0], lam=[1.0])
     assert r.status == "rejected"
+
+
+def test_pool_finds_any_free_slot():
+    """A window is placed whenever some slot is free, also when the slot at
+    the head and slot 0 are both taken; runs never wrap past the last slot."""
+    from paper_2203_10587_amd.serve import _Pool
+    p = _Pool(6)
+    assert p.alloc(2) == (0, 2) and p.alloc(3) == (2, 3)   # slots 0..4 taken, head 5
+    assert p.alloc(4) == (5, 1)                            # the run stops at the end
+    assert p.alloc(1) is None                              # all six taken
+    p.free(3, 1)                                           # head 0 taken, slot 3 free
+    assert p.alloc(2) == (3, 1)
+    p.free(0, 2)
+    p.free(4, 1)
+    assert p.alloc(8) == (4, 1)                            # head was 4; slot 5 taken
+    assert p.alloc(8) == (0, 2)
+    assert p.alloc(1) is None
