@@ -47,6 +47,7 @@ struct acopf_batch_s {
   int ntiles = 0;
   int grid = 0;  // 0: one workgroup per tile
   acopf::Tile* d_tiles_inst = nullptr;  // the same tiles, instance after instance
+  acopf::WorkItem* d_work = nullptr;    // work items of every distinct base, back to back
   std::vector<int32_t> inst_tile_off;   // count + 1
   int max_len = 0;                      // max n + m over instances
   int max_chunks = 1;                   // f partials per instance, at most
@@ -105,7 +106,8 @@ unsigned variant_of(unsigned what) {
 
 // The evaluation kernel, then (if f is wanted) the f reduction.
 hipError_t enqueue(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStream_t s) {
-  const InstOff none{};
+  InstOff none{};
+  none.work = b->d_work;  // the tiles' w0 index this array
   hipError_t e = launch_eval(variant, b->sched.tile_be, bufs, b->d_table, none, b->d_tiles,
                              b->ntiles, b->grid, s);
   // a single-chunk instance has its f written by its generator tile
@@ -233,6 +235,10 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
       }
       pb.work_off = work_total;
       work_total += pb.sch.work.size();
+      if (work_total > size_t(INT32_MAX)) {
+        free_batch(b);
+        return fail(ACOPF_EINVAL, "the batch's work items exceed 2^31");
+      }
       per_base.emplace(B, std::move(pb));
     }
     // XCD queues, largest instances first (LPT on tile counts)
@@ -244,8 +250,10 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     std::vector<int64_t> load(queue.size(), 0);
     for (int k : order) {
       const size_t qi = std::min_element(load.begin(), load.end()) - load.begin();
-      for (Tile t : per_base[nets[k]->base.get()].sch.tiles) {
+      const PerBase& pb = per_base[nets[k]->base.get()];
+      for (Tile t : pb.sch.tiles) {
         t.inst = k;
+        t.w0 += int32_t(pb.work_off);
         queue[qi].push_back(t);
       }
       load[qi] += ntile(k);
@@ -253,8 +261,10 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     std::vector<Tile> tiles_inst;
     b->inst_tile_off.assign(count + 1, 0);
     for (int k = 0; k < count; ++k) {
-      for (Tile t : per_base[nets[k]->base.get()].sch.tiles) {
+      const PerBase& pb = per_base[nets[k]->base.get()];
+      for (Tile t : pb.sch.tiles) {
         t.inst = k;
+        t.w0 += int32_t(pb.work_off);
         tiles_inst.push_back(t);
       }
       b->inst_tile_off[k + 1] = int32_t(tiles_inst.size());
@@ -295,6 +305,7 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     b->d_table = reinterpret_cast<InstOff*>(base);
     b->d_tiles = reinterpret_cast<Tile*>(base + s_table);
     WorkItem* d_work = reinterpret_cast<WorkItem*>(base + s_table + s_tiles);
+    b->d_work = d_work;
     b->d_fpart = reinterpret_cast<double*>(base + s_table + s_tiles + s_work);
     b->d_tiles_inst = reinterpret_cast<Tile*>(base + s_table + s_tiles + s_work + s_fpart);
     std::vector<InstOff> table(count);
@@ -429,7 +440,8 @@ int acopf_batch_eval_range(acopf_batch b, int32_t first, int32_t count, const do
   bufs.hess = (what & ACOPF_H) ? hess_val : nullptr;
   bufs.fpart = b->d_fpart;
   const int t0 = b->inst_tile_off[first], t1 = b->inst_tile_off[first + count];
-  const InstOff none{};
+  InstOff none{};
+  none.work = b->d_work;  // the tiles' w0 index this array
   const unsigned variant = variant_of(what) | (b->form == ACOPF_CARTESIAN ? W_CART : 0u);
   e = launch_eval(variant, b->sched.tile_be, bufs, b->d_table, none, b->d_tiles_inst + t0,
                   t1 - t0, 0, stream);

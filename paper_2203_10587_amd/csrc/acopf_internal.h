@@ -36,7 +36,8 @@ constexpr uint32_t kNoSlot = 0xFFFFu;
 enum TileKind : int32_t { TILE_BUS = 1, TILE_GEN = 2 };
 
 // A unit of work.  Bus tile: buses [a0, a1), branch ends [e0, e0 + ne) of the
-// adjacency, work items [w0, w0 + nw), the largest parallel-branch group
+// adjacency, work items [w0, w0 + nw) of the launch's work array (a batch
+// holds every distinct base's items back to back), the largest parallel-branch group
 // among them (gmax), and the tile's row segments as base positions: J P rows
 // [jP0, jP0 + nP) (Q rows [jQ0, jQ0 + nP)), H theta rows [hT0, hT0 + nT),
 // H v rows [hV0, hV0 + nV).  Gen tile: cost items [a0, a1) (item k >= ng is
@@ -112,7 +113,8 @@ struct NetDev {
 // the number of removed positions before it.
 struct InstOff {
   const NetDev* net;
-  const WorkItem* work;     // work items of the schedule in use
+  const WorkItem* work;     // work items of the schedule in use; kernels read them through
+                            // the launch's `one` argument (a batch's tiles index its array)
   int32_t out_l;            // removed branch, -1 for none
   int32_t out_rm;           // 1 if the removal drops the (p, q) slots
   int32_t rj[8];

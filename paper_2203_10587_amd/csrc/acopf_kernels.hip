@@ -264,7 +264,7 @@ __device__ __forceinline__ void group_sum(double (&v)[NV], int g, int gmax) {
 
 template <unsigned WHAT, int WG, int BE, int NBUS, int STAGE>
 __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const Tile& T,
-                         double* smem) {
+                         const WorkItem* __restrict__ work, double* smem) {
   using R = Rec<WHAT>;
   using L = Lds<WHAT, BE, STAGE>;
   static_assert(NBUS <= WG, "one bus per lane");
@@ -332,7 +332,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       const int k = k0 + tid;
       WorkItem wi{};
       wi.l = -2;  // lanes past the list: no branch, no group
-      if (k < T.nw) wi = I.work[T.w0 + k];
+      if (k < T.nw) wi = work[T.w0 + k];
       const int l = wi.l, f = wi.f, t = wi.t;
       const uint32_t sf = wi.slots & 0xFFFFu, st = wi.slots >> 16;
       const bool live = l >= 0 && l != ol;
@@ -553,7 +553,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       const int k = k0 + tid;
       WorkItem wi{};
       wi.l = -2;  // lanes past the list: no branch, no group
-      if (k < T.nw) wi = I.work[T.w0 + k];
+      if (k < T.nw) wi = work[T.w0 + k];
       const int l = wi.l, f = wi.f, t = wi.t;
       const uint32_t sf = wi.slots & 0xFFFFu, st = wi.slots >> 16;
       const bool live = l >= 0 && l != ol;
@@ -1135,7 +1135,7 @@ __global__ __launch_bounds__(WG) void k_eval(Bufs B, const InstOff* __restrict__
     const InstOff I = table ? table[T.inst] : one;
     const NetDev& N = *I.net;
     if ((T.kind_aux & 3) == TILE_BUS) {
-      bus_tile<WHAT, WG, BE, NBUS, STAGE>(B, I, N, T, smem);
+      bus_tile<WHAT, WG, BE, NBUS, STAGE>(B, I, N, T, one.work, smem);
     } else {
       if constexpr ((WHAT & (W_F | W_GRADF | W_H | W_VJP | W_HVP)) != 0)
         gen_tile<WHAT, WG>(B, I, N, T.a0, T.a1, T.kind_aux >> 2, smem);
