@@ -295,7 +295,8 @@ typedef struct {
  * exists): per-instance offsets, the XCD-aware tile list and the device
  * descriptor table.  `sched` may be NULL for the default schedule
  * {256, 0, 1, 0}.  Errors: EINVAL (also when a bus exceeds the tile
- * capacity of the schedule), ENOMEM, EHIP. */
+ * capacity of the schedule, or the distinct networks' branch work items
+ * exceed 2^31 in total), ENOMEM, EHIP. */
 int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* sched,
                        acopf_batch* out);
 int acopf_batch_destroy(acopf_batch batch);
