@@ -20,13 +20,19 @@ _M1 = np.uint64(0xBF58476D1CE4E5B9)
 _M2 = np.uint64(0x94D049BB133111EB)
 
 
-def uniforms(seed: int, j: np.ndarray) -> np.ndarray:
+def splitmix64(seed: int, j: np.ndarray) -> np.ndarray:
+    """Raw 64-bit output for stream elements j: output j + 1 of SplitMix64
+    started at state `seed`."""
     with np.errstate(over="ignore"):
-        x = np.uint64(seed) + (j.astype(np.uint64) + np.uint64(1)) * _GAMMA
+        x = np.uint64(seed) + (np.asarray(j).astype(np.uint64) + np.uint64(1)) * _GAMMA
         z = (x ^ (x >> np.uint64(30))) * _M1
         z = (z ^ (z >> np.uint64(27))) * _M2
-        z = z ^ (z >> np.uint64(31))
-    return (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+        return z ^ (z >> np.uint64(31))
+
+
+def uniforms(seed: int, j: np.ndarray) -> np.ndarray:
+    """Doubles in [0, 1) from the top 53 bits of splitmix64(seed, j)."""
+    return (splitmix64(seed, j) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
 
 
 def request_iterate(seed: int, nb: int, ng: int, m: int, bounds):
