@@ -96,7 +96,9 @@ typedef struct acopf_batch_s* acopf_batch;
  * kept; the caller keeps ownership.  Bus ids are 0-based.  Validation:
  * nbus >= 1, nbranch >= 0, ngen >= 0, base_mva > 0, endpoints in range and
  * distinct, not both r and x zero, tap > 0, generator buses in range,
- * every value finite.  Parallel branches are allowed. */
+ * every value finite.  Parallel branches are allowed.  br_rate is not used
+ * by the evaluation; it sets the flow rows' upper bounds (acopf_flow_limits,
+ * the h+ of the OPFLOW section's inequality h- <= h(x) <= h+). */
 typedef struct {
   int32_t nbus, nbranch, ngen;
   double base_mva;                  /* the cost is on MW = base_mva * Pg   */
@@ -107,6 +109,8 @@ typedef struct {
   const double* br_b;               /* [nbranch] total charging, pu        */
   const double* br_tap;             /* [nbranch] tap ratio (1 for lines)   */
   const double* br_shift;           /* [nbranch] phase shift, rad          */
+  const double* br_rate;            /* [nbranch] apparent-power limit, pu;
+                                       <= 0: unlimited                     */
   const double* bus_pd;             /* [nbus] active load, pu              */
   const double* bus_qd;             /* [nbus] reactive load, pu            */
   const double* bus_gs;             /* [nbus] shunt conductance at v = 1   */
@@ -120,6 +124,7 @@ typedef struct {
 typedef struct {
   int64_t n;         /* 2 nbus + 2 ngen (+ nbus per slack block)           */
   int64_t m;         /* 2 nbus + 2 (live branches) (+ nbus, cartesian)     */
+  int64_t m_eq;      /* equality rows g = 0, the first 2 nbus rows of c    */
   int64_t nnz_jac;   /* Jacobian pattern entries                           */
   int64_t nnz_hess;  /* lower-Hessian pattern entries                      */
   int32_t nbus, nbranch, ngen;
@@ -152,6 +157,17 @@ int acopf_dims_get(acopf_net net, acopf_dims* out);
  * nnz_hess.  Any pointer may be NULL to skip that array. */
 int acopf_pattern(acopf_net net, int32_t* jac_rowptr, int32_t* jac_col,
                   int32_t* hess_rowptr, int32_t* hess_col);
+
+/* Upper bounds h+ of the flow rows (paper: OPFLOW section, h- <= h(x) <= h+
+ * with h the squared apparent flows): hmax[r] = rate^2 for flow row r, in the
+ * order of c (from ends of the live branches, then their to ends), +inf for a
+ * branch whose rate is <= 0; the lower bounds are 0.  hmax: caller-owned HOST
+ * array of 2 (live branches) entries.  Errors: EINVAL. */
+int acopf_flow_limits(acopf_net net, double* hmax);
+
+/* acopf_flow_limits for a description (no device needed); `outage` = -1 for
+ * the base network, else the branch to remove. */
+int acopf_flow_limits_host(const acopf_net_desc* desc, int32_t outage, double* hmax);
 
 /* Host-only form of acopf_pattern for a description (no device needed):
  * fills *dims (may be NULL) and, where non-NULL, the four arrays.
@@ -325,6 +341,14 @@ int acopf_batch_hvp(acopf_batch batch, const double* x, const double* sigma,
                     const double* lambda, const double* d, double* out, hipStream_t stream);
 int acopf_batch_jvp(acopf_batch batch, const double* x, const double* d, double* out,
                     hipStream_t stream);
+
+/* Per-instance dot products over the packed x layout: out[k] = a_k . v_k,
+ * the sum over the n_k entries of instance k (a, v packed like x; out has
+ * count entries; DEVICE pointers), added in a fixed order.  With a = grad f
+ * it is the directional derivative of each objective, which the second-order
+ * adjoint of the batched VJP needs for the weight w_f.  Errors: EINVAL, EHIP. */
+int acopf_batch_xdot(acopf_batch batch, const double* a, const double* v, double* out,
+                     hipStream_t stream);
 
 /* As acopf_batch_eval, for the instances [first, first + count) only (same
  * packed buffers and offsets; other instances' outputs are not touched).

@@ -37,13 +37,13 @@ class acopf_net_desc(C.Structure):
     _fields_ = [("nbus", C.c_int32), ("nbranch", C.c_int32), ("ngen", C.c_int32),
                 ("base_mva", C.c_double),
                 ("br_from", _i32p), ("br_to", _i32p), ("br_r", _f64p), ("br_x", _f64p),
-                ("br_b", _f64p), ("br_tap", _f64p), ("br_shift", _f64p),
+                ("br_b", _f64p), ("br_tap", _f64p), ("br_shift", _f64p), ("br_rate", _f64p),
                 ("bus_pd", _f64p), ("bus_qd", _f64p), ("bus_gs", _f64p), ("bus_bs", _f64p),
                 ("gen_bus", _i32p), ("gen_c2", _f64p), ("gen_c1", _f64p), ("gen_c0", _f64p)]
 
 
 class acopf_dims(C.Structure):
-    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("nnz_jac", C.c_int64),
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("m_eq", C.c_int64), ("nnz_jac", C.c_int64),
                 ("nnz_hess", C.c_int64), ("nbus", C.c_int32), ("nbranch", C.c_int32),
                 ("ngen", C.c_int32), ("outage", C.c_int32)]
 
@@ -86,6 +86,8 @@ _SIGS = {
     "acopf_pattern": (C.c_int, [C.c_void_p, _i32p, _i32p, _i32p, _i32p]),
     "acopf_pattern_host": (C.c_int, [C.POINTER(acopf_net_desc), C.c_int32, C.POINTER(acopf_dims),
                                      _i32p, _i32p, _i32p, _i32p]),
+    "acopf_flow_limits": (C.c_int, [C.c_void_p, _f64p]),
+    "acopf_flow_limits_host": (C.c_int, [C.POINTER(acopf_net_desc), C.c_int32, _f64p]),
     "acopf_pattern_host_form": (C.c_int, [C.POINTER(acopf_net_desc), C.c_int32, C.c_int32,
                                           C.POINTER(acopf_dims), _i32p, _i32p, _i32p, _i32p]),
     "acopf_eval_f_g": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -109,6 +111,7 @@ _SIGS = {
     "acopf_batch_offsets": (C.c_int, [C.c_void_p, _i64p, _i64p, _i64p, _i64p]),
     "acopf_batch_eval": (C.c_int, [C.c_void_p] + [C.c_void_p] * 8 + [C.c_uint, C.c_void_p]),
     "acopf_batch_vjp": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4 + [C.c_void_p]),
+    "acopf_batch_xdot": (C.c_int, [C.c_void_p] * 5),
     "acopf_batch_eval_range": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 8
                                + [C.c_uint, C.c_void_p]),
     "acopf_batch_draw_iterates": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
@@ -157,6 +160,7 @@ class _Desc:
         self.arrs = dict(
             br_from=i32(g.br_from), br_to=i32(g.br_to), br_r=f64(g.br_r), br_x=f64(g.br_x),
             br_b=f64(g.br_b), br_tap=f64(g.br_tap), br_shift=f64(g.br_shift),
+            br_rate=f64(g.br_rate),
             bus_pd=f64(g.bus_pd), bus_qd=f64(g.bus_qd), bus_gs=f64(g.bus_gs), bus_bs=f64(g.bus_bs),
             gen_bus=i32(g.gen_bus), gen_c2=f64(g.gen_c2), gen_c1=f64(g.gen_c1),
             gen_c0=f64(g.gen_c0))
@@ -289,6 +293,21 @@ def acopf_pattern(net: Net):
     _check(lib().acopf_pattern(net.handle, jp.ctypes.data_as(_i32p), jc.ctypes.data_as(_i32p),
                                hp.ctypes.data_as(_i32p), hc.ctypes.data_as(_i32p)))
     return jp, jc, hp, hc
+
+
+def acopf_flow_limits(net: Net) -> np.ndarray:
+    """h+ of the net's flow rows (host float64 array of 2 live branches)."""
+    out = np.empty(2 * int(net.dims.nbranch), np.float64)
+    _check(lib().acopf_flow_limits(net.handle, out.ctypes.data_as(_f64p)))
+    return out
+
+
+def acopf_flow_limits_host(grid, outage: int = -1) -> np.ndarray:
+    d = _Desc(grid)
+    live = len(d.arrs["br_from"]) - (1 if outage >= 0 else 0)
+    out = np.empty(2 * live, np.float64)
+    _check(lib().acopf_flow_limits_host(C.byref(d.desc), int(outage), out.ctypes.data_as(_f64p)))
+    return out
 
 
 def acopf_pattern_host(grid, outage: int = -1):
@@ -427,6 +446,12 @@ def acopf_batch_eval(b: Batch, x, sigma, lam, f, grad_f, c, jac_val, hess_val,
         _ptr(grad_f, int(b.x_off[-1]), "grad_f"), _ptr(c, int(b.c_off[-1]), "c"),
         _ptr(jac_val, int(b.j_off[-1]), "jac_val"), _ptr(hess_val, int(b.h_off[-1]), "hess_val"),
         C.c_uint(what), _stream(stream)))
+
+
+def acopf_batch_xdot(b: Batch, a, v, out, stream=None):
+    nx = int(b.x_off[-1])
+    _check(lib().acopf_batch_xdot(b.handle, _ptr(a, nx, "a"), _ptr(v, nx, "v"),
+                                  _ptr(out, b.count, "out"), _stream(stream)))
 
 
 def acopf_batch_vjp(b: Batch, x, w_f, w_c, u, stream=None):

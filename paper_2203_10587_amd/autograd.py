@@ -11,7 +11,7 @@ backward works:
   d/dx    of u along a direction dx = (g_f grad^2 f + sum g_c,r grad^2 c_r) dx
           (Hessian-vector product kernel, H never formed);
   d/dg_c  = J dx (Jacobian-vector product kernel);
-  d/dg_f  = grad f . dx.
+  d/dg_f  = grad f . dx (per-instance dot product kernel).
 """
 from __future__ import annotations
 
@@ -59,9 +59,8 @@ class _BatchVjp(torch.autograd.Function):
         if ctx.needs_input_grad[1]:
             gf = torch.empty_like(x)
             A.acopf_batch_eval(b, x, None, None, None, gf, None, None, None, A.ACOPF_GRADF)
-            prod = gf * gu
-            gwf = torch.stack([prod[int(b.x_off[k]):int(b.x_off[k + 1])].sum()
-                               for k in range(b.count)])
+            gwf = torch.empty_like(w_f)
+            A.acopf_batch_xdot(b, gf, gu, gwf)
         return gx, gwf, gwc, None
 
 

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libacopf.so")
 SOURCES = ["acopf_host.cpp", "acopf_batch.cpp", "acopf_kernels.hip", "acopf_rng.hip",
-           "acopf_couple.hip"]
+           "acopf_couple.hip", "acopf_reduce.hip"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [

@@ -483,6 +483,18 @@ int acopf_batch_vjp(acopf_batch b, const double* x, const double* w_f, const dou
   return run_batch(b, K_VJP, bufs, stream);
 }
 
+int acopf_batch_xdot(acopf_batch b, const double* a, const double* v, double* out,
+                     hipStream_t stream) {
+  if (!b || !a || !v || !out) return fail(ACOPF_EINVAL, "null argument");
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != b->device) return fail(ACOPF_EINVAL, "batch lives on another device");
+  e = launch_xdot(b->d_table, b->count, a, v, out, stream);
+  if (e != hipSuccess) return hip_fail(e, "dot kernel launch");
+  return ACOPF_OK;
+}
+
 // ---------------------------------------------------------------------------
 // coupling rows
 

@@ -77,7 +77,7 @@ int build_topology(const acopf_net_desc* d, const acopf_net_opts* o, Topology* T
   if (!(d->base_mva > 0.0) || !finite(d->base_mva)) return fail(ACOPF_EINVAL, "base_mva must be > 0");
   const int nb = d->nbus, nl = d->nbranch, ng = d->ngen;
   if (nl > 0 && (!d->br_from || !d->br_to || !d->br_r || !d->br_x || !d->br_b || !d->br_tap ||
-                 !d->br_shift))
+                 !d->br_shift || !d->br_rate))
     return fail(ACOPF_EINVAL, "null branch array");
   if (!d->bus_pd || !d->bus_qd || !d->bus_gs || !d->bus_bs) return fail(ACOPF_EINVAL, "null bus array");
   if (ng > 0 && (!d->gen_bus || !d->gen_c2 || !d->gen_c1 || !d->gen_c0))
@@ -90,6 +90,7 @@ int build_topology(const acopf_net_desc* d, const acopf_net_opts* o, Topology* T
   T->base = d->base_mva;
   T->ft.resize(nl);
   T->y.resize(nl);
+  T->rate.resize(nl);
   for (int l = 0; l < nl; ++l) {
     const int f = d->br_from[l], t = d->br_to[l];
     if (f < 0 || f >= nb || t < 0 || t >= nb)
@@ -97,8 +98,10 @@ int build_topology(const acopf_net_desc* d, const acopf_net_opts* o, Topology* T
     if (f == t) return fail(ACOPF_EINVAL, "branch " + std::to_string(l) + ": from == to");
     const double r = d->br_r[l], x = d->br_x[l], b = d->br_b[l];
     const double tap = d->br_tap[l], sh = d->br_shift[l];
-    if (!finite(r) || !finite(x) || !finite(b) || !finite(tap) || !finite(sh))
+    if (!finite(r) || !finite(x) || !finite(b) || !finite(tap) || !finite(sh) ||
+        !finite(d->br_rate[l]))
       return fail(ACOPF_EINVAL, "branch " + std::to_string(l) + ": non-finite parameter");
+    T->rate[l] = d->br_rate[l];
     if (r == 0.0 && x == 0.0)
       return fail(ACOPF_EINVAL, "branch " + std::to_string(l) + ": zero impedance");
     if (!(tap > 0.0)) return fail(ACOPF_EINVAL, "branch " + std::to_string(l) + ": tap must be > 0");
@@ -241,12 +244,25 @@ void fill_dims(const Topology& T, int32_t outage, int32_t rm, acopf_dims* d) {
   const bool cart = T.form == ACOPF_CARTESIAN;
   d->n = 2 * int64_t(T.nb) + 2 * int64_t(T.ng) + int64_t(T.sl.ns) * T.nb;
   d->m = 2 * int64_t(T.nb) + 2 * int64_t(live) + (cart ? T.nb : 0);
+  d->m_eq = 2 * int64_t(T.nb);
   d->nnz_jac = T.nnz_jac - (outage >= 0 ? 8 + 8 * rm : 0) + (cart ? 2 * int64_t(T.nb) : 0);
   d->nnz_hess = T.nnz_hess - (outage >= 0 ? 4 * rm : 0);
   d->nbus = T.nb;
   d->nbranch = live;
   d->ngen = T.ng;
   d->outage = outage;
+}
+
+// h+ of the live branches' flow rows: from ends, then to ends.
+void flow_limits(const Topology& T, int32_t outage, double* hmax) {
+  const int live = T.nl - (outage >= 0 ? 1 : 0);
+  int r = 0;
+  for (int l = 0; l < T.nl; ++l) {
+    if (l == outage) continue;
+    const double a = T.rate[l];
+    hmax[r] = hmax[r + live] = a > 0.0 ? a * a : HUGE_VAL;
+    ++r;
+  }
 }
 
 // The structural pattern rule, applied to the live branches.
@@ -646,7 +662,7 @@ extern "C" {
 
 const char* acopf_last_error(void) { return t_err.c_str(); }
 
-int acopf_version(void) { return 10300; }
+int acopf_version(void) { return 10400; }
 
 static acopf_net_opts form_opts(int32_t form) {
   acopf_net_opts o{};
@@ -659,6 +675,27 @@ int acopf_pattern_host(const acopf_net_desc* desc, int32_t outage, acopf_dims* d
                        int32_t* hess_col) {
   return acopf_pattern_host_opts(desc, nullptr, outage, dims, jac_rowptr, jac_col, hess_rowptr,
                                  hess_col);
+}
+
+int acopf_flow_limits_host(const acopf_net_desc* desc, int32_t outage, double* hmax) {
+  if (!hmax) return fail(ACOPF_EINVAL, "null hmax");
+  try {
+    Topology T;
+    int rc = build_topology(desc, nullptr, &T);
+    if (rc) return rc;
+    if (outage < -1 || outage >= T.nl) return fail(ACOPF_EINVAL, "outage must be -1 or a branch index");
+    flow_limits(T, outage, hmax);
+    t_err.clear();
+    return ACOPF_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(ACOPF_ENOMEM, "host allocation failed");
+  }
+}
+
+int acopf_flow_limits(acopf_net net, double* hmax) {
+  if (!net || !hmax) return fail(ACOPF_EINVAL, "null net or hmax");
+  flow_limits(net->base->topo, net->out_l, hmax);
+  return ACOPF_OK;
 }
 
 int acopf_pattern_host_form(const acopf_net_desc* desc, int32_t form, int32_t outage,

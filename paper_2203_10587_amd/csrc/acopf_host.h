@@ -21,6 +21,7 @@ struct Topology {
   std::vector<int2> ft;
   std::vector<BranchY> y;
   std::vector<double4> bus;
+  std::vector<double> rate;       // apparent-power limit per branch (<= 0: none)
   std::vector<int32_t> gen_bus;
   std::vector<double> c2, c1, c0;
   std::vector<int32_t> be_ptr, be;
@@ -74,6 +75,7 @@ int hip_fail(hipError_t e, const char* what);
 int build_topology(const acopf_net_desc* d, const acopf_net_opts* o, Topology* T);
 int outage_info(const Topology& T, int32_t l, int32_t* p, int32_t* q, int32_t* rm);
 void fill_dims(const Topology& T, int32_t outage, int32_t rm, acopf_dims* d);
+void flow_limits(const Topology& T, int32_t outage, double* hmax);
 void build_pattern(const Topology& T, int32_t outage, std::vector<int32_t>* jp,
                    std::vector<int32_t>* jc, std::vector<int32_t>* hp, std::vector<int32_t>* hc);
 int make_tiles(const Topology& T, int tile_be, Schedule* S);
@@ -83,5 +85,10 @@ int upload_base(Base* B);
 int net_init_scratch(acopf_net_s* net);
 InstOff net_inst(const acopf_net_s* net);
 int check_device(const acopf_net_s* net);
+
+// Per-instance dot products over the packed x layout of a batch table:
+// out[k] = a_k . b_k (fixed summation order).
+hipError_t launch_xdot(const InstOff* table, int count, const double* a, const double* b,
+                       double* out, hipStream_t stream);
 
 }  // namespace acopf

@@ -20,7 +20,7 @@ static int same(const char* what, const int32_t* got, const int32_t* want, int n
 int main(void) {
   const int32_t from[2] = {0, 1}, to[2] = {1, 2}, gen_bus[1] = {0};
   const double r[2] = {0.01, 0.02}, x[2] = {0.1, 0.2}, b[2] = {0.0, 0.05};
-  const double tap[2] = {1.0, 1.0}, shift[2] = {0.0, 0.0};
+  const double tap[2] = {1.0, 1.0}, shift[2] = {0.0, 0.0}, rate[2] = {1.5, 0.0};
   const double pd[3] = {0.0, 0.5, 0.3}, qd[3] = {0.0, 0.1, 0.1};
   const double gs[3] = {0.0, 0.0, 0.0}, bs[3] = {0.0, 0.0, 0.0};
   const double c2[1] = {0.02}, c1[1] = {20.0}, c0[1] = {0.0};
@@ -37,6 +37,7 @@ int main(void) {
   d.br_b = b;
   d.br_tap = tap;
   d.br_shift = shift;
+  d.br_rate = rate;
   d.bus_pd = pd;
   d.bus_qd = qd;
   d.bus_gs = gs;
@@ -53,11 +54,23 @@ int main(void) {
     return 2;
   }
   /* x = [th0 th1 th2 v0 v1 v2 Pg0 Qg0]; c = [gP0..2 gQ0..2 hf0 hf1 ht0 ht1] */
-  if (dims.n != 8 || dims.m != 10 || dims.nnz_jac != 46 || dims.nnz_hess != 18) {
-    printf("dims n=%lld m=%lld nnz_jac=%lld nnz_hess=%lld\n", (long long)dims.n,
-           (long long)dims.m, (long long)dims.nnz_jac, (long long)dims.nnz_hess);
+  if (dims.n != 8 || dims.m != 10 || dims.m_eq != 6 || dims.nnz_jac != 46 ||
+      dims.nnz_hess != 18 || dims.nbus != 3 || dims.nbranch != 2 || dims.ngen != 1 ||
+      dims.outage != -1) {
+    printf("dims n=%lld m=%lld m_eq=%lld nnz_jac=%lld nnz_hess=%lld\n", (long long)dims.n,
+           (long long)dims.m, (long long)dims.m_eq, (long long)dims.nnz_jac,
+           (long long)dims.nnz_hess);
     return 3;
   }
+  /* h+ = rate^2 per flow row (from ends, then to ends); rate 0 is unlimited */
+  double hmax[4];
+  if (acopf_flow_limits_host(&d, -1, hmax) != ACOPF_OK) return 10;
+  if (hmax[0] != 2.25 || hmax[2] != 2.25 || !(hmax[1] > 1e308) || !(hmax[3] > 1e308)) {
+    printf("hmax %g %g %g %g\n", hmax[0], hmax[1], hmax[2], hmax[3]);
+    return 11;
+  }
+  if (acopf_flow_limits_host(&d, 1, hmax) != ACOPF_OK || hmax[0] != 2.25 || hmax[1] != 2.25)
+    return 12;
   int32_t jp[11], jc[46], hp[9], hc[18];
   if (acopf_pattern_host(&d, -1, NULL, jp, jc, hp, hc) != ACOPF_OK) return 4;
   const int32_t want_jp[11] = {0, 5, 11, 15, 20, 26, 30, 34, 38, 42, 46};
@@ -72,7 +85,9 @@ int main(void) {
   /* an N-1 child of branch 0: bus 0 loses its neighbour, the flow rows of
      branch 0 go */
   if (acopf_pattern_host(&d, 0, &dims, NULL, NULL, NULL, NULL) != ACOPF_OK) return 6;
-  if (dims.m != 8 || dims.nnz_jac != 46 - 8 - 8 || dims.nnz_hess != 18 - 4) return 7;
+  if (dims.m != 8 || dims.m_eq != 6 || dims.nnz_jac != 46 - 8 - 8 || dims.nnz_hess != 18 - 4 ||
+      dims.nbranch != 1 || dims.outage != 0)
+    return 7;
   /* errors come back as codes with a message, never as exceptions */
   d.base_mva = 0.0;
   if (acopf_pattern_host(&d, -1, &dims, NULL, NULL, NULL, NULL) != ACOPF_EINVAL) return 8;

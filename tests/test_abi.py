@@ -175,3 +175,35 @@ def test_opts_validation():
     b = A.acopf_pattern_host_opts(g, None)
     for x, y in zip(a[1:], b[1:]):
         np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("name,g", [x for x in _grids() if x[1].nbranch > 0])
+def test_flow_limits_are_rate_squared(name, g):
+    """h+ of each flow row: rate^2 of its branch (from ends, then to ends),
+    unlimited for rate <= 0; an outage drops its branch's two rows."""
+    rate = np.asarray(g.br_rate, dtype=np.float64).copy()
+    rate[::5] = 0.0  # some unlimited branches
+    g = S.Grid(**{**g.__dict__, "br_rate": rate})
+    want = np.where(rate > 0, rate * rate, np.inf)
+    np.testing.assert_array_equal(A.acopf_flow_limits_host(g), np.concatenate([want, want]))
+    l = g.nbranch // 2
+    keep = np.arange(g.nbranch) != l
+    np.testing.assert_array_equal(A.acopf_flow_limits_host(g, l),
+                                  np.concatenate([want[keep], want[keep]]))
+
+
+def test_dims_report_equality_rows():
+    g = S.random_grid(30, 50, 11, seed=3, parallel=3)
+    for form in (A.ACOPF_POLAR, A.ACOPF_CARTESIAN):
+        dims, *_ = A.acopf_pattern_host_form(g, form)
+        assert dims.m_eq == 2 * g.nbus
+        assert dims.m == 2 * g.nbus + 2 * g.nbranch + (g.nbus if form == A.ACOPF_CARTESIAN else 0)
+
+
+def test_non_finite_rate_is_rejected():
+    g = S.ring9(0)[0]
+    rate = np.asarray(g.br_rate, dtype=np.float64).copy()
+    rate[3] = np.nan
+    with pytest.raises(A.AcopfError) as ei:
+        A.acopf_pattern_host(S.Grid(**{**g.__dict__, "br_rate": rate}))
+    assert ei.value.code == A.ACOPF_EINVAL and "branch 3" in str(ei.value)
