@@ -5,7 +5,8 @@ sigma: a solver's request) or a seed, from which the device draws the
 iterate and multipliers (the synthetic served workload).  Each is evaluated
 (f, grad f, c, J and H) into a slot of that grid's pool; with keep_results
 the finished request holds device copies of its outputs (a future: poll
-Request.status, read Request.result).  The scheduler
+Request.status; once it reads "done" the copies have completed on the
+device, so Request.result can be read on any stream).  The scheduler
 
   - keeps each grid's network resident on the device and one slot pool per
     grid (the instance slots of one batch handle);
@@ -42,7 +43,7 @@ class Request:
     t_launch: float = float("nan")
     t_done: float = float("nan")
     slot: int = -1
-    status: str = "queued"     # queued | running | done | failed | rejected
+    status: str = "queued"     # queued | running | copying | done | failed | rejected
     error: str = ""
     inputs: Optional[tuple] = None   # (x, lam, sigma) given by the caller, else drawn
     result: Optional[dict] = None    # device outputs once done (keep_results)
@@ -88,7 +89,14 @@ class Executor:
         raise TypeError("this executor evaluates drawn iterates only")
 
     def collect(self, grid: int, slot: int) -> dict:
-        """The outputs of a finished slot, kept apart from the pool."""
+        """The outputs of a finished slot, kept apart from the pool: copies
+        enqueued behind the grid's work, so a later window cannot overwrite
+        the slot first; complete once mark(grid) completes."""
+        raise NotImplementedError
+
+    def mark(self, grid: int):
+        """A handle (polled with done) that completes once everything
+        enqueued so far for `grid`, collect copies included, has finished."""
         raise NotImplementedError
 
 
@@ -142,6 +150,7 @@ class Server:
         self.bytes_in_flight = 0
         self.peak_bytes = 0
         self.requests: List[Request] = []
+        self.copying: collections.deque = collections.deque()  # (requests, handle)
         self.windows_launched = 0
         self._rr = 0
 
@@ -175,18 +184,29 @@ class Server:
     # -- progress -------------------------------------------------------------
     def _retire(self, now: float) -> int:
         n = 0
+        # requests whose result copies have completed on the device
+        while self.copying and self.ex.done(self.copying[0][1]):
+            for r in self.copying.popleft()[0]:
+                r.t_done, r.status = now, "done"
+            n += 1
         for g, q in self.inflight.items():
             keep = collections.deque()
             for w in q:
                 if w.handle is not None and self.ex.done(w.handle):
                     if w.reqs and w.reqs[0].status == "running":
                         for r in w.reqs:
-                            if self.keep_results:
-                                # copied on the grid's stream before the slot
-                                # can be reused by a later window there
-                                r.result = self.ex.collect(g, r.slot)
-                            r.t_done, r.status = now, "done"
                             r.inputs = None  # copied into the slot long ago
+                        if self.keep_results:
+                            # copies enqueued behind the window's work, before
+                            # the slots can take a later window; the requests
+                            # are done once they have completed
+                            for r in w.reqs:
+                                r.result = self.ex.collect(g, r.slot)
+                                r.status = "copying"
+                            self.copying.append((w.reqs, self.ex.mark(g)))
+                        else:
+                            for r in w.reqs:
+                                r.t_done, r.status = now, "done"
                     self.pools[g].free(w.first, len(w.reqs))
                     self.bytes_in_flight -= w.nbytes
                     n += 1
@@ -244,7 +264,8 @@ class Server:
         return self._retire(now) + self._admit(now)
 
     def idle(self) -> bool:
-        return not any(self.queues.values()) and not any(self.inflight.values())
+        return (not any(self.queues.values()) and not any(self.inflight.values())
+                and not self.copying)
 
     # -- open-loop driver -------------------------------------------------------
     def run_trace(self, arrivals: Sequence[tuple], progress: Optional[Callable] = None,
@@ -384,16 +405,34 @@ class GpuExecutor(Executor):
         return handle.query()
 
     def collect(self, grid, slot):
-        """Device copies of one slot's outputs, enqueued on the grid's stream
-        (so later windows there cannot overwrite them first)."""
+        """Device copies of one slot's outputs.  The copies run on the grid's
+        stream (so later windows there cannot overwrite the slot first); the
+        copy tensors belong to the caller's current stream, and the allocator
+        is told that the grid's stream uses them too, so their memory is not
+        handed out again before the copies have run."""
         import torch
         P = self.pool[grid]
         b, B = P["batch"], P["bufs"]
-        sl = lambda t, o: t[int(o[slot]):int(o[slot + 1])].clone()
-        with torch.cuda.stream(P["stream"]):
-            return {"f": B["f"][slot:slot + 1].clone(), "grad_f": sl(B["gf"], b.x_off),
-                    "c": sl(B["c"], b.c_off), "jac_val": sl(B["jac"], b.j_off),
-                    "hess_val": sl(B["hess"], b.h_off)}
+        st = P["stream"]
+        srcs = {"f": B["f"][slot:slot + 1],
+                "grad_f": B["gf"][int(b.x_off[slot]):int(b.x_off[slot + 1])],
+                "c": B["c"][int(b.c_off[slot]):int(b.c_off[slot + 1])],
+                "jac_val": B["jac"][int(b.j_off[slot]):int(b.j_off[slot + 1])],
+                "hess_val": B["hess"][int(b.h_off[slot]):int(b.h_off[slot + 1])]}
+        out = {k: torch.empty_like(v) for k, v in srcs.items()}
+        # the caller's stream may have used this memory before: copy after it
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            for k, v in srcs.items():
+                out[k].copy_(v, non_blocking=True)
+                out[k].record_stream(st)
+        return out
+
+    def mark(self, grid):
+        import torch
+        ev = torch.cuda.Event()
+        ev.record(self.pool[grid]["stream"])
+        return ev
 
     def fetch(self, grid, slot):
         """Host copies of one slot's outputs (tests)."""

@@ -103,14 +103,14 @@ def test_caller_iterates_with_results(gpu_lib):
     assert bad.status == "rejected"
     while not srv.idle():
         srv.step()
-    torch.cuda.synchronize()
-    # more traffic through the same slots; the kept results must not change
+    # "done" means the result copies have completed: read them with no
+    # synchronisation, then push more traffic through the same slots; the
+    # kept results must not change
     kept = {r.rid: {k: v.cpu().numpy().copy() for k, v in r.result.items()} for r, _ in own}
     for k in range(12):
         srv.submit(k % 3, seed=k)
     while not srv.idle():
         srv.step()
-    torch.cuda.synchronize()
     for r, it in own:
         assert r.status == "done", r.error
         log(f"[served own iterate] request {r.rid} grid {r.grid}")

@@ -199,8 +199,14 @@ class InputExecutor(FakeExecutor):
             self.slots[(g, first + i)] = (sum(inp[0]) * inp[2]) if inp else float(s)
         return super().launch(g, first, seeds)
 
+    copy_delay = 0.0
+
     def collect(self, g, slot):
         return {"f": self.slots[(g, slot)]}
+
+    def mark(self, g):
+        # the copies queue behind the grid's work, then take copy_delay
+        return max(self.clock(), self.busy.get(g, 0.0)) + self.copy_delay
 
 
 def test_caller_iterates_and_results():
@@ -246,3 +252,35 @@ def test_pool_finds_any_free_slot():
     assert p.alloc(8) == (4, 1)                            # head was 4; slot 5 taken
     assert p.alloc(8) == (0, 2)
     assert p.alloc(1) is None
+
+
+def test_kept_results_are_done_only_after_their_copies():
+    """With keep_results a finished window's requests wait in 'copying' until
+    the executor's mark for the grid completes (the copies have run); only
+    then are they 'done', and their slots are free for the next window at
+    once (the copies are ordered before it on the grid's stream)."""
+    clock = Clock()
+    ex = InputExecutor(clock, caps=(2, 2))
+    ex.copy_delay = 0.05
+    srv = Server(ex, budget_bytes=10_000, clock=clock, keep_results=True)
+    a = srv.submit(0, seed=3)
+    b = srv.submit(0, seed=4)
+    srv.step()
+    assert a.status == b.status == "running"
+    clock.t = 0.02  # the window has finished on the device
+    srv.step()
+    assert a.status == b.status == "copying" and a.result == {"f": 3.0}
+    assert not srv.idle()
+    c = srv.submit(0, seed=5)
+    srv.step()
+    assert c.status == "running"          # the slots were free again
+    clock.t = 0.06
+    srv.step()
+    assert a.status == "copying"          # copies still running
+    clock.t = 0.08
+    srv.step()
+    assert a.status == b.status == "done"
+    assert a.t_done == b.t_done == 0.08
+    drive(srv, clock)
+    assert c.status == "done" and c.result == {"f": 5.0}
+    assert srv.idle()
