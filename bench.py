@@ -2,11 +2,17 @@
 
 Default workload: the batched N-1 security set -- a 2,000-bus / 3,000-branch
 grid with 1,000 single-branch outages, each with its own iterate and
-multipliers, evaluated in one persistent kernel launch replayed from a HIP
-graph.  One step = one full evaluation of every instance.  Reported beside
-it: the plain path (the same kernels, one instance per launch), per-step
-latency percentiles, the roofline of the batched kernel, and the CPU
-oracle timed on a bounded sample on this host.
+multipliers, evaluated in one kernel launch per step with the autotuned
+schedule (one workgroup per tile, launched directly: the tuner found that
+faster than a persistent grid replayed from a HIP graph, which is timed
+beside it).  One step = one full evaluation of every instance.  Reported
+beside it: the plain path (the same kernels, one instance per launch),
+per-step latency percentiles, the roofline of the batched kernel, the
+batched products, the other formulations, the 512 uneven scenario grids with
+their VJP, 60 s of served Poisson requests, and the CPU oracle timed on a
+bounded sample on this host.  Before each timed region the GPU runs untimed
+steps until it has done WARM_MS of work, whatever --warmup says (short
+warm-ups leave the clocks below their steady state).
 
     python bench.py [--gpus 1] [--steps 50] [--warmup 50]
                     [--workload n1|grid10k|uneven|served] [--model polar|cartesian|slacks]
@@ -28,6 +34,41 @@ HBM_PEAK_GBS = 8000.0
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+WARM_MS = 200.0  # GPU time of untimed work before each timed region
+
+
+def warm_to_steady(call, stream, min_ms=None, chunk=20, max_calls=20000):
+    """Untimed calls until at least min_ms (default WARM_MS) of GPU time has
+    run; returns the calls made and their GPU time."""
+    import torch
+    min_ms = WARM_MS if min_ms is None else min_ms
+    done, gpu_ms = 0, 0.0
+    while gpu_ms < min_ms and done < max_calls:
+        s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s_.record(stream)
+        for _ in range(chunk):
+            call()
+        e_.record(stream)
+        torch.cuda.synchronize()
+        gpu_ms += s_.elapsed_time(e_)
+        done += chunk
+    return {"calls": done, "gpu_ms": gpu_ms}
+
+
+def time_calls(call, stream, n):
+    """Mean ms per call over n calls back to back between two events on the
+    launch stream."""
+    import torch
+    s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s_.record(stream)
+    for _ in range(n):
+        call()
+    e_.record(stream)
+    torch.cuda.synchronize()
+    return s_.elapsed_time(e_) / n
 
 
 # ---------------------------------------------------------------------------
@@ -317,22 +358,99 @@ def products_bench(A, w, model, batch, x, sigma, lam, nbus_total, steps, dev, st
     nbytes = product_bytes(w, model_opts(A, model))
     out = {}
     for name, call in calls.items():
-        for _ in range(max(10, steps // 2)):
-            call()
-        s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        s_.record(stream)
-        for _ in range(steps):
-            call()
-        e_.record(stream)
-        torch.cuda.synchronize()
-        ms = s_.elapsed_time(e_) / steps
+        warm_to_steady(call, stream)
+        ms = time_calls(call, stream, steps)
         gbs = nbytes[name] / (ms / 1e3) / 1e9
         out[name] = {"ms_per_step": ms, "value": nbus_total / (ms / 1e3), "unit": "bus-evals/s",
                      "algorithmic_bytes": nbytes[name], "achieved_GBps": gbs,
                      "frac": gbs / HBM_PEAK_GBS}
         log(f"[bench] {name}: {ms:.4f} ms/step, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.3f} of peak)")
     return out
+
+
+LAT_SAMPLES = 200
+PERSISTENT_SCHED = {"grid_mult": 4, "no_graph": 0}
+
+
+def persistent_graph_bench(A, w, nets, sched, x, sigma, lam, nbus_total, steps, dev, stream):
+    """The step with a persistent grid (4 workgroups per CU) replayed from
+    one HIP graph, the tile class and XCD grouping of the tuned schedule."""
+    import torch
+    K = count(w)
+    ps = dict(sched, **PERSISTENT_SCHED)
+    pb = A.acopf_batch_create(nets, **ps)
+    outs = [torch.empty(n, dtype=torch.float64, device=dev)
+            for n in (K, int(pb.x_off[-1]), int(pb.c_off[-1]), int(pb.j_off[-1]),
+                      int(pb.h_off[-1]))]
+
+    def pstep():
+        A.acopf_batch_eval(pb, x, sigma, lam, *outs, A.ACOPF_ALL, stream)
+
+    warm_to_steady(pstep, stream)
+    ms = time_calls(pstep, stream, steps)
+    alg = algorithmic_bytes(w)
+    res = {"schedule": ps, "ms_per_step": ms, "value": nbus_total / (ms / 1e3),
+           "unit": "bus-evals/s", "frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    log(f"[bench] persistent graph-replayed schedule: {ms:.4f} ms/step, frac {res['frac']:.3f}")
+    del outs
+    pb.close()
+    return res
+
+
+def uneven_bench(A, steps, dev, stream):
+    """The 512 uneven scenario grids (200..25,000 buses, loads scaled per
+    scenario) in their tuned schedule: one full evaluation per step, then
+    the batched VJP with seeded cotangents, each timed like the headline
+    step, with algorithmic bytes, roofline fraction and counter traffic."""
+    import torch
+    from paper_2203_10587_amd import tune
+    t0 = time.time()
+    w = workload_uneven()
+    K = count(w)
+    _, nets = make_nets(A, w, "polar")
+    sched = tune.lookup_or_default(nets)
+    b = A.acopf_batch_create(nets, **sched)
+    x, lam = packed_inputs(w, b, "polar")
+    x, lam = x.to(dev), lam.to(dev)
+    sigma = torch.tensor([it.sigma for it in w["iterates"]], dtype=torch.float64, device=dev)
+    outs = [torch.empty(n, dtype=torch.float64, device=dev)
+            for n in (K, int(b.x_off[-1]), int(b.c_off[-1]), int(b.j_off[-1]), int(b.h_off[-1]))]
+    nbus = sum(int(n.dims.nbus) for n in nets)
+    log(f"[bench] uneven: {K} grids, {nbus} buses, prepared in {time.time() - t0:.1f}s")
+
+    def ustep():
+        A.acopf_batch_eval(b, x, sigma, lam, *outs, A.ACOPF_ALL, stream)
+
+    warm_to_steady(ustep, stream)
+    ms = time_calls(ustep, stream, steps)
+    alg = algorithmic_bytes(w)
+    res = {"workload": w["name"], "instances": K, "buses_per_step": nbus, "schedule": sched,
+           "ms_per_step": ms, "value": nbus / (ms / 1e3), "unit": "bus-evals/s",
+           "algorithmic_bytes": alg, "achieved_GBps": alg / (ms / 1e3) / 1e9,
+           "frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+           "traffic": load_traffic("k_eval_all", traffic_key(w, "polar"))}
+    log(f"[bench] uneven: {ms:.4f} ms/step, {res['value']:.4e} bus-evals/s, frac {res['frac']:.3f}")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(20220322)
+    wc = torch.randn(int(b.c_off[-1]), dtype=torch.float64, device=dev, generator=gen)
+    wf = torch.randn(K, dtype=torch.float64, device=dev, generator=gen)
+    u = torch.empty(int(b.x_off[-1]), dtype=torch.float64, device=dev)
+
+    def vjp():
+        A.acopf_batch_vjp(b, x, wf, wc, u, stream)
+
+    warm_to_steady(vjp, stream)
+    vms = time_calls(vjp, stream, steps)
+    vbytes = product_bytes(w)["vjp"]
+    res["vjp"] = {"ms_per_step": vms, "algorithmic_bytes": vbytes,
+                  "achieved_GBps": vbytes / (vms / 1e3) / 1e9,
+                  "frac": vbytes / (vms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    log(f"[bench] uneven vjp: {vms:.4f} ms/step, frac {res['vjp']['frac']:.3f}")
+    del outs, x, lam, u, wc
+    b.close()
+    for n in nets:
+        n.close()
+    return res
 
 
 def make_nets(A, w, model):
@@ -374,14 +492,8 @@ def variant_bench(A, w, model, sched, sigma, nbus_total, args, dev, stream):
 
     for _ in range(args.warmup):
         vstep()
-    s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    s_.record(stream)
-    for _ in range(args.steps):
-        vstep()
-    e_.record(stream)
-    torch.cuda.synchronize()
-    ms = s_.elapsed_time(e_) / args.steps
+    warm_to_steady(vstep, stream)
+    ms = time_calls(vstep, stream, args.steps)
     alg = algorithmic_bytes(w, model_opts(A, model))
     label = LABELS[model]
     res = {"formulation": label, "ms_per_step": ms, "value": nbus_total / (ms / 1e3),
@@ -399,6 +511,7 @@ def variant_bench(A, w, model, sched, sigma, nbus_total, args, dev, stream):
 
 
 def main():
+    global WARM_MS
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
@@ -408,8 +521,8 @@ def main():
                     help="n1: 1,000 N-1 outages of a 2,000-bus grid (default); grid10k: one "
                          "10,000-bus grid; uneven: 512 scenario grids of 200..25,000 buses; "
                          "served: Poisson requests over four resident grids")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
-                    help="length of the served Poisson trace (the full served workload is 60 s)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the served Poisson trace (the served workload is 60 s)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
@@ -417,8 +530,15 @@ def main():
                     help="formulation of the timed step: polar (default), cartesian, or polar "
                          "with load-loss and power-imbalance slacks")
     ap.add_argument("--no-variants", dest="variants", action="store_false",
-                    help="skip timing the workload in the other formulations and the "
-                         "batched products (VJP, HVP, JVP)")
+                    help="skip timing the workload in the other formulations, the "
+                         "batched products (VJP, HVP, JVP), the persistent graph-replayed "
+                         "schedule and the uneven scenario grids")
+    ap.add_argument("--warm-ms", type=float, default=WARM_MS,
+                    help="GPU time of untimed work before each timed region (0 for profiled "
+                         "runs, where every dispatch is recorded)")
+    ap.add_argument("--no-uneven", dest="uneven", action="store_false",
+                    help="skip the uneven scenario grids (512 grids of 200..25,000 buses "
+                         "with their VJP) in the default line")
     ap.add_argument("--tile-be", type=int, default=0)
     ap.add_argument("--grid-mult", type=int, default=-1)
     ap.add_argument("--xcd", type=int, default=-1)
@@ -430,6 +550,7 @@ def main():
                     help="only run a device-to-device copy of MIB MiB five times (the "
                          "reference kernel for scaling HBM traffic counters)")
     args = ap.parse_args()
+    WARM_MS = args.warm_ms
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 8
@@ -526,6 +647,10 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # then untimed steps until the GPU has run WARM_MS of work, so that the
+    # timed region starts at steady clocks however small --warmup is
+    warm_extra = warm_to_steady(step, stream)
+    log(f"[bench] extra warm-up: {warm_extra['calls']} steps, {warm_extra['gpu_ms']:.0f} ms of GPU time")
     # the timed region: K steps back to back between two events on the
     # launch stream (throughput and the roofline's per-launch time)
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -538,11 +663,13 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = start.elapsed_time(end)
-    # per-step latency (p50/p99) from K more steps, each between its own
-    # events (which serialise the stream, so they stay out of the timed region)
+    # per-step latency (p50/p99) from at least LAT_SAMPLES more steps, each
+    # between its own events (which serialise the stream, so they stay out of
+    # the timed region)
+    n_lat = max(args.steps, LAT_SAMPLES)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    for k in range(args.steps):
+          for _ in range(n_lat)]
+    for k in range(n_lat):
         ev[k][0].record(stream)
         step()
         ev[k][1].record(stream)
@@ -587,6 +714,13 @@ def main():
     if args.variants:
         products = products_bench(A, w, args.model, batch, x, sigma, lam, nbus_total, args.steps,
                                   dev, stream)
+
+    # the same step with a persistent grid replayed from a HIP graph: the
+    # tuner's best such schedule, beside the tuned (direct) one
+    persistent = None
+    if args.variants and not sched.get("grid_mult", 0):
+        persistent = persistent_graph_bench(A, w, nets, sched, x, sigma, lam, nbus_total,
+                                            args.steps, dev, stream)
 
     variants = {}
     if args.variants:
@@ -639,6 +773,10 @@ def main():
         log(f"[bench] served: {serving['done']} requests, p50 {serving['p50_ms']:.3f} ms, "
             f"p99 {serving['p99_ms']:.3f} ms")
 
+    uneven = None
+    if args.variants and args.uneven and args.workload == "n1" and args.model == "polar":
+        uneven = uneven_bench(A, args.steps, dev, stream)
+
     alg = algorithmic_bytes(w, model_opts(A, args.model))
     avg_ms = total_ms / args.steps  # per launch of the step, over the timed region
     achieved = alg / (avg_ms / 1e3) / 1e9
@@ -651,8 +789,12 @@ def main():
         "config": {"workload": w["name"], "formulation": LABELS[args.model], "instances": K,
                    "buses_per_step": nbus_total,
                    "outputs": "f, grad_f, c, J, H", "schedule": sched},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "samples": int(len(lat))},
+        "warmup_extra": warm_extra,
         "plain": plain,
+        "persistent_graph": persistent,
+        "uneven": uneven,
         "coupled": coupled,
         "products": products,
         "variants": variants or None,
