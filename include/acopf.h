@@ -361,6 +361,24 @@ int acopf_batch_eval_range(acopf_batch batch, int32_t first, int32_t count, cons
                            double* grad_f, double* c, double* jac_val, double* hess_val,
                            unsigned what, hipStream_t stream);
 
+/* acopf_batch_eval for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, outputs and errors as acopf_batch_eval, and
+ * bitwise the same results; the call itself allocates nothing (no hipMalloc,
+ * hipFree or graph instantiation: the batch is always launched directly).
+ * The objective partials of instances with several cost-item chunks (one
+ * chunk per 1,024 generators or 2,048 slack variables, at least one per
+ * instance) go to a fixed device array of 32,768 doubles (256 KiB) that the
+ * library holds on each device it runs on until the process ends; a batch
+ * whose chunks exceed that count is refused with EINVAL before anything is
+ * launched.  Every call on one device shares that array and nothing in it
+ * needs to start at zero, but calls that overlap in time on one device
+ * (other streams, other threads) race on it: serialise them. */
+int acopf_batch_eval_noalloc(acopf_batch batch, const double* x, const double* sigma,
+                             const double* lambda, double* f, double* grad_f, double* c,
+                             double* jac_val, double* hess_val, unsigned what,
+                             hipStream_t stream);
+
 /* Random iterates for the instances [first, first + count), drawn on the
  * device for a served request stream (the request carries only a seed).
  * Counter-based: stream element j of instance k is

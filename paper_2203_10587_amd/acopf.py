@@ -110,6 +110,8 @@ _SIGS = {
     "acopf_batch_destroy": (C.c_int, [C.c_void_p]),
     "acopf_batch_offsets": (C.c_int, [C.c_void_p, _i64p, _i64p, _i64p, _i64p]),
     "acopf_batch_eval": (C.c_int, [C.c_void_p] + [C.c_void_p] * 8 + [C.c_uint, C.c_void_p]),
+    "acopf_batch_eval_noalloc": (C.c_int, [C.c_void_p] + [C.c_void_p] * 8
+                                 + [C.c_uint, C.c_void_p]),
     "acopf_batch_vjp": (C.c_int, [C.c_void_p] + [C.c_void_p] * 4 + [C.c_void_p]),
     "acopf_batch_xdot": (C.c_int, [C.c_void_p] * 5),
     "acopf_batch_eval_range": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 8
@@ -441,6 +443,17 @@ def acopf_batch_eval(b: Batch, x, sigma, lam, f, grad_f, c, jac_val, hess_val,
                      what: int = ACOPF_ALL, stream=None):
     k = b.count
     _check(lib().acopf_batch_eval(
+        b.handle, _ptr(x, int(b.x_off[-1]), "x"), _ptr(sigma, k, "sigma"),
+        _ptr(lam, int(b.c_off[-1]), "lambda"), _ptr(f, k, "f"),
+        _ptr(grad_f, int(b.x_off[-1]), "grad_f"), _ptr(c, int(b.c_off[-1]), "c"),
+        _ptr(jac_val, int(b.j_off[-1]), "jac_val"), _ptr(hess_val, int(b.h_off[-1]), "hess_val"),
+        C.c_uint(what), _stream(stream)))
+
+
+def acopf_batch_eval_noalloc(b: Batch, x, sigma, lam, f, grad_f, c, jac_val, hess_val,
+                             what: int = ACOPF_ALL, stream=None):
+    k = b.count
+    _check(lib().acopf_batch_eval_noalloc(
         b.handle, _ptr(x, int(b.x_off[-1]), "x"), _ptr(sigma, k, "sigma"),
         _ptr(lam, int(b.c_off[-1]), "lambda"), _ptr(f, k, "f"),
         _ptr(grad_f, int(b.x_off[-1]), "grad_f"), _ptr(c, int(b.c_off[-1]), "c"),

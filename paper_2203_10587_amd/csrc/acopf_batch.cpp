@@ -14,6 +14,7 @@
 #include <cstring>
 #include <list>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -51,6 +52,7 @@ struct acopf_batch_s {
   std::vector<int32_t> inst_tile_off;   // count + 1
   int max_len = 0;                      // max n + m over instances
   int max_chunks = 1;                   // f partials per instance, at most
+  int64_t nparts = 0;                   // f partials of the whole batch
   hipStream_t cap_stream = nullptr;
   std::list<std::pair<acopf::GraphKey, hipGraphExec_t>> graphs;  // most recent first
   std::atomic<int> refs{0};             // couplings built on this batch
@@ -71,6 +73,39 @@ struct acopf_couple_s {
 };
 
 using namespace acopf;
+
+// Scratch of acopf_batch_eval_noalloc: the objective partials of the
+// instances with several cost-item chunks live in this file-scope device
+// array instead of the batch's own allocation.  Each device holds its own
+// copy.  In host code the name is only a host-side stand-in, so its device
+// address is taken once per device with hipGetSymbolAddress (from
+// acopf_batch_create, which runs with the device current) and only that
+// address is handed to kernels.
+static constexpr int64_t kScratchParts = int64_t(1) << 15;  // 32,768 doubles, 256 KiB
+static __device__ __align__(256) double scratch[kScratchParts];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev`, which must be current.
+static int scratch_address(int dev, double** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(ACOPF_EINVAL, "device index " + std::to_string(dev) + " beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return hip_fail(e, "hipGetSymbolAddress of the scratch array");
+    }
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return ACOPF_OK;
+}
 
 namespace {
 
@@ -217,6 +252,7 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
       fpo[k + 1] = fpo[k] + nets[k]->base->topo.nchunks;
       b->max_chunks = std::max(b->max_chunks, nets[k]->base->topo.nchunks);
     }
+    b->nparts = fpo[count];
     // per-base schedule (outage children share their base's)
     struct PerBase {
       Schedule sch;
@@ -337,6 +373,10 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
       free_batch(b);
       return hip_fail(e, "batch table upload");
     }
+    // set-up of the allocation-free entry point on this device; a failure
+    // here is reported by that entry point, not by the batch
+    double* sp = nullptr;
+    if (scratch_address(dev, &sp) != ACOPF_OK) t_err.clear();
     *out = b;
     t_err.clear();
     return ACOPF_OK;
@@ -386,6 +426,45 @@ int acopf_batch_eval(acopf_batch b, const double* x, const double* sigma, const 
   bufs.hess = (what & ACOPF_H) ? hess_val : nullptr;
   bufs.fpart = b->d_fpart;
   return run_batch(b, variant_of(what), bufs, stream);
+}
+
+int acopf_batch_eval_noalloc(acopf_batch b, const double* x, const double* sigma,
+                             const double* lambda, double* f, double* grad_f, double* c,
+                             double* jac_val, double* hess_val, unsigned what,
+                             hipStream_t stream) {
+  if (!b || !x) return fail(ACOPF_EINVAL, "null batch or x");
+  if (what & ~unsigned(ACOPF_ALL)) return fail(ACOPF_EINVAL, "unknown bits in what");
+  if (((what & ACOPF_F) && !f) || ((what & ACOPF_GRADF) && !grad_f) || ((what & ACOPF_C) && !c) ||
+      ((what & ACOPF_J) && !jac_val) ||
+      ((what & ACOPF_H) && (!hess_val || !lambda || !sigma)))
+    return fail(ACOPF_EINVAL, "a selected output (or lambda/sigma for ACOPF_H) is null");
+  if (b->nparts > kScratchParts)
+    return fail(ACOPF_EINVAL, "the batch needs " + std::to_string(b->nparts) +
+                                  " objective partials; the allocation-free evaluation holds at most " +
+                                  std::to_string(kScratchParts));
+  if (!what) return ACOPF_OK;
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != b->device) return fail(ACOPF_EINVAL, "batch lives on another device");
+  double* sp = nullptr;
+  int rc = scratch_address(cur, &sp);
+  if (rc) return rc;
+  Bufs bufs{};
+  bufs.x = x;
+  bufs.lam = (what & ACOPF_H) ? lambda : nullptr;
+  bufs.sigma = (what & ACOPF_H) ? sigma : nullptr;
+  bufs.f = (what & ACOPF_F) ? f : nullptr;
+  bufs.gradf = (what & ACOPF_GRADF) ? grad_f : nullptr;
+  bufs.c = (what & ACOPF_C) ? c : nullptr;
+  bufs.jac = (what & ACOPF_J) ? jac_val : nullptr;
+  bufs.hess = (what & ACOPF_H) ? hess_val : nullptr;
+  bufs.fpart = sp;
+  // always a direct launch: capturing and instantiating a graph allocates
+  const unsigned variant = variant_of(what) | (b->form == ACOPF_CARTESIAN ? W_CART : 0u);
+  e = enqueue(b, variant, bufs, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+  return ACOPF_OK;
 }
 
 int acopf_batch_hvp(acopf_batch b, const double* x, const double* sigma, const double* lambda,
