@@ -292,8 +292,11 @@ int acopf_eval_all(acopf_net net, const double* x, double sigma, const double* l
  * in packed DEVICE buffers at the offsets returned by acopf_batch_offsets:
  * x at x_off[k] (length n_k), lambda and c at c_off[k] (m_k), jac_val at
  * j_off[k] (nnz_jac_k), hess_val at h_off[k] (nnz_hess_k), grad_f and u at
- * x_off[k]; sigma, f and w_f are arrays of `count`.  The whole batch runs as
- * one persistent kernel launch replayed from a HIP graph.
+ * x_off[k]; sigma, f and w_f are arrays of `count`.  The whole batch runs in
+ * one kernel launch (plus a small reduction launch when some instance has
+ * several objective chunks), issued as the schedule says: one workgroup per
+ * tile or a persistent grid striding over the tile list, launched directly
+ * or replayed from a HIP graph captured per buffer set.
  * ---------------------------------------------------------------------- */
 
 /* Tile/schedule configuration chosen by the autotuner (or fixed by hand). */
