@@ -2,6 +2,8 @@
 
     python -m paper_2203_10587_amd.profiling stats DIR OUT.md --cmd "..."
         kernel-trace --stats run: per-kernel calls and durations.
+    python -m paper_2203_10587_amd.profiling counters DIR [DIR ...] --out OUT.md --cmd "..."
+        occupancy, stall and L2 counters per kernel (one DIR per counter set).
     python -m paper_2203_10587_amd.profiling traffic --workload NAME \
         --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR --copy-mib MIB \
         --json profiles/traffic.json --md OUT.md --cmd "..."
@@ -182,6 +184,88 @@ def cmd_traffic(args):
     print("\n".join(lines))
 
 
+XCDS = 8  # GRBM_GUI_ACTIVE comes summed over the accelerator complex dies
+
+
+def _counter_table(dirs):
+    """{(kernel, grid): {counter: mean per dispatch}} over the given pmc runs;
+    per kernel only the grid size seen most often (the batched launch), the
+    first of its dispatches dropped when there are more."""
+    acc = defaultdict(lambda: defaultdict(float))
+    meta = {}
+    for d in dirs:
+        for r in _csv(d, "counter_collection.csv"):
+            key = (d, int(r["Dispatch_Id"]))
+            acc[key][r["Counter_Name"]] += float(r["Counter_Value"])
+            meta[key] = (r["Kernel_Name"], int(r["Grid_Size"]), int(r["VGPR_Count"]),
+                         int(r["LDS_Block_Size"]),
+                         int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    by = defaultdict(list)
+    for key, cnt in acc.items():
+        by[(key[0], meta[key][0], meta[key][1])].append((key[1], cnt, meta[key]))
+    best = {}
+    for (d, name, grid), lst in by.items():
+        k = (name, grid)
+        cur = best.setdefault(k, {"n": 0, "vals": defaultdict(list), "meta": lst[0][2]})
+        lst.sort()
+        if len(lst) > 1:
+            lst = lst[1:]
+        for _, cnt, m in lst:
+            for c, v in cnt.items():
+                cur["vals"][c].append(v)
+        cur["n"] = max(cur["n"], len(lst))
+        cur.setdefault("dur", []).extend(m[4] for _, _, m in lst)
+    # keep the modal grid of each kernel
+    out = {}
+    for (name, grid), ent in best.items():
+        prev = out.get(name)
+        if prev is None or ent["n"] > prev[1]["n"]:
+            out[name] = (grid, ent)
+    return out
+
+
+def cmd_counters(args):
+    tab = _counter_table(args.dirs)
+    lines = [f"# {args.title}", "", "Commands (one rocprofv3 run per counter set):", "", "```",
+             args.cmd, "```", "",
+             "Per dispatch of each kernel's batched launch (mean over its warm dispatches). "
+             "Derived: waves/CU = 4 SQ_WAVE_CYCLES / (active cycles x CUs) with "
+             f"active cycles = GRBM_GUI_ACTIVE / {XCDS} (the counter is summed over the dies) "
+             "and SQ_WAVE_CYCLES in quad-cycles; wait, issue-wait and active are SQ_WAIT_ANY, "
+             "SQ_WAIT_INST_ANY and SQ_ACTIVE_INST_ANY as fractions of SQ_WAVE_CYCLES; L2 hit = "
+             "TCC_HIT / TCC_REQ; HBM reads = TCC_EA0_RDREQ; L1->L2 = TCP_TCC_READ_REQ and "
+             "TCP_TCC_WRITE_REQ; per instance = divided by --instances.", "",
+             "| kernel | grid | VGPR | LDS B | us | waves/CU | wait | issue-wait | active | "
+             "L2 req | L2 hit | HBM rd req | L1->L2 rd | L1->L2 wr | rd req/inst |",
+             "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    m = lambda ent, c: (sum(ent["vals"][c]) / len(ent["vals"][c])) if ent["vals"].get(c) else None
+    f = lambda v, fmt: "-" if v is None else format(v, fmt)
+    for name, (grid, ent) in sorted(tab.items()):
+        if args.kernel and args.kernel not in name:
+            continue
+        g = m(ent, "GRBM_GUI_ACTIVE")
+        cyc = g / XCDS if g else None
+        wc = m(ent, "SQ_WAVE_CYCLES")
+        wpc = 4 * wc / (cyc * args.cus) if (wc and cyc) else None
+        frac = lambda c: (m(ent, c) / wc) if (wc and m(ent, c) is not None) else None
+        req, hit = m(ent, "TCC_REQ_sum"), m(ent, "TCC_HIT_sum")
+        rd = m(ent, "TCP_TCC_READ_REQ_sum")
+        dur = sorted(ent["dur"])[len(ent["dur"]) // 2] / 1e3 if ent.get("dur") else None
+        meta = ent["meta"]
+        lines.append(
+            f"| `{_short(name)}` | {grid} | {2 * meta[2]} | {meta[3]} | {f(dur, '.1f')} | "
+            f"{f(wpc, '.1f')} | {f(frac('SQ_WAIT_ANY'), '.2f')} | {f(frac('SQ_WAIT_INST_ANY'), '.2f')} | "
+            f"{f(frac('SQ_ACTIVE_INST_ANY'), '.2f')} | {f(req, '.3g')} | "
+            f"{f(None if not req else hit / req, '.2f')} | {f(m(ent, 'TCC_EA0_RDREQ_sum'), '.3g')} | "
+            f"{f(rd, '.3g')} | {f(m(ent, 'TCP_TCC_WRITE_REQ_sum'), '.3g')} | "
+            f"{f(None if rd is None else rd / args.instances, '.0f')} |")
+    lines += ["", "VGPR is the allocation the trace reports (twice its VGPR_Count field, the "
+              "granule this device counts in); durations are medians under counter collection."]
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -201,8 +285,16 @@ def main():
     t.add_argument("--json", required=True)
     t.add_argument("--md", required=True)
     t.add_argument("--cmd", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--out", required=True)
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--title", default="rocprofv3 counters")
+    c.add_argument("--kernel", default="k_eval")
+    c.add_argument("--instances", type=int, default=1)
+    c.add_argument("--cus", type=int, default=256)
     args = ap.parse_args()
-    {"stats": cmd_stats, "traffic": cmd_traffic}[args.what](args)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[args.what](args)
 
 
 if __name__ == "__main__":
