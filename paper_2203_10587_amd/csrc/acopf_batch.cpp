@@ -48,6 +48,8 @@ struct acopf_batch_s {
   int ntiles = 0;
   int grid = 0;  // 0: one workgroup per tile
   acopf::Tile* d_tiles_inst = nullptr;  // the same tiles, instance after instance
+  acopf::Tile* d_ptiles = nullptr;      // product tiles: instances of one base in pairs
+  int nptiles = 0;
   acopf::WorkItem* d_work = nullptr;    // work items of every distinct base, back to back
   std::vector<int32_t> inst_tile_off;   // count + 1
   int max_len = 0;                      // max n + m over instances
@@ -139,12 +141,19 @@ unsigned variant_of(unsigned what) {
   return K_ALL;
 }
 
-// The evaluation kernel, then (if f is wanted) the f reduction.
+bool is_product(unsigned variant) { return (variant & (W_VJP | W_HVP | W_JVP)) != 0; }
+
+// The evaluation kernel, then (if f is wanted) the f reduction.  The
+// products walk their own tile list, whose bus tiles serve two instances of
+// one base network at a time.
 hipError_t enqueue(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStream_t s) {
   InstOff none{};
   none.work = b->d_work;  // the tiles' w0 index this array
-  hipError_t e = launch_eval(variant, b->sched.tile_be, bufs, b->d_table, none, b->d_tiles,
-                             b->ntiles, b->grid, s);
+  const bool prod = is_product(variant);
+  const Tile* tiles = prod ? b->d_ptiles : b->d_tiles;
+  const int nt = prod ? b->nptiles : b->ntiles;
+  const int grid = b->grid > 0 ? std::min(b->grid, nt) : 0;
+  hipError_t e = launch_eval(variant, b->sched.tile_be, bufs, b->d_table, none, tiles, nt, grid, s);
   // a single-chunk instance has its f written by its generator tile
   if (e == hipSuccess && bufs.f && b->max_chunks > 1)
     e = launch_fsum(b->d_table, none, 0, b->count, bufs.fpart, bufs.f, s);
@@ -201,6 +210,10 @@ int run_batch(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStream_t 
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return ACOPF_OK;
 }
+
+int enqueue_range(acopf_batch_s* b, int32_t first, int32_t count, const double* x,
+                  const double* sigma, const double* lambda, double* f, double* grad_f, double* c,
+                  double* jac_val, double* hess_val, unsigned what, hipStream_t stream);
 
 }  // namespace
 
@@ -307,16 +320,68 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
       const acopf_dims& d = nets[k]->dims;
       b->max_len = std::max<int>(b->max_len, int(d.n + d.m));
     }
-    std::vector<Tile> tiles;
-    size_t total = 0;
-    for (auto& q : queue) total += q.size();
-    tiles.reserve(total);
-    std::vector<size_t> pos(queue.size(), 0);
-    while (tiles.size() < total) {
-      for (size_t qi = 0; qi < queue.size(); ++qi)
-        if (pos[qi] < queue[qi].size()) tiles.push_back(queue[qi][pos[qi]++]);
-    }
+    // interleave XCD queues: list position p runs on XCD p mod 8
+    auto interleave = [](const std::vector<std::vector<Tile>>& qs) {
+      std::vector<Tile> out;
+      size_t total = 0;
+      for (auto& q : qs) total += q.size();
+      out.reserve(total);
+      std::vector<size_t> pos(qs.size(), 0);
+      while (out.size() < total) {
+        for (size_t qi = 0; qi < qs.size(); ++qi)
+          if (pos[qi] < qs[qi].size()) out.push_back(qs[qi][pos[qi]++]);
+      }
+      return out;
+    };
+    std::vector<Tile> tiles = interleave(queue);
     b->ntiles = int(tiles.size());
+    // product tiles: the instances of each base network in pairs (instance
+    // order), a pair's bus tiles once with both instances, each instance's
+    // generator tiles on their own; pairs spread over the XCD queues
+    // largest-first like the instances above
+    std::vector<Tile> ptiles;
+    {
+      std::map<const Base*, std::vector<int>> by_base;
+      std::vector<const Base*> base_order;
+      for (int k = 0; k < count; ++k) {
+        const Base* B = nets[k]->base.get();
+        if (!by_base.count(B)) base_order.push_back(B);
+        by_base[B].push_back(k);
+      }
+      std::vector<std::pair<int, int>> units;
+      for (const Base* B : base_order) {
+        const std::vector<int>& ks = by_base[B];
+        for (size_t j = 0; j < ks.size(); j += 2)
+          units.emplace_back(ks[j], j + 1 < ks.size() ? ks[j + 1] : -1);
+      }
+      std::stable_sort(units.begin(), units.end(), [&](const std::pair<int, int>& a,
+                                                       const std::pair<int, int>& c) {
+        return ntile(a.first) > ntile(c.first);
+      });
+      std::vector<std::vector<Tile>> pq(s.xcd_group ? kXcds : 1);
+      std::vector<int64_t> pload(pq.size(), 0);
+      for (const auto& u : units) {
+        const size_t qi = std::min_element(pload.begin(), pload.end()) - pload.begin();
+        const PerBase& pb = per_base[nets[u.first]->base.get()];
+        for (Tile t : pb.sch.tiles) {
+          t.inst = u.first;
+          t.w0 += int32_t(pb.work_off);
+          if ((t.kind_aux & 3) == TILE_BUS) {
+            t.inst2 = u.second;
+            pq[qi].push_back(t);
+          } else {
+            pq[qi].push_back(t);
+            if (u.second >= 0) {
+              t.inst = u.second;
+              pq[qi].push_back(t);
+            }
+          }
+        }
+        pload[qi] += ntile(u.first);
+      }
+      ptiles = interleave(pq);
+    }
+    b->nptiles = int(ptiles.size());
     int cus = 256;
     int rc = cu_count(dev, &cus);
     if (rc) {
@@ -330,7 +395,8 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     const size_t s_tinst = align_up(tiles_inst.size() * sizeof(Tile));
     const size_t s_work = align_up(std::max<size_t>(work_total, 1) * sizeof(WorkItem));
     const size_t s_fpart = align_up(size_t(fpo[count]) * sizeof(double));
-    e = hipMalloc(&b->mem, s_table + s_tiles + s_work + s_fpart + s_tinst);
+    const size_t s_ptiles = align_up(ptiles.size() * sizeof(Tile));
+    e = hipMalloc(&b->mem, s_table + s_tiles + s_work + s_fpart + s_tinst + s_ptiles);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       b->mem = nullptr;
@@ -344,6 +410,7 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     b->d_work = d_work;
     b->d_fpart = reinterpret_cast<double*>(base + s_table + s_tiles + s_work);
     b->d_tiles_inst = reinterpret_cast<Tile*>(base + s_table + s_tiles + s_work + s_fpart);
+    b->d_ptiles = reinterpret_cast<Tile*>(base + s_table + s_tiles + s_work + s_fpart + s_tinst);
     std::vector<InstOff> table(count);
     for (int k = 0; k < count; ++k) {
       InstOff I = net_inst(nets[k]);
@@ -367,6 +434,9 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     }
     if (e == hipSuccess)
       e = hipMemcpy(b->d_tiles_inst, tiles_inst.data(), tiles_inst.size() * sizeof(Tile),
+                    hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_ptiles, ptiles.data(), ptiles.size() * sizeof(Tile),
                     hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(b->d_fpart, 0, s_fpart);
     if (e != hipSuccess) {
@@ -508,6 +578,41 @@ int acopf_batch_eval_range(acopf_batch b, int32_t first, int32_t count, const do
   hipError_t e = hipGetDevice(&cur);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   if (cur != b->device) return fail(ACOPF_EINVAL, "batch lives on another device");
+  return enqueue_range(b, first, count, x, sigma, lambda, f, grad_f, c, jac_val, hess_val, what,
+                       stream);
+}
+
+int acopf_batch_serve_window(acopf_batch b, int32_t first, int32_t count, const uint64_t* seeds,
+                             double pmin, double pmax, double qmin, double qmax, double* x,
+                             double* lambda, double* sigma, double* f, double* grad_f, double* c,
+                             double* jac_val, double* hess_val, hipStream_t stream) {
+  if (!b || !seeds || !x || !lambda || !sigma || !f || !grad_f || !c || !jac_val || !hess_val)
+    return fail(ACOPF_EINVAL, "null argument");
+  if (first < 0 || count < 1 || first > b->count - count)
+    return fail(ACOPF_EINVAL, "instance window out of range");
+  if (count > kWindowSeeds)
+    return fail(ACOPF_EINVAL, "at most " + std::to_string(kWindowSeeds) + " instances per window");
+  if (b->form != ACOPF_POLAR) return fail(ACOPF_EINVAL, "iterates are drawn for the polar representation only");
+  for (int32_t k = first; k < first + count; ++k)
+    if (b->nets[k]->base->topo.sl.ns) return fail(ACOPF_EINVAL, "iterates are not drawn for nets with slack variables");
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != b->device) return fail(ACOPF_EINVAL, "batch lives on another device");
+  e = launch_draw_window(b->d_table, first, count, b->max_len, seeds, pmin, pmax, qmin, qmax, x,
+                         lambda, sigma, stream);
+  if (e != hipSuccess) return hip_fail(e, "draw kernel launch");
+  return enqueue_range(b, first, count, x, sigma, lambda, f, grad_f, c, jac_val, hess_val,
+                       ACOPF_ALL, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+int enqueue_range(acopf_batch_s* b, int32_t first, int32_t count, const double* x,
+                  const double* sigma, const double* lambda, double* f, double* grad_f, double* c,
+                  double* jac_val, double* hess_val, unsigned what, hipStream_t stream) {
   Bufs bufs{};
   bufs.x = x;
   bufs.lam = (what & ACOPF_H) ? lambda : nullptr;
@@ -518,6 +623,7 @@ int acopf_batch_eval_range(acopf_batch b, int32_t first, int32_t count, const do
   bufs.jac = (what & ACOPF_J) ? jac_val : nullptr;
   bufs.hess = (what & ACOPF_H) ? hess_val : nullptr;
   bufs.fpart = b->d_fpart;
+  hipError_t e;
   const int t0 = b->inst_tile_off[first], t1 = b->inst_tile_off[first + count];
   InstOff none{};
   none.work = b->d_work;  // the tiles' w0 index this array
@@ -529,6 +635,10 @@ int acopf_batch_eval_range(acopf_batch b, int32_t first, int32_t count, const do
   if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
   return ACOPF_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int acopf_batch_draw_iterates(acopf_batch b, int32_t first, int32_t count, const uint64_t* seeds,
                               double pmin, double pmax, double qmin, double qmax, double* x,

@@ -638,6 +638,9 @@ int upload_base(Base* B) {
   nd.jflow = T.jflow;
   nd.hpg = T.hpg;
   nd.qoff = T.rows[0].y - T.rows[0].x;
+  nd.gen_ident = 1;
+  for (int g = 0; g < T.ng; ++g)
+    if (T.gen_list[g] != g) nd.gen_ident = 0;
   nd.sl = T.sl;
   B->d_tiles = static_cast<Tile*>(at(9));
   B->d_work = static_cast<WorkItem*>(at(10));

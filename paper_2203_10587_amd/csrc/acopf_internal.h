@@ -43,9 +43,12 @@ enum TileKind : int32_t { TILE_BUS = 1, TILE_GEN = 2 };
 // H v rows [hV0, hV0 + nV).  Gen tile: cost items [a0, a1) (item k >= ng is
 // slack variable k - ng);
 // kind_aux = (chunk << 2) | kind.
+// A product bus tile may serve a second instance of the same base network
+// (inst2; -1 for none).
 struct Tile {
   int32_t inst, kind_aux, a0, a1, e0, ne, w0, nw;
   int32_t gmax, nP, nT, nV, jP0, jQ0, hT0, hV0;
+  int32_t inst2 = -1;
 };
 
 // One branch evaluated by a bus tile.  l < 0 pads the list so that no
@@ -103,6 +106,7 @@ struct NetDev {
   int32_t jflow;            // base start of the flow rows in J
   int32_t hpg;              // base start of the Pg rows in H
   int32_t qoff;             // J Q row of a bus minus its P row
+  int32_t gen_ident;        // 1 if gen_list is the identity (generators numbered by bus)
   SlackDev sl;              // slack blocks (sl.ns = 0: none)
 };
 

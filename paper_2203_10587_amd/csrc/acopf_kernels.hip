@@ -58,6 +58,28 @@ namespace {
 // the network data stay resident in L2.
 __device__ __forceinline__ void put(double* p, double v) { __builtin_nontemporal_store(v, p); }
 
+// A flow-limit Jacobian row (four consecutive entries): two 16-byte stores
+// when the row is 16-byte aligned (so the L2 sees two pieces of each 32-byte
+// row instead of four), else four 8-byte ones.
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void put_row4(double* p, bool al16, double a, double b, double c,
+                                         double d) {
+  if (al16) {
+    dbl2 lo, hi;
+    lo.x = a;
+    lo.y = b;
+    hi.x = c;
+    hi.y = d;
+    __builtin_nontemporal_store(lo, reinterpret_cast<dbl2*>(p));
+    __builtin_nontemporal_store(hi, reinterpret_cast<dbl2*>(p + 2));
+  } else {
+    put(&p[0], a);
+    put(&p[1], b);
+    put(&p[2], c);
+    put(&p[3], d);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // one branch: both end flows; first derivatives with respect to
 // (theta_f, v_f, v_t) are formed where they are used (members below)
@@ -201,7 +223,9 @@ struct Rec {
 // stored).
 template <unsigned WHAT, int BE, int STAGE>
 struct Lds {
-  static constexpr int kRec = Rec<WHAT>::N * BE;
+  // a product tile may hold the records of two instances
+  static constexpr int kInst = (WHAT & (W_VJP | W_HVP | W_JVP)) != 0 ? 2 : 1;
+  static constexpr int kRec = Rec<WHAT>::N * BE * kInst;
   static constexpr int kStage = (Rec<WHAT>::J || Rec<WHAT>::H) ? STAGE : 0;
   static constexpr int kGen = kGenChunk;
   static constexpr int kMax = kRec + kStage > kGen ? kRec + kStage : kGen;
@@ -293,6 +317,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   const double* dir = (R::HV || R::JV) ? B.dir + I.xo : nullptr;
   double* cflow = (R::C && B.c) ? B.c + I.co + 2 * nb : nullptr;
   double* jflow = (R::J && B.jac) ? B.jac + I.jo + (N.jflow - 8 * I.out_rm) : nullptr;
+  const bool jal = (reinterpret_cast<uintptr_t>(jflow) & 15) == 0;
   double* jac = (R::J && B.jac) ? B.jac + I.jo : nullptr;
   double* hess = (R::H && B.hess) ? B.hess + I.ho : nullptr;
   // Phase C's store of one staged row segment, consecutive lanes on
@@ -409,14 +434,8 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
             double* rf = jflow + 4 * lp;
             double* rt = jflow + 4 * nll + 4 * lp;
             // columns ascend: e_lo, e_hi, f_lo, f_hi
-            put(&rf[0], fwd ? hf0 : hf2);
-            put(&rf[1], fwd ? hf2 : hf0);
-            put(&rf[2], fwd ? hf1 : hf3);
-            put(&rf[3], fwd ? hf3 : hf1);
-            put(&rt[0], fwd ? ht0 : ht2);
-            put(&rt[1], fwd ? ht2 : ht0);
-            put(&rt[2], fwd ? ht1 : ht3);
-            put(&rt[3], fwd ? ht3 : ht1);
+            put_row4(rf, jal, fwd ? hf0 : hf2, fwd ? hf2 : hf0, fwd ? hf1 : hf3, fwd ? hf3 : hf1);
+            put_row4(rt, jal, fwd ? ht0 : ht2, fwd ? ht2 : ht0, fwd ? ht1 : ht3, fwd ? ht3 : ht1);
           }
         }
       }
@@ -627,14 +646,11 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
             const double ht_t = 2.0 * fma(b.Pt, b.Pt_t(), b.Qt * b.Qt_t());
             double* rf = jflow + 4 * lp;
             double* rt = jflow + 4 * nll + 4 * lp;
-            put(&rf[0], fwd ? hf_a : -hf_a);  // columns ascend: theta_lo, theta_hi, v_lo, v_hi
-            put(&rf[1], fwd ? -hf_a : hf_a);
-            put(&rf[2], fwd ? hf_f : hf_t);
-            put(&rf[3], fwd ? hf_t : hf_f);
-            put(&rt[0], fwd ? ht_a : -ht_a);
-            put(&rt[1], fwd ? -ht_a : ht_a);
-            put(&rt[2], fwd ? ht_f : ht_t);
-            put(&rt[3], fwd ? ht_t : ht_f);
+            // columns ascend: theta_lo, theta_hi, v_lo, v_hi
+            put_row4(rf, jal, fwd ? hf_a : -hf_a, fwd ? -hf_a : hf_a, fwd ? hf_f : hf_t,
+                     fwd ? hf_t : hf_f);
+            put_row4(rt, jal, fwd ? ht_a : -ht_a, fwd ? -ht_a : ht_a, fwd ? ht_f : ht_t,
+                     fwd ? ht_t : ht_f);
           }
         }
       }
@@ -825,7 +841,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       if (c) {
         double pg = 0, qg = 0;
         for (int g = N.gen_ptr[i], g1 = N.gen_ptr[i + 1]; g < g1; ++g) {
-          const int k = N.gen_list[g];
+          const int k = N.gen_ident ? g : N.gen_list[g];
           pg += x[2 * nb + k];
           qg += x[2 * nb + N.ng + k];
         }
@@ -863,7 +879,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
     if constexpr (R::JV) {
       double dpg = 0, dqg = 0;
       for (int g = N.gen_ptr[i], g1 = N.gen_ptr[i + 1]; g < g1; ++g) {
-        const int k = N.gen_list[g];
+        const int k = N.gen_ident ? g : N.gen_list[g];
         dpg += dir[2 * nb + k];
         dqg += dir[2 * nb + N.ng + k];
       }
@@ -1017,6 +1033,351 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
 }
 
 // ---------------------------------------------------------------------------
+// product tile: a bus tile of the VJP, HVP or JVP for NI instances that share
+// one base network (an N-1 batch pairs its instances).  The work items, the
+// branch admittances and the bus data are loaded once for all of them; each
+// instance gathers its own x, multipliers and direction (all of them before
+// any arithmetic, so that their loads are in flight together) and keeps its
+// own records.  Per instance the arithmetic and its order are those of a
+// tile of one instance, so results do not depend on the pairing.
+template <unsigned WHAT, int WG, int BE, int NI>
+__device__ void prod_tile(const Bufs& B, const InstOff& I0, const InstOff& I1, const NetDev& N,
+                          const Tile& T, const WorkItem* __restrict__ work, double* smem) {
+  using R = Rec<WHAT>;
+  static_assert(NI == 1 || NI == 2, "one or two instances per tile");
+  static_assert(!R::C && !R::J && !R::H, "products only");
+  constexpr bool CART = (WHAT & W_CART) != 0;
+  constexpr bool MUL = R::V || R::HV;   // weights: w_c (VJP) or lambda (HVP)
+  constexpr bool DIR = R::HV || R::JV;
+  const int tid = threadIdx.x;
+  const int nb = N.nb;
+  const int b0 = T.a0, nbus = T.a1 - T.a0, e0 = T.e0;
+  int ol[NI], nll[NI];
+  const double* xs[NI];
+  const double* mul[NI];
+  const double* dir[NI];
+  int64_t xo[NI], co[NI];
+#pragma unroll
+  for (int ii = 0; ii < NI; ++ii) {
+    const InstOff& I = ii ? I1 : I0;
+    ol[ii] = I.out_l;
+    nll[ii] = N.nl - (I.out_l >= 0 ? 1 : 0);
+    xo[ii] = I.xo;
+    co[ii] = I.co;
+    xs[ii] = B.x + I.xo;
+    mul[ii] = MUL ? (R::HV ? B.lam + I.co : B.wc + I.co) : nullptr;
+    dir[ii] = DIR ? B.dir + I.xo : nullptr;
+  }
+
+  // ---- phase A: lane per branch touching the tile
+  for (int k0 = 0; k0 < T.nw; k0 += WG) {
+    const int k = k0 + tid;
+    WorkItem wi{};
+    wi.l = -2;  // lanes past the list: no branch
+    if (k < T.nw) wi = work[T.w0 + k];
+    const int l = wi.l, f = wi.f, t = wi.t;
+    const uint32_t sf = wi.slots & 0xFFFFu, st = wi.slots >> 16;
+    BranchY y{};
+    if (l >= 0) y = N.br_y[l];
+    // every instance's inputs first
+    bool live[NI];
+    int lp[NI];
+    double gx[NI][4], gm[NI][6], gd[NI][4];
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+      live[ii] = l >= 0 && l != ol[ii];
+      lp[ii] = live[ii] ? l - after_outage(l, ol[ii]) : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) gx[ii][q] = gd[ii][q] = 0.0;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) gm[ii][q] = 0.0;
+      if (live[ii]) {
+        const double* x = xs[ii];
+        gx[ii][0] = x[f];
+        gx[ii][1] = x[t];
+        gx[ii][2] = x[nb + f];
+        gx[ii][3] = x[nb + t];
+        if constexpr (MUL) {
+          const double* m = mul[ii];
+          gm[ii][0] = m[2 * nb + lp[ii]];
+          gm[ii][1] = m[2 * nb + nll[ii] + lp[ii]];
+          gm[ii][2] = m[f];
+          gm[ii][3] = m[nb + f];
+          gm[ii][4] = m[t];
+          gm[ii][5] = m[nb + t];
+        }
+        if constexpr (DIR) {
+          const double* d = dir[ii];
+          gd[ii][0] = d[f];
+          gd[ii][1] = d[t];
+          gd[ii][2] = d[nb + f];
+          gd[ii][3] = d[nb + t];
+        }
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+      double* rec = smem + ii * (R::N * BE);
+      if (l >= 0 && !live[ii]) {  // removed branch: its ends keep their places and add zero
+#pragma unroll
+        for (int q = 0; q < R::N; ++q) {
+          if (sf != kNoSlot) rec[q * BE + sf] = 0.0;
+          if (st != kNoSlot) rec[q * BE + st] = 0.0;
+        }
+      }
+      if (!live[ii]) continue;
+      const int lpi = lp[ii], nl_i = nll[ii];
+      if constexpr (CART) {
+        BrC b;
+        branch_eval_cart(gx[ii][0], gx[ii][2], gx[ii][1], gx[ii][3], y, b);
+        if constexpr (R::JV) {
+          const double d0 = gd[ii][0], d1 = gd[ii][2], d2 = gd[ii][1], d3 = gd[ii][3];
+          const double jPf = fma(b.gPf<0>(), d0, fma(b.gPf<1>(), d1, fma(b.gPf<2>(), d2, b.gPf<3>() * d3)));
+          const double jQf = fma(b.gQf<0>(), d0, fma(b.gQf<1>(), d1, fma(b.gQf<2>(), d2, b.gQf<3>() * d3)));
+          const double jPt = fma(b.gPt<0>(), d0, fma(b.gPt<1>(), d1, fma(b.gPt<2>(), d2, b.gPt<3>() * d3)));
+          const double jQt = fma(b.gQt<0>(), d0, fma(b.gQt<1>(), d1, fma(b.gQt<2>(), d2, b.gQt<3>() * d3)));
+          if (sf != kNoSlot) {
+            rec[(R::oJV + 0) * BE + sf] = jPf;
+            rec[(R::oJV + 1) * BE + sf] = jQf;
+            double* o = B.out + co[ii] + 2 * nb;
+            put(&o[lpi], 2.0 * fma(b.Pf, jPf, b.Qf * jQf));
+            put(&o[nl_i + lpi], 2.0 * fma(b.Pt, jPt, b.Qt * jQt));
+          }
+          if (st != kNoSlot) {
+            rec[(R::oJV + 0) * BE + st] = jPt;
+            rec[(R::oJV + 1) * BE + st] = jQt;
+          }
+        }
+        if constexpr (MUL) {
+          const double mf = gm[ii][0], mt = gm[ii][1];
+          const double oPf = fma(2.0 * mf, b.Pf, gm[ii][2]);
+          const double oQf = fma(2.0 * mf, b.Qf, gm[ii][3]);
+          const double oPt = fma(2.0 * mt, b.Pt, gm[ii][4]);
+          const double oQt = fma(2.0 * mt, b.Qt, gm[ii][5]);
+          if constexpr (R::V) {
+            const double u0 = fma(oPf, b.gPf<0>(), fma(oQf, b.gQf<0>(), fma(oPt, b.gPt<0>(), oQt * b.gQt<0>())));
+            const double u1 = fma(oPf, b.gPf<1>(), fma(oQf, b.gQf<1>(), fma(oPt, b.gPt<1>(), oQt * b.gQt<1>())));
+            const double u2 = fma(oPf, b.gPf<2>(), fma(oQf, b.gQf<2>(), fma(oPt, b.gPt<2>(), oQt * b.gQt<2>())));
+            const double u3 = fma(oPf, b.gPf<3>(), fma(oQf, b.gQf<3>(), fma(oPt, b.gPt<3>(), oQt * b.gQt<3>())));
+            if (sf != kNoSlot) {
+              rec[(R::oV + 0) * BE + sf] = u0;
+              rec[(R::oV + 1) * BE + sf] = u1;
+            }
+            if (st != kNoSlot) {
+              rec[(R::oV + 0) * BE + st] = u2;
+              rec[(R::oV + 1) * BE + st] = u3;
+            }
+          }
+          if constexpr (R::HV) {
+            // the branch's local Hessian (see the bus tile) times the direction
+            const double cf = fma(oPf, b.gff, -(oQf * b.bff));
+            const double ct = fma(oPt, b.gtt, -(oQt * b.btt));
+            const double cA = fma(oPf, b.gft, fma(-oQf, b.bft, fma(oPt, b.gtf, -(oQt * b.btf))));
+            const double cB = fma(oPf, b.bft, fma(oQf, b.gft, -fma(oPt, b.btf, oQt * b.gtf)));
+            const double m2f = 2.0 * mf, m2t = 2.0 * mt;
+            const double pf0 = b.gPf<0>(), pf1 = b.gPf<1>(), pf2 = b.gPf<2>(), pf3 = b.gPf<3>();
+            const double qf0 = b.gQf<0>(), qf1 = b.gQf<1>(), qf2 = b.gQf<2>(), qf3 = b.gQf<3>();
+            const double pt0 = b.gPt<0>(), pt1 = b.gPt<1>(), pt2 = b.gPt<2>(), pt3 = b.gPt<3>();
+            const double qt0 = b.gQt<0>(), qt1 = b.gQt<1>(), qt2 = b.gQt<2>(), qt3 = b.gQt<3>();
+            auto gn = [&](double w, double pa, double pb, double qa, double qb, double sa,
+                          double sb, double ra, double rb) {
+              return fma(m2f, fma(pa, pb, qa * qb), fma(m2t, fma(sa, sb, ra * rb), w));
+            };
+            const double h00 = gn(2.0 * cf, pf0, pf0, qf0, qf0, pt0, pt0, qt0, qt0);
+            const double h10 = gn(0.0, pf1, pf0, qf1, qf0, pt1, pt0, qt1, qt0);
+            const double h11 = gn(2.0 * cf, pf1, pf1, qf1, qf1, pt1, pt1, qt1, qt1);
+            const double h22 = gn(2.0 * ct, pf2, pf2, qf2, qf2, pt2, pt2, qt2, qt2);
+            const double h32 = gn(0.0, pf3, pf2, qf3, qf2, pt3, pt2, qt3, qt2);
+            const double h33 = gn(2.0 * ct, pf3, pf3, qf3, qf3, pt3, pt3, qt3, qt3);
+            const double h02 = gn(cA, pf0, pf2, qf0, qf2, pt0, pt2, qt0, qt2);
+            const double h03 = gn(-cB, pf0, pf3, qf0, qf3, pt0, pt3, qt0, qt3);
+            const double h12 = gn(cB, pf1, pf2, qf1, qf2, pt1, pt2, qt1, qt2);
+            const double h13 = gn(cA, pf1, pf3, qf1, qf3, pt1, pt3, qt1, qt3);
+            const double d0 = gd[ii][0], d1 = gd[ii][2], d2 = gd[ii][1], d3 = gd[ii][3];
+            if (sf != kNoSlot) {
+              rec[(R::oHV + 0) * BE + sf] = fma(h00, d0, fma(h10, d1, fma(h02, d2, h03 * d3)));
+              rec[(R::oHV + 1) * BE + sf] = fma(h10, d0, fma(h11, d1, fma(h12, d2, h13 * d3)));
+            }
+            if (st != kNoSlot) {
+              rec[(R::oHV + 0) * BE + st] = fma(h02, d0, fma(h12, d1, fma(h22, d2, h32 * d3)));
+              rec[(R::oHV + 1) * BE + st] = fma(h03, d0, fma(h13, d1, fma(h32, d2, h33 * d3)));
+            }
+          }
+        }
+      } else {
+        Br b;
+        branch_eval(gx[ii][0], gx[ii][1], gx[ii][2], gx[ii][3], y, b);
+        if constexpr (R::JV) {  // J d: first derivatives along the direction
+          const double da = gd[ii][0] - gd[ii][1], dvf = gd[ii][2], dvt = gd[ii][3];
+          const double jPf = fma(b.Pf_a(), da, fma(b.Pf_f(), dvf, b.Pf_t() * dvt));
+          const double jQf = fma(b.Qf_a(), da, fma(b.Qf_f(), dvf, b.Qf_t() * dvt));
+          const double jPt = fma(b.Pt_a(), da, fma(b.Pt_f(), dvf, b.Pt_t() * dvt));
+          const double jQt = fma(b.Qt_a(), da, fma(b.Qt_f(), dvf, b.Qt_t() * dvt));
+          if (sf != kNoSlot) {
+            rec[(R::oJV + 0) * BE + sf] = jPf;
+            rec[(R::oJV + 1) * BE + sf] = jQf;
+            double* o = B.out + co[ii] + 2 * nb;
+            put(&o[lpi], 2.0 * fma(b.Pf, jPf, b.Qf * jQf));
+            put(&o[nl_i + lpi], 2.0 * fma(b.Pt, jPt, b.Qt * jQt));
+          }
+          if (st != kNoSlot) {
+            rec[(R::oJV + 0) * BE + st] = jPt;
+            rec[(R::oJV + 1) * BE + st] = jQt;
+          }
+        }
+        if constexpr (MUL) {
+          const double mf = gm[ii][0], mt = gm[ii][1];
+          // weights of dP, dQ in  lP P + lQ Q + mu (P^2 + Q^2)
+          const double oPf = fma(2.0 * mf, b.Pf, gm[ii][2]);
+          const double oQf = fma(2.0 * mf, b.Qf, gm[ii][3]);
+          const double oPt = fma(2.0 * mt, b.Pt, gm[ii][4]);
+          const double oQt = fma(2.0 * mt, b.Qt, gm[ii][5]);
+          // s, r: the weighted transfer terms (see the bus tile)
+          const double s = fma(oPf, b.cP, fma(oQf, b.cQ, fma(oPt, b.cPt, oQt * b.cQt)));
+          const double r = fma(oQf, b.cP, fma(-oPf, b.cQ, fma(oPt, b.cQt, -(oQt * b.cPt))));
+          if constexpr (R::V) {
+            const double u_a = b.w * r;  // d/dtheta_f; d/dtheta_t = -u_a
+            const double u_f = fma(2.0 * b.vf, fma(oPf, b.gff, -(oQf * b.bff)), b.vt * s);
+            const double u_t = fma(2.0 * b.vt, fma(oPt, b.gtt, -(oQt * b.btt)), b.vf * s);
+            if (sf != kNoSlot) {
+              rec[(R::oV + 0) * BE + sf] = u_a;
+              rec[(R::oV + 1) * BE + sf] = u_f;
+            }
+            if (st != kNoSlot) {
+              rec[(R::oV + 0) * BE + st] = -u_a;
+              rec[(R::oV + 1) * BE + st] = u_t;
+            }
+          }
+          if constexpr (R::HV) {
+            const double m2f = 2.0 * mf, m2t = 2.0 * mt;
+            const double ccf = fma(b.cP, b.cP, b.cQ * b.cQ), cct = fma(b.cPt, b.cPt, b.cQt * b.cQt);
+            const double a = fma(-b.w, s, (b.w * b.w) * fma(m2f, ccf, m2t * cct));
+            const double beta_f =
+                fma(b.vt, r, -(2.0 * m2f) * (b.vf * b.w) * fma(b.gff, b.cQ, b.bff * b.cP));
+            const double beta_t =
+                -fma(b.vf, r, (2.0 * m2t) * (b.vt * b.w) * fma(b.gtt, b.cQt, b.btt * b.cPt));
+            const double pff = b.Pf_f(), qff = b.Qf_f(), ptt = b.Pt_t(), qtt = b.Qt_t();
+            const double vv_ff = fma(2.0, fma(oPf, b.gff, -(oQf * b.bff)),
+                                     fma(m2f, fma(pff, pff, qff * qff), m2t * (b.vt * b.vt) * cct));
+            const double vv_tt = fma(2.0, fma(oPt, b.gtt, -(oQt * b.btt)),
+                                     fma(m2f * (b.vf * b.vf), ccf, m2t * fma(ptt, ptt, qtt * qtt)));
+            const double vv_ft =
+                s + fma(m2f * b.vf, fma(2.0 * b.vf, fma(b.gff, b.cP, -(b.bff * b.cQ)), b.vt * ccf),
+                        m2t * b.vt * fma(2.0 * b.vt, fma(b.gtt, b.cPt, -(b.btt * b.cQt)), b.vf * cct));
+            const double da = gd[ii][0] - gd[ii][1], dvf = gd[ii][2], dvt = gd[ii][3];
+            const double h_a = fma(a, da, fma(beta_f, dvf, -(beta_t * dvt)));
+            if (sf != kNoSlot) {
+              rec[(R::oHV + 0) * BE + sf] = h_a;
+              rec[(R::oHV + 1) * BE + sf] = fma(beta_f, da, fma(vv_ff, dvf, vv_ft * dvt));
+            }
+            if (st != kNoSlot) {
+              rec[(R::oHV + 0) * BE + st] = -h_a;
+              rec[(R::oHV + 1) * BE + st] = fma(-beta_t, da, fma(vv_ft, dvf, vv_tt * dvt));
+            }
+          }
+        }
+      }
+    }
+  }
+
+  // ---- lane per bus: its own terms, then (after the barrier) its ends'
+  // records summed in adjacency order
+  const bool has_bus = tid < nbus;
+  const int i = b0 + tid;
+  int ea = 0, eb = 0;
+  double own0[NI], own1[NI], own2[NI];  // per product: the bus's own terms
+#pragma unroll
+  for (int ii = 0; ii < NI; ++ii) own0[ii] = own1[ii] = own2[ii] = 0.0;
+  if (has_bus) {
+    ea = N.be_ptr[i] - e0;
+    eb = N.be_ptr[i + 1] - e0;
+    const double4 bd = N.bus[i];  // pd, qd, gs, bs
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+      const double* x = xs[ii];
+      const double vi = x[nb + i];  // v_i, or f_i in the cartesian representation
+      double lvm = 0.0;
+      (void)lvm;
+      double ei = 0.0;
+      (void)ei;
+      if constexpr (CART) {
+        ei = x[i];
+        if constexpr (MUL) lvm = mul[ii][2 * nb + 2 * nll[ii] + i];
+      }
+      if constexpr (R::V) {
+        const double* m = mul[ii];
+        if constexpr (CART) {
+          const double kap = 2.0 * (fma(m[i], bd.z, -(m[nb + i] * bd.w)) + lvm);
+          own0[ii] = kap * ei;   // theta (e) column
+          own1[ii] = kap * vi;   // v (f) column
+        } else {
+          own1[ii] = 2.0 * vi * fma(m[i], bd.z, -(m[nb + i] * bd.w));
+        }
+      }
+      if constexpr (R::HV) {
+        const double* m = mul[ii];
+        const double* d = dir[ii];
+        if constexpr (CART) {
+          const double kap = 2.0 * (fma(m[i], bd.z, -(m[nb + i] * bd.w)) + lvm);
+          own0[ii] = kap * d[i];
+          own1[ii] = kap * d[nb + i];
+        } else {
+          own1[ii] = 2.0 * fma(m[i], bd.z, -(m[nb + i] * bd.w)) * d[nb + i];
+        }
+      }
+      if constexpr (R::JV) {
+        const double* d = dir[ii];
+        double dpg = 0, dqg = 0;
+        for (int g = N.gen_ptr[i], g1 = N.gen_ptr[i + 1]; g < g1; ++g) {
+          const int kk = N.gen_ident ? g : N.gen_list[g];
+          dpg += d[2 * nb + kk];
+          dqg += d[2 * nb + N.ng + kk];
+        }
+        double jvP, jvQ;
+        if constexpr (CART) {  // d|V_i|^2 along the direction
+          const double jvm = 2.0 * fma(ei, d[i], vi * d[nb + i]);
+          own2[ii] = jvm;
+          jvP = bd.z * jvm - dpg;
+          jvQ = -bd.w * jvm - dqg;
+        } else {
+          jvP = 2.0 * bd.z * vi * d[nb + i] - dpg;
+          jvQ = -2.0 * bd.w * vi * d[nb + i] - dqg;
+        }
+        for (int q = 0; q < N.sl.ns; ++q) {
+          const double tt = N.sl.coef[q] * d[2 * nb + 2 * N.ng + q * nb + i];
+          if (N.sl.row[q] == 0) jvP += tt; else jvQ += tt;
+        }
+        own0[ii] = jvP;
+        own1[ii] = jvQ;
+      }
+    }
+  }
+  __syncthreads();
+  if (has_bus) {
+#pragma unroll
+    for (int ii = 0; ii < NI; ++ii) {
+      const double* rec = smem + ii * (R::N * BE);
+      constexpr int o = R::V ? R::oV : (R::HV ? R::oHV : R::oJV);
+      double s0 = 0.0, s1 = 0.0;
+      for (int e = ea; e < eb; ++e) {
+        s0 += rec[(o + 0) * BE + e];
+        s1 += rec[(o + 1) * BE + e];
+      }
+      if constexpr (R::V || R::HV) {
+        double* out = (R::V ? B.u : B.out) + xo[ii];
+        put(&out[i], CART ? s0 + own0[ii] : s0);
+        put(&out[nb + i], s1 + own1[ii]);
+      } else {
+        double* out = B.out + co[ii];
+        put(&out[i], s0 + own0[ii]);
+        put(&out[nb + i], s1 + own1[ii]);
+        if constexpr (CART) put(&out[2 * nb + 2 * nll[ii] + i], own2[ii]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // gen tile: objective, its gradient, the Pg diagonal of H, the Pg/Qg part of
 // the VJP, and this chunk's fixed-tree partial sum of the cost.  Its items
 // are the generators, then (if the net has them) the slack variables, each
@@ -1125,6 +1486,36 @@ __global__ __launch_bounds__(256) void k_fsum(const InstOff* __restrict__ table,
 
 // ---------------------------------------------------------------------------
 
+// The products' kernel: bus tiles of one or two instances (prod_tile) and
+// generator tiles, at the waves per SIMD their registers allow without
+// spilling: three for the HVP and the polar JVP, four otherwise.
+template <unsigned WHAT>
+struct ProdWaves {
+  static constexpr int value =
+      ((WHAT & W_HVP) != 0 || ((WHAT & W_JVP) != 0 && (WHAT & W_CART) == 0)) ? 3 : 4;
+};
+
+template <unsigned WHAT, int WG, int BE>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(ProdWaves<WHAT>::value)))
+void k_prod(Bufs B, const InstOff* __restrict__ table, InstOff one, const Tile* __restrict__ tiles,
+            int ntiles) {
+  __shared__ double smem[Lds<WHAT, BE, 0>::kMax];
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const Tile T = tiles[t];
+    const InstOff I = table ? table[T.inst] : one;
+    const NetDev& N = *I.net;
+    if ((T.kind_aux & 3) == TILE_BUS) {
+      if (T.inst2 >= 0)
+        prod_tile<WHAT, WG, BE, 2>(B, I, table[T.inst2], N, T, one.work, smem);
+      else
+        prod_tile<WHAT, WG, BE, 1>(B, I, I, N, T, one.work, smem);
+    } else {
+      gen_tile<WHAT, WG>(B, I, N, T.a0, T.a1, T.kind_aux >> 2, smem);
+    }
+    __syncthreads();
+  }
+}
+
 template <unsigned WHAT, int WG, int BE, int NBUS, int STAGE>
 __global__ __launch_bounds__(WG) void k_eval(Bufs B, const InstOff* __restrict__ table,
                                              InstOff one, const Tile* __restrict__ tiles,
@@ -1152,7 +1543,10 @@ hipError_t launch_caps(int tile_be, const Bufs& b, const InstOff* table, const I
   switch (tile_be) {
 #define ACOPF_CASE(C)                                                                      \
   case C.cls:                                                                              \
-    k_eval<WHAT, C.wg, C.be, C.nbus, C.stage><<<blocks, C.wg, 0, s>>>(b, table, one, tiles, ntiles); \
+    if constexpr ((WHAT & (W_VJP | W_HVP | W_JVP)) != 0)                                   \
+      k_prod<WHAT, C.wg, C.be><<<blocks, C.wg, 0, s>>>(b, table, one, tiles, ntiles);       \
+    else                                                                                   \
+      k_eval<WHAT, C.wg, C.be, C.nbus, C.stage><<<blocks, C.wg, 0, s>>>(b, table, one, tiles, ntiles); \
     break;
     ACOPF_CASE(kCaps64)
     ACOPF_CASE(kCaps128)
