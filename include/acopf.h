@@ -382,6 +382,21 @@ int acopf_batch_eval_noalloc(acopf_batch batch, const double* x, const double* s
                              double* jac_val, double* hess_val, unsigned what,
                              hipStream_t stream);
 
+/* One served window in one call: draws the iterates of the instances
+ * [first, first + count) from the request seeds as acopf_batch_draw_iterates
+ * does (same stream of numbers), sets their sigma to 1 and evaluates every
+ * output as acopf_batch_eval_range with ACOPF_ALL.  seeds: HOST array of
+ * count entries, copied into the launch arguments (no device staging, no
+ * wait for the host array afterwards); count <= 64.  x, lambda, sigma and the
+ * outputs: the batch's packed DEVICE buffers.  The serving loop's fast path
+ * for requests that carry only a seed.  Errors: EINVAL (window, count, a
+ * cartesian batch or nets with slack variables), EHIP. */
+int acopf_batch_serve_window(acopf_batch batch, int32_t first, int32_t count,
+                             const uint64_t* seeds, double pmin, double pmax, double qmin,
+                             double qmax, double* x, double* lambda, double* sigma, double* f,
+                             double* grad_f, double* c, double* jac_val, double* hess_val,
+                             hipStream_t stream);
+
 /* Random iterates for the instances [first, first + count), drawn on the
  * device for a served request stream (the request carries only a seed).
  * Counter-based: stream element j of instance k is

@@ -116,6 +116,8 @@ _SIGS = {
     "acopf_batch_xdot": (C.c_int, [C.c_void_p] * 5),
     "acopf_batch_eval_range": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32] + [C.c_void_p] * 8
                                + [C.c_uint, C.c_void_p]),
+    "acopf_batch_serve_window": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+                                 + [C.c_double] * 4 + [C.c_void_p] * 9),
     "acopf_batch_draw_iterates": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
                                   + [C.c_double] * 4 + [C.c_void_p, C.c_void_p, C.c_void_p]),
     "acopf_couple_create": (C.c_int, [C.c_void_p, _i32p, _i32p, C.c_int32, C.POINTER(C.c_void_p)]),
@@ -497,6 +499,21 @@ def acopf_batch_draw_iterates(b: Batch, first: int, count: int, seeds, bounds, x
     _check(lib().acopf_batch_draw_iterates(
         b.handle, int(first), int(count), C.c_void_p(seeds.data_ptr()), pmin, pmax, qmin, qmax,
         _ptr(x, int(b.x_off[-1]), "x"), _ptr(lam, int(b.c_off[-1]), "lambda"), _stream(stream)))
+
+
+def acopf_batch_serve_window(b: Batch, first: int, count: int, seeds, bounds, x, lam, sigma,
+                             f, grad_f, c, jac_val, hess_val, stream=None):
+    """seeds: host sequence of count request seeds (bit patterns, unsigned
+    64-bit); bounds: (pmin, pmax, qmin, qmax)."""
+    k = b.count
+    arr = (C.c_uint64 * int(count))(*[int(v) & 0xFFFFFFFFFFFFFFFF for v in seeds])
+    pmin, pmax, qmin, qmax = (float(v) for v in bounds)
+    _check(lib().acopf_batch_serve_window(
+        b.handle, int(first), int(count), C.cast(arr, C.c_void_p), pmin, pmax, qmin, qmax,
+        _ptr(x, int(b.x_off[-1]), "x"), _ptr(lam, int(b.c_off[-1]), "lambda"),
+        _ptr(sigma, k, "sigma"), _ptr(f, k, "f"), _ptr(grad_f, int(b.x_off[-1]), "grad_f"),
+        _ptr(c, int(b.c_off[-1]), "c"), _ptr(jac_val, int(b.j_off[-1]), "jac_val"),
+        _ptr(hess_val, int(b.h_off[-1]), "hess_val"), _stream(stream)))
 
 
 def acopf_batch_hvp(b: Batch, x, sigma, lam, d, out, stream=None):

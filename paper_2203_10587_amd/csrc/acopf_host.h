@@ -86,6 +86,19 @@ int net_init_scratch(acopf_net_s* net);
 InstOff net_inst(const acopf_net_s* net);
 int check_device(const acopf_net_s* net);
 
+// Seeds of one served window, passed by value in the draw kernel's arguments.
+constexpr int kWindowSeeds = 64;
+struct WindowSeeds {
+  uint64_t s[kWindowSeeds];
+};
+
+// Draw the iterates of instances [first, first + count) from host seeds and
+// set their sigma to 1 (count <= kWindowSeeds).
+hipError_t launch_draw_window(const InstOff* table, int first, int count, int max_len,
+                              const uint64_t* host_seeds, double pmin, double pmax, double qmin,
+                              double qmax, double* x, double* lam, double* sigma,
+                              hipStream_t stream);
+
 // Per-instance dot products over the packed x layout of a batch table:
 // out[k] = a_k . b_k (fixed summation order).
 hipError_t launch_xdot(const InstOff* table, int count, const double* a, const double* b,

@@ -8,7 +8,7 @@
 // a double in [0, 1).  Normals by the Box-Muller transform.
 #include <hip/hip_runtime.h>
 
-#include "acopf_internal.h"
+#include "acopf_host.h"
 
 namespace acopf {
 namespace {
@@ -21,14 +21,11 @@ __device__ __forceinline__ double uniform01(uint64_t seed, uint64_t j) {
   return static_cast<double>(z >> 11) * 0x1.0p-53;
 }
 
-__global__ __launch_bounds__(256) void k_draw(const InstOff* __restrict__ table, int first,
-                                              const uint64_t* __restrict__ seeds, double pmin,
-                                              double pmax, double qmin, double qmax, double* x,
-                                              double* lam) {
-  const int k = first + static_cast<int>(blockIdx.y);
-  const InstOff I = table[k];
+// Instance k's x and lambda from its seed; the workgroups of grid row y
+// stride over the n + m stream elements.
+__device__ __forceinline__ void draw_one(const InstOff& I, uint64_t seed, double pmin, double pmax,
+                                         double qmin, double qmax, double* x, double* lam) {
   const NetDev& N = *I.net;
-  const uint64_t seed = seeds[k];
   const int nb = N.nb, ng = N.ng;
   const int n = 2 * nb + 2 * ng;
   const int m = 2 * nb + 2 * (N.nl - (I.out_l >= 0 ? 1 : 0));
@@ -57,7 +54,40 @@ __global__ __launch_bounds__(256) void k_draw(const InstOff* __restrict__ table,
   }
 }
 
+__global__ __launch_bounds__(256) void k_draw(const InstOff* __restrict__ table, int first,
+                                              const uint64_t* __restrict__ seeds, double pmin,
+                                              double pmax, double qmin, double qmax, double* x,
+                                              double* lam) {
+  const int k = first + static_cast<int>(blockIdx.y);
+  draw_one(table[k], seeds[k], pmin, pmax, qmin, qmax, x, lam);
+}
+
+// A served window: the seeds travel in the launch arguments (no copy to the
+// device first), and each instance's sigma is set to 1.
+__global__ __launch_bounds__(256) void k_draw_window(const InstOff* __restrict__ table, int first,
+                                                     WindowSeeds seeds, double pmin, double pmax,
+                                                     double qmin, double qmax, double* x,
+                                                     double* lam, double* sigma) {
+  const int k = first + static_cast<int>(blockIdx.y);
+  draw_one(table[k], seeds.s[blockIdx.y], pmin, pmax, qmin, qmax, x, lam);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sigma[k] = 1.0;
+}
+
 }  // namespace
+
+hipError_t launch_draw_window(const InstOff* table, int first, int count, int max_len,
+                              const uint64_t* host_seeds, double pmin, double pmax, double qmin,
+                              double qmax, double* x, double* lam, double* sigma,
+                              hipStream_t stream) {
+  if (count <= 0) return hipSuccess;
+  if (count > kWindowSeeds) return hipErrorInvalidValue;
+  WindowSeeds ws;
+  for (int k = 0; k < count; ++k) ws.s[k] = host_seeds[k];
+  const int bx = (max_len + 255) / 256 < 64 ? (max_len + 255) / 256 : 64;
+  k_draw_window<<<dim3(bx > 0 ? bx : 1, count), 256, 0, stream>>>(table, first, ws, pmin, pmax,
+                                                                  qmin, qmax, x, lam, sigma);
+  return hipGetLastError();
+}
 
 hipError_t launch_draw(const InstOff* table, int first, int count, int max_len,
                        const uint64_t* seeds, double pmin, double pmax, double qmin, double qmax,

@@ -29,6 +29,7 @@ a simulated executor with the same interface.
 from __future__ import annotations
 
 import collections
+import ctypes
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Sequence
@@ -39,9 +40,11 @@ class Request:
     rid: int
     grid: int
     seed: int
-    t_arrive: float
-    t_launch: float = float("nan")
-    t_done: float = float("nan")
+    t_arrive: float                 # scheduled arrival (latency runs from here)
+    t_submit: float = float("nan")  # when the server took it in
+    t_launch: float = float("nan")  # admission: its window's launch call began
+    t_issued: float = float("nan")  # the launch call returned
+    t_done: float = float("nan")    # completion observed by the server
     slot: int = -1
     status: str = "queued"     # queued | running | copying | done | failed | rejected
     error: str = ""
@@ -152,6 +155,7 @@ class Server:
         self.requests: List[Request] = []
         self.copying: collections.deque = collections.deque()  # (requests, handle)
         self.windows_launched = 0
+        self.peak_windows = 0   # windows in flight at once, at most
         self._rr = 0
 
     # -- intake ---------------------------------------------------------------
@@ -159,8 +163,9 @@ class Server:
                lam=None, sigma: float = 1.0) -> Request:
         """Queue one evaluation of `grid`: at the caller's iterate (x, lam,
         sigma) if x is given, else at the iterate drawn from `seed`."""
+        now = self.clock()
         r = Request(rid=len(self.requests), grid=grid, seed=int(seed),
-                    t_arrive=self.clock() if t_arrive is None else float(t_arrive))
+                    t_arrive=now if t_arrive is None else float(t_arrive), t_submit=now)
         self.requests.append(r)
         if grid not in self.pools:
             r.status, r.error = "rejected", "unknown grid"
@@ -186,13 +191,15 @@ class Server:
         n = 0
         # requests whose result copies have completed on the device
         while self.copying and self.ex.done(self.copying[0][1]):
+            t = self.clock()
             for r in self.copying.popleft()[0]:
-                r.t_done, r.status = now, "done"
+                r.t_done, r.status = t, "done"
             n += 1
         for g, q in self.inflight.items():
             keep = collections.deque()
             for w in q:
                 if w.handle is not None and self.ex.done(w.handle):
+                    now = self.clock()  # when this completion was seen
                     if w.reqs and w.reqs[0].status == "running":
                         for r in w.reqs:
                             r.inputs = None  # copied into the slot long ago
@@ -238,6 +245,7 @@ class Server:
                     break
                 first, k = got
                 reqs = [q.popleft() for _ in range(k)]
+                t_call = self.clock()
                 try:
                     seeds = [r.seed for r in reqs]
                     if any(r.inputs is not None for r in reqs):
@@ -249,12 +257,16 @@ class Server:
                     for r in reqs:
                         r.status, r.error, r.t_done = "failed", f"launch: {exc}", now
                     continue
+                t_ret = self.clock()
                 for i, r in enumerate(reqs):
-                    r.slot, r.status, r.t_launch = first + i, "running", now
+                    r.slot, r.status = first + i, "running"
+                    r.t_launch, r.t_issued = t_call, t_ret
                 self.bytes_in_flight += k * sb
                 self.peak_bytes = max(self.peak_bytes, self.bytes_in_flight)
                 self.inflight[g].append(_Window(g, first, reqs, h, now, k * sb))
                 self.windows_launched += 1
+                self.peak_windows = max(self.peak_windows,
+                                        sum(len(v) for v in self.inflight.values()))
                 launched += 1
         self._rr = (self._rr + 1) % max(1, len(grids))
         return launched
@@ -299,14 +311,29 @@ class Server:
             if len(lg):
                 per[str(g)] = {"n": int(len(lg)), "p50_ms": float(np.percentile(lg, 50)),
                                "p99_ms": float(np.percentile(lg, 99))}
+        # where the time of a request goes: waiting to be taken in and
+        # admitted (queue), the launch call (launch), and the device work until
+        # the server saw it finish (complete); and the same parts averaged over
+        # the requests slower than the p99 latency
+        parts = {}
+        if done:
+            q = np.array([r.t_launch - r.t_arrive for r in done]) * 1e3
+            la = np.array([r.t_issued - r.t_launch for r in done]) * 1e3
+            co = np.array([r.t_done - r.t_issued for r in done]) * 1e3
+            tail = lat > np.percentile(lat, 99)
+            for name, v in (("queue", q), ("launch", la), ("complete", co)):
+                parts[name] = {"p50_ms": float(np.percentile(v, 50)),
+                               "p99_ms": float(np.percentile(v, 99)),
+                               "tail_mean_ms": float(v[tail].mean()) if tail.any() else 0.0}
         return {
-            "requests": len(self.requests), "done": len(done),
+            "requests": len(self.requests), "done": len(done), "parts": parts,
             "failed": sum(r.status == "failed" for r in self.requests),
             "rejected": sum(r.status == "rejected" for r in self.requests),
             "wall_s": wall_s, "throughput_rps": len(done) / wall_s if wall_s > 0 else 0.0,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "windows": self.windows_launched,
             "mean_window": len(done) / max(1, self.windows_launched),
+            "peak_windows_in_flight": self.peak_windows,
             "peak_bytes_in_flight": self.peak_bytes, "per_grid": per,
         }
 
@@ -346,9 +373,16 @@ class GpuExecutor(Executor):
             bounds = (float(g.gen_pmin[0]) if g.ngen else 0.0, float(g.gen_pmax[0]) if g.ngen else 0.0,
                       float(g.gen_qmin[0]) if g.ngen else 0.0, float(g.gen_qmax[0]) if g.ngen else 0.0)
             per_slot = 8 * (2 * net.n + 2 * net.m + 1 + net.nnz_jac + net.nnz_hess) + 16
+            stream = torch.cuda.Stream()
+            # the seeded window's one library call, its pointer arguments
+            # marshalled once: (batch, first, count, seeds, bounds, buffers, stream)
+            vp = lambda t: ctypes.c_void_p(t.data_ptr())
+            fast = ([b.handle], [ctypes.c_double(v) for v in bounds],
+                    [vp(bufs[k]) for k in ("x", "lam", "sigma", "f", "gf", "c", "jac", "hess")]
+                    + [ctypes.c_void_p(stream.cuda_stream)])
             self.pool.append(dict(net=net, batch=b, bufs=bufs, seeds=seeds, pinned=pinned,
-                                  bounds=bounds, cap=int(cap), stream=torch.cuda.Stream(),
-                                  slot_bytes=per_slot))
+                                  bounds=bounds, cap=int(cap), stream=stream,
+                                  slot_bytes=per_slot, fast=fast))
 
     def grids(self):
         return list(range(len(self.pool)))
@@ -367,10 +401,20 @@ class GpuExecutor(Executor):
     def launch(self, grid, first, seeds, inputs=None):
         """Draw the window's iterates from the seeds, overwrite the slots whose
         request brought its own (x, lam, sigma), evaluate; returns the
-        completion event."""
+        completion event.  A window of seeded requests only is one library
+        call (acopf_batch_serve_window), the seeds in its launch arguments."""
         import torch
         P = self.pool[grid]
         k = len(seeds)
+        if not inputs or all(inp is None for inp in inputs):
+            head, bounds, tail = P["fast"]
+            arr = (ctypes.c_uint64 * k)(*[s & ((1 << 63) - 1) for s in seeds])
+            rc = self.A.lib().acopf_batch_serve_window(*head, first, k, arr, *bounds, *tail)
+            if rc:
+                raise self.A.AcopfError(rc, self.A.lib().acopf_last_error().decode())
+            ev = torch.cuda.Event()
+            ev.record(P["stream"])
+            return ev
         P["pinned"][first:first + k] = torch.tensor([s & ((1 << 63) - 1) for s in seeds],
                                                     dtype=torch.int64)
         st = P["stream"]

@@ -122,3 +122,34 @@ def test_caller_iterates_with_results(gpu_lib):
         out = O.evaluate(mdl, it.x, it.sigma, it.lam)
         ref = {"mdl": mdl, "out": out, "scale": O.scales(mdl, it.x, out, it.sigma, it.lam)}
         compare_outputs(f"own-{r.rid}", got, ref)
+
+
+def test_burst_forms_windows_and_results_match_alone(gpu_lib):
+    """Continuous batching on the GPU: a burst of 48 requests over three grids
+    arrives at once; the server admits them in windows of several requests,
+    windows of different grids are in flight together, and every result
+    (kept on the device) equals, bit for bit, the same request served alone."""
+    from paper_2203_10587_amd.serve import GpuExecutor, Server
+    grids = _grids()
+    ex = GpuExecutor(grids, [16, 16, 16])
+    srv = Server(ex, budget_bytes=1 << 30, max_window=8, keep_results=True)
+    rng = np.random.default_rng(17)
+    reqs = [srv.submit(k % 3, int(rng.integers(0, 2 ** 62))) for k in range(48)]
+    while not srv.idle():
+        srv.step()
+    st = srv.stats(1.0)
+    log(f"[burst] windows {st['windows']}, mean window {st['mean_window']:.2f}, "
+        f"peak windows in flight {st['peak_windows_in_flight']}")
+    assert st["done"] == 48 and st["failed"] == 0
+    assert st["mean_window"] > 1.0 and st["peak_windows_in_flight"] > 1
+    for r in reqs:
+        got = {k: v.cpu().numpy() for k, v in r.result.items()}
+        ex1 = GpuExecutor([grids[r.grid]], [1])
+        s1 = Server(ex1, budget_bytes=1 << 30)
+        s1.submit(0, r.seed)
+        while not s1.idle():
+            s1.step()
+        alone = ex1.fetch(0, 0)
+        for key in got:
+            np.testing.assert_array_equal(np.atleast_1d(got[key]), np.atleast_1d(alone[key]),
+                                          err_msg=f"request {r.rid} {key}")

@@ -284,3 +284,21 @@ def test_kept_results_are_done_only_after_their_copies():
     drive(srv, clock)
     assert c.status == "done" and c.result == {"f": 5.0}
     assert srv.idle()
+
+
+def test_stats_break_latency_into_parts():
+    """queue + launch + complete = latency for every request; the parts and
+    the peak of windows in flight are reported."""
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    s = Server(ex, max_window=3, clock=clk)
+    for i in range(30):
+        s.submit(i % 2, i)
+    drive(s, clk)
+    for r in s.requests:
+        parts = (r.t_launch - r.t_arrive) + (r.t_issued - r.t_launch) + (r.t_done - r.t_issued)
+        assert abs(parts - r.latency) < 1e-12
+    st = s.stats(clk.t)
+    assert set(st["parts"]) == {"queue", "launch", "complete"}
+    assert st["peak_windows_in_flight"] >= 2  # both grids' windows run together
+    assert st["mean_window"] > 1.0            # a burst is taken in windows of several
