@@ -1,7 +1,8 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
-    python -m paper_2203_10587_amd.profiling stats DIR OUT.md --cmd "..."
-        kernel-trace --stats run: per-kernel calls and durations.
+    python -m paper_2203_10587_amd.profiling stats DIR OUT.md --cmd "..." [--by-grid]
+        kernel-trace --stats run: per-kernel calls and durations (per kernel
+        and launch size with --by-grid).
     python -m paper_2203_10587_amd.profiling counters DIR [DIR ...] --out OUT.md --cmd "..."
         occupancy, stall and L2 counters per kernel (one DIR per counter set).
     python -m paper_2203_10587_amd.profiling traffic --workload NAME \
@@ -128,7 +129,37 @@ def _medians(d: str) -> dict:
     return out
 
 
+def _by_grid(d: str):
+    """Per (kernel, grid size) from the kernel trace: calls, mean, median,
+    min, max in ns (one kernel template can serve launches of different
+    sizes: a schedule's persistent grid, another formulation's batch)."""
+    per = defaultdict(list)
+    for r in _csv(d, "kernel_trace.csv"):
+        g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        per[(r["Kernel_Name"], g)].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out = []
+    for (name, g), v in per.items():
+        v.sort()
+        out.append((name, g, len(v), sum(v) / len(v), v[len(v) // 2], v[0], v[-1]))
+    out.sort(key=lambda t: -t[2] * t[3])
+    return out
+
+
 def cmd_stats(args):
+    if args.by_grid:
+        lines = [f"# {args.title}", "", "Command:", "", "```", args.cmd, "```", "",
+                 "Per kernel and launch size (workgroups x threads), from the kernel trace:", "",
+                 "| kernel | grid | calls | avg us | median us | min us | max us |",
+                 "|---|---|---|---|---|---|---|"]
+        for name, g, n, avg, med, mn, mx in _by_grid(args.dir):
+            if args.kernel and args.kernel not in name:
+                continue
+            lines.append(f"| `{_short(name)}` | {g} | {n} | {avg / 1e3:.1f} | {med / 1e3:.1f} | "
+                         f"{mn / 1e3:.1f} | {mx / 1e3:.1f} |")
+        with open(args.out, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        return
     rows = _csv(args.dir, "kernel_stats.csv")
     med = _medians(args.dir)
     lines = [f"# {args.title}", "", "Command:", "", "```", args.cmd, "```", "",
@@ -274,6 +305,9 @@ def main():
     s.add_argument("out")
     s.add_argument("--cmd", required=True)
     s.add_argument("--title", default="rocprofv3 kernel trace")
+    s.add_argument("--by-grid", action="store_true",
+                   help="one row per kernel and launch size, from the kernel trace")
+    s.add_argument("--kernel", default="", help="name fragment of the kernels to list")
     t = sub.add_parser("traffic")
     t.add_argument("--workload", required=True)
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
