@@ -286,7 +286,8 @@ def load_traffic(kernel_name, workload):
         return None
 
 
-def served(seconds: float, rate: float = 2000.0, budget_gb: float = 8.0, log_progress=True):
+def served(seconds: float, rate: float = 2000.0, budget_gb: float = 8.0, log_progress=True,
+           gc_off: bool = False):
     """The served workload: four resident grids (1k/10k/30k/70k buses),
     open-loop Poisson arrivals, grid chosen uniformly per request, iterate
     drawn on the device from the request seed; continuous batching with
@@ -306,7 +307,7 @@ def served(seconds: float, rate: float = 2000.0, budget_gb: float = 8.0, log_pro
     torch.cuda.synchronize()
     tr = poisson_trace(rate, seconds, 4, seed=1)
     prog = (lambda i, n: log(f"[serve] {i}/{n} arrivals")) if log_progress else None
-    st = srv.run_trace(tr, progress=prog, time_limit_s=seconds * 3 + 30)
+    st = srv.run_trace(tr, progress=prog, time_limit_s=seconds * 3 + 30, gc_off=gc_off)
     st["grids_buses"] = [g.nbus for g in grids]
     st["offered_rate_rps"] = rate
     st["budget_bytes"] = int(budget_gb * (1 << 30))
@@ -524,6 +525,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the served Poisson trace (the served workload is 60 s)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-gc-on", dest="serve_gc_off", action="store_false",
+                    help="keep Python's garbage collector running during the served trace (by "
+                         "default it is off there: its generation-2 pauses, up to ~70 ms with "
+                         "120,000 live requests, stall the serving loop)")
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--model", default="polar", choices=list(MODELS),
@@ -576,7 +581,7 @@ def main():
     if args.workload == "served":
         import torch
         torch.cuda.set_device(0)
-        st = served(args.serve_seconds, args.serve_rate)
+        st = served(args.serve_seconds, args.serve_rate, gc_off=args.serve_gc_off)
         out = {"metric": METRIC, "value": st["bus_evals_per_s"], "unit": "bus-evals/s", "n_gpus": 1,
                "steps": st["done"], "warmup": 4, "ms_per_step": 1e3 / max(st["throughput_rps"], 1e-9),
                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -769,7 +774,7 @@ def main():
     if args.serve_seconds > 0:
         log(f"[bench] served workload: {args.serve_seconds:.0f} s of Poisson arrivals at "
             f"{args.serve_rate:.0f}/s")
-        serving = served(args.serve_seconds, args.serve_rate)
+        serving = served(args.serve_seconds, args.serve_rate, gc_off=args.serve_gc_off)
         log(f"[bench] served: {serving['done']} requests, p50 {serving['p50_ms']:.3f} ms, "
             f"p99 {serving['p99_ms']:.3f} ms")
 

@@ -137,6 +137,9 @@ class _Pool:
             self.occ[s] = False
 
 
+STALL_S = 0.5e-3  # a gap between two passes of the serving loop longer than this is a stall
+
+
 class Server:
     def __init__(self, executor: Executor, budget_bytes: int = 8 << 30, max_window: int = 64,
                  timeout_s: float = 10.0, clock: Callable[[], float] = time.perf_counter,
@@ -281,25 +284,66 @@ class Server:
 
     # -- open-loop driver -------------------------------------------------------
     def run_trace(self, arrivals: Sequence[tuple], progress: Optional[Callable] = None,
-                  time_limit_s: float = 600.0) -> Dict:
+                  time_limit_s: float = 600.0, gc_off: bool = False) -> Dict:
         """arrivals: (t_offset_s, grid, seed) sorted by time; requests enter at
-        their scheduled time and latency runs from that time (open loop)."""
+        their scheduled time and latency runs from that time (open loop).
+        Records every gap of more than STALL_S between two passes of the loop
+        (a stall: nothing is admitted or retired meanwhile) and every pause of
+        Python's garbage collector; with gc_off the collector is disabled for
+        the trace."""
+        import gc
         t0 = self.clock()
         i = 0
         last_report = t0
-        while i < len(arrivals) or not self.idle():
-            now = self.clock()
-            while i < len(arrivals) and t0 + arrivals[i][0] <= now:
-                t, g, s = arrivals[i]
-                self.submit(g, s, t_arrive=t0 + t)
-                i += 1
-            self.step()
-            if progress and now - last_report > 5.0:
-                progress(i, len(arrivals))
-                last_report = now
-            if now - t0 > time_limit_s:
-                break
-        return self.stats(self.clock() - t0)
+        stalls = []      # (start, length) of gaps between loop passes, s
+        gc_pauses = []   # (start, length) of garbage collections, s
+        gc_t = [0.0]
+
+        def on_gc(phase, info):
+            if phase == "start":
+                gc_t[0] = time.perf_counter()
+            else:
+                gc_pauses.append((gc_t[0] - t0, time.perf_counter() - gc_t[0]))
+
+        was_enabled = gc.isenabled()
+        if gc_off:
+            gc.collect()
+            gc.freeze()  # what exists now is never traversed again
+            gc.disable()
+        gc.callbacks.append(on_gc)
+        try:
+            prev = t0
+            while i < len(arrivals) or not self.idle():
+                now = self.clock()
+                if now - prev > STALL_S:
+                    stalls.append((prev - t0, now - prev))
+                prev = now
+                while i < len(arrivals) and t0 + arrivals[i][0] <= now:
+                    t, g, s = arrivals[i]
+                    self.submit(g, s, t_arrive=t0 + t)
+                    i += 1
+                self.step()
+                if progress and now - last_report > 5.0:
+                    progress(i, len(arrivals))
+                    last_report = now
+                if now - t0 > time_limit_s:
+                    break
+        finally:
+            gc.callbacks.remove(on_gc)
+            if gc_off:
+                gc.unfreeze()
+                if was_enabled:
+                    gc.enable()
+        st = self.stats(self.clock() - t0)
+        in_gc = sum(any(gs < s0 + sl and s0 < gs + gl for gs, gl in gc_pauses) for s0, sl in stalls)
+        st["stalls"] = {"threshold_ms": STALL_S * 1e3, "count": len(stalls),
+                        "max_ms": max((sl for _, sl in stalls), default=0.0) * 1e3,
+                        "total_ms": sum(sl for _, sl in stalls) * 1e3,
+                        "overlapping_gc": in_gc,
+                        "gc_pauses": len(gc_pauses),
+                        "gc_max_ms": max((gl for _, gl in gc_pauses), default=0.0) * 1e3,
+                        "gc_off": bool(gc_off)}
+        return st
 
     def stats(self, wall_s: float) -> Dict:
         import numpy as np

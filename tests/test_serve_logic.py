@@ -302,3 +302,30 @@ def test_stats_break_latency_into_parts():
     assert set(st["parts"]) == {"queue", "launch", "complete"}
     assert st["peak_windows_in_flight"] >= 2  # both grids' windows run together
     assert st["mean_window"] > 1.0            # a burst is taken in windows of several
+
+
+def test_run_trace_reports_stalls():
+    """A pass of the serving loop that takes longer than the stall threshold
+    is reported, with its length; the collector can be switched off for the
+    trace and is restored afterwards."""
+    import gc
+    from paper_2203_10587_amd import serve as SV
+
+    class SlowClock(Clock):
+        def __call__(self):
+            self.t += 1e-4          # every reading advances the clock a little
+            if abs(self.t - 0.01) < 5e-5:
+                self.t += 0.004     # one 4 ms gap
+            return self.t
+
+    clk = SlowClock()
+    ex = FakeExecutor(clk)
+    s = Server(ex, clock=clk)
+    tr = [(0.002 * k, k % 2, k) for k in range(20)]
+    was = gc.isenabled()
+    st = s.run_trace(tr, gc_off=True)
+    assert gc.isenabled() == was
+    assert st["done"] == 20
+    assert st["stalls"]["count"] >= 1 and st["stalls"]["max_ms"] >= 4.0
+    assert st["stalls"]["gc_off"] is True and st["stalls"]["gc_pauses"] == 0
+    assert SV.STALL_S * 1e3 == st["stalls"]["threshold_ms"]
