@@ -619,7 +619,7 @@ def main():
         outs = [torch.empty(n, dtype=torch.float64, device=dev)
                 for n in (K, nx_, nc_, int(bx.j_off[-1]), int(bx.h_off[-1]))]
         bx.close()
-        best = tune.autotune(nets, xt.to(dev), ts.to(dev), lt.to(dev), outs, reps=20)
+        best = tune.autotune(nets, xt.to(dev), ts.to(dev), lt.to(dev), outs, reps=20, progress=log)
         print(json.dumps({"autotune": best, "bucket": tune.bucket(nets),
                           "cache": tune.cache_path()}), flush=True)
         return

@@ -1,9 +1,10 @@
 """Autotuner for the batched schedule.
 
-A schedule is (tile_be, grid_mult, xcd_group): branch ends per bus tile
-(64/128/256, which also fixes the workgroup size and the LDS footprint),
-the persistent grid in workgroups per CU (0 = one workgroup per tile), and
-whether each instance's tiles are pinned to one XCD.  The tuner times every
+A schedule is (tile_be, grid_mult, xcd_group, no_graph): branch ends per
+bus tile (64/128/256/512, which also fixes the workgroup size and the LDS
+footprint), the persistent grid in workgroups per CU (0 = one workgroup per
+tile), whether each instance's tiles are pinned to one XCD, and whether the
+batch is launched directly or replayed from a HIP graph.  The tuner times every
 candidate on the caller's own batch with HIP events and caches the winner
 in a JSON file keyed by GPU architecture and a size bucket of the batch.
 Every schedule gives bitwise identical results (sums have fixed owners and
@@ -70,7 +71,8 @@ def store(nets: Sequence, sched: Dict, timings: List) -> None:
 
 
 def autotune(nets: Sequence, x, sigma, lam, outs, what=None, reps: int = 10,
-             candidates: Sequence[Dict] = CANDIDATES, save: bool = True) -> Dict:
+             candidates: Sequence[Dict] = CANDIDATES, save: bool = True,
+             progress=None) -> Dict:
     """Time every candidate schedule on this batch (outputs `outs` =
     (f, grad_f, c, jac, hess) packed for the batch) and return the fastest."""
     import torch
@@ -95,6 +97,8 @@ def autotune(nets: Sequence, x, sigma, lam, outs, what=None, reps: int = 10,
         ms = s.elapsed_time(e) / reps
         results.append((ms, cand))
         b.close()
+        if progress:
+            progress(f"[tune] {cand}: {ms:.4f} ms")
     if not results:
         raise RuntimeError("no schedule fits this batch")
     results.sort(key=lambda r: r[0])
