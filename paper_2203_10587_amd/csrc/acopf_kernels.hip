@@ -1079,12 +1079,13 @@ __device__ void prod_tile(const Bufs& B, const InstOff& I0, const InstOff& I1, c
     const uint32_t sf = wi.slots & 0xFFFFu, st = wi.slots >> 16;
     BranchY y{};
     if (l >= 0) y = N.br_y[l];
-    // every instance's inputs first
+    // each instance's inputs are gathered just before its arithmetic:
+    // gathering both instances' first holds both sets in registers, which
+    // costs a wave per SIMD and measured slower in every product
     bool live[NI];
     int lp[NI];
     double gx[NI][4], gm[NI][6], gd[NI][4];
-#pragma unroll
-    for (int ii = 0; ii < NI; ++ii) {
+    auto gather = [&](int ii) {
       live[ii] = l >= 0 && l != ol[ii];
       lp[ii] = live[ii] ? l - after_outage(l, ol[ii]) : 0;
 #pragma unroll
@@ -1114,9 +1115,10 @@ __device__ void prod_tile(const Bufs& B, const InstOff& I0, const InstOff& I1, c
           gd[ii][3] = d[nb + t];
         }
       }
-    }
+    };
 #pragma unroll
     for (int ii = 0; ii < NI; ++ii) {
+      gather(ii);
       double* rec = smem + ii * (R::N * BE);
       if (l >= 0 && !live[ii]) {  // removed branch: its ends keep their places and add zero
 #pragma unroll
@@ -1488,11 +1490,10 @@ __global__ __launch_bounds__(256) void k_fsum(const InstOff* __restrict__ table,
 
 // The products' kernel: bus tiles of one or two instances (prod_tile) and
 // generator tiles, at the waves per SIMD their registers allow without
-// spilling: three for the HVP and the polar JVP, four otherwise.
+// spilling: three for the HVP, four otherwise.
 template <unsigned WHAT>
 struct ProdWaves {
-  static constexpr int value =
-      ((WHAT & W_HVP) != 0 || ((WHAT & W_JVP) != 0 && (WHAT & W_CART) == 0)) ? 3 : 4;
+  static constexpr int value = (WHAT & W_HVP) != 0 ? 3 : 4;
 };
 
 template <unsigned WHAT, int WG, int BE>
