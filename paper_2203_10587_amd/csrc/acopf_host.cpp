@@ -422,7 +422,8 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
         for (int q = 0; q < pad; ++q) {
           WorkItem d{};
           d.l = -2;
-          d.jlo = d.hvlo = d.jhi = d.hvhi = d.hthi = -1;
+          d.j = d.hv = kNoPos | (kNoPos << 16);
+          d.th = kNoPos;
           d.slots = kNoSlot | (kNoSlot << 16);
           S->work.push_back(d);
         }
@@ -438,21 +439,24 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
         const uint32_t sf = in_tile(f) ? uint32_t(pos_from[l] - e0) : kNoSlot;
         const uint32_t st = in_tile(t) ? uint32_t(pos_to[l] - e0) : kNoSlot;
         w.slots = sf | (st << 16);
-        w.grp = (m == k) ? g : 0;
-        w.jlo = w.hvlo = w.jhi = w.hvhi = w.hthi = -1;
-        w.alo = T.acnt[lo].x;
-        w.ahi = T.acnt[hi].x;
+        // positions relative to the tile's segments (J P rows from r0.x,
+        // H theta rows from r0.z, H v rows from r0.w)
+        uint32_t jlo = kNoPos, hvlo = kNoPos, jhi = kNoPos, hvhi = kNoPos, hthi = kNoPos;
         if (in_tile(lo)) {
           const int r = rank_in(T, lo, hi);
-          w.jlo = T.rows[lo].x + r;
-          w.hvlo = T.rows[lo].w + r;
+          jlo = uint32_t(T.rows[lo].x + r - r0.x);
+          hvlo = uint32_t(T.rows[lo].w + r - r0.w);
         }
         if (in_tile(hi)) {
           const int r = rank_in(T, hi, lo);
-          w.jhi = T.rows[hi].x + r;
-          w.hvhi = T.rows[hi].w + r;
-          w.hthi = T.rows[hi].z + r;
+          jhi = uint32_t(T.rows[hi].x + r - r0.x);
+          hvhi = uint32_t(T.rows[hi].w + r - r0.w);
+          hthi = uint32_t(T.rows[hi].z + r - r0.z);
         }
+        w.j = jlo | (jhi << 16);
+        w.hv = hvlo | (hvhi << 16);
+        w.th = hthi | (uint32_t((m == k) ? g : 0) << 16);
+        w.a = uint32_t(T.acnt[lo].x) | (uint32_t(T.acnt[hi].x) << 16);
         S->work.push_back(w);
       }
       k = k1;
@@ -461,14 +465,16 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
     // the J segments and the H segments are staged one after the other
     bool ok = e1 - e0 <= caps.be && b1 - b0 <= caps.nbus && 2 * (r1.x - r0.x) <= caps.stage &&
               (r1.z - r0.z) + (r1.w - r0.w) <= caps.stage;
+    // (and fit the 16-bit relative encoding)
+    ok = ok && r1.x - r0.x < int(kNoPos) && r1.z - r0.z < int(kNoPos) && r1.w - r0.w < int(kNoPos);
     for (size_t k = w0; ok && k < S->work.size(); ++k) {
       const WorkItem& w = S->work[k];
       if (w.l < 0) continue;
-      if (w.jlo >= 0)
-        ok = ok && w.jlo >= r0.x && w.jlo + w.alo < r1.x && w.hvlo >= r0.w && w.hvlo < r1.w;
-      if (w.jhi >= 0)
-        ok = ok && w.jhi >= r0.x && w.jhi + w.ahi < r1.x && w.hvhi >= r0.w &&
-             w.hvhi + w.ahi < r1.w && w.hthi >= r0.z && w.hthi < r1.z;
+      if (w.jlo() != kNoPos)
+        ok = ok && int(w.jlo() + w.alo()) < r1.x - r0.x && int(w.hvlo()) < r1.w - r0.w;
+      if (w.jhi() != kNoPos)
+        ok = ok && int(w.jhi() + w.ahi()) < r1.x - r0.x && int(w.hvhi() + w.ahi()) < r1.w - r0.w &&
+             int(w.hthi()) < r1.z - r0.z;
     }
     if (!ok) {
       tiler_error = true;

@@ -51,26 +51,38 @@ struct Tile {
   int32_t inst2 = -1;
 };
 
-// One branch evaluated by a bus tile.  l < 0 pads the list so that no
-// parallel-branch group straddles two waves.  slots = slot_from |
-// slot_to << 16: the tile-local branch-end records of the two ends
-// (kNoSlot if that end's bus is outside the tile).  With lo < hi the end
-// buses, the base positions this tile stores (-1 where the end's bus is
-// outside the tile), Q rows at +qoff from the P rows:
-//   jlo  J (P_lo, theta_hi); (P_lo, v_hi) at jlo + alo
-//   hvlo H (v_lo, theta_hi)
-//   jhi  J (P_hi, theta_lo); (P_hi, v_lo) at jhi + ahi
-//   hvhi H (v_hi, theta_lo); (v_hi, v_lo) at hvhi + ahi
-//   hthi H (theta_hi, theta_lo)
+// One branch evaluated by a bus tile, in 32 bytes.  l < 0 pads the list so
+// that no parallel-branch group straddles two waves.  slots = slot_from |
+// slot_to << 16: the tile-local branch-end records of the two ends (kNoSlot
+// if that end's bus is outside the tile).  With lo < hi the end buses, the
+// positions this tile stores, relative to the start of the tile's row
+// segment of the same kind (kNoPos where the end's bus is outside the tile;
+// Q rows at the same offsets in the Q segment):
+//   jlo  J (P_lo, theta_hi); (P_lo, v_hi) at jlo + alo   (J P rows)
+//   hvlo H (v_lo, theta_hi)                              (H v rows)
+//   jhi  J (P_hi, theta_lo); (P_hi, v_lo) at jhi + ahi   (J P rows)
+//   hvhi H (v_hi, theta_lo); (v_hi, v_lo) at hvhi + ahi  (H v rows)
+//   hthi H (theta_hi, theta_lo)                          (H theta rows)
 // a_e = |{e} u N(e)|, the length of the theta part of bus e's rows.
 // grp: for the first branch of a group of parallel branches, the group size
 // (1 for a branch without a twin); 0 for the other members, which follow in
 // the next lanes.
+constexpr uint32_t kNoPos = 0xFFFFu;
 struct WorkItem {
   int32_t l, f, t;
   uint32_t slots;
-  int32_t jlo, hvlo, alo, grp;
-  int32_t jhi, hvhi, hthi, ahi;
+  uint32_t j;    // jlo | jhi << 16
+  uint32_t hv;   // hvlo | hvhi << 16
+  uint32_t th;   // hthi | grp << 16
+  uint32_t a;    // alo | ahi << 16
+  __host__ __device__ uint32_t jlo() const { return j & 0xFFFFu; }
+  __host__ __device__ uint32_t jhi() const { return j >> 16; }
+  __host__ __device__ uint32_t hvlo() const { return hv & 0xFFFFu; }
+  __host__ __device__ uint32_t hvhi() const { return hv >> 16; }
+  __host__ __device__ uint32_t hthi() const { return th & 0xFFFFu; }
+  __host__ __device__ int grp() const { return int((th >> 16) & 0xFFu); }
+  __host__ __device__ uint32_t alo() const { return a & 0xFFFFu; }
+  __host__ __device__ uint32_t ahi() const { return a >> 16; }
 };
 
 // Feasibility slack blocks of a network (at most 6: dP+, dP-, dQ+, dQ-, Pl,

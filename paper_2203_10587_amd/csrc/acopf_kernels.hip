@@ -457,19 +457,22 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
 #pragma unroll
           for (int q = 0; q < 8; ++q) jv[q] = 0.0;
         }
-        if (gmax > 1) group_sum(jv, wi.grp, gmax);
-        if (wi.grp > 0) {
-          if (wi.jlo >= 0) {
-            stg[sP + wi.jlo] = jv[0];
-            stg[sP + wi.jlo + wi.alo] = jv[1];
-            stg[sQ + wi.jlo] = jv[2];
-            stg[sQ + wi.jlo + wi.alo] = jv[3];
+        if (gmax > 1) group_sum(jv, wi.grp(), gmax);
+        if (wi.grp() > 0) {
+          const uint32_t jlo = wi.jlo(), jhi = wi.jhi();
+          if (jlo != kNoPos) {
+            const int alo = int(wi.alo());
+            stg[jlo] = jv[0];
+            stg[jlo + alo] = jv[1];
+            stg[T.nP + jlo] = jv[2];
+            stg[T.nP + jlo + alo] = jv[3];
           }
-          if (wi.jhi >= 0) {
-            stg[sP + wi.jhi] = jv[4];
-            stg[sP + wi.jhi + wi.ahi] = jv[5];
-            stg[sQ + wi.jhi] = jv[6];
-            stg[sQ + wi.jhi + wi.ahi] = jv[7];
+          if (jhi != kNoPos) {
+            const int ahi = int(wi.ahi());
+            stg[jhi] = jv[4];
+            stg[jhi + ahi] = jv[5];
+            stg[T.nP + jhi] = jv[6];
+            stg[T.nP + jhi + ahi] = jv[7];
           }
         }
       }
@@ -555,13 +558,14 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
           }
         }
         if constexpr (pH) {
-          if (gmax > 1) group_sum(hv4, wi.grp, gmax);
-          if (wi.grp > 0) {
-            if (wi.jlo >= 0) stg[sV + wi.hvlo] = hv4[1];
-            if (wi.jhi >= 0) {
-              stg[sT + wi.hthi] = hv4[0];
-              stg[sV + wi.hvhi] = hv4[2];
-              stg[sV + wi.hvhi + wi.ahi] = hv4[3];
+          if (gmax > 1) group_sum(hv4, wi.grp(), gmax);
+          if (wi.grp() > 0) {
+            const int v0 = h0 + T.nT;  // the H v rows follow the theta rows
+            if (wi.jlo() != kNoPos) stg[v0 + wi.hvlo()] = hv4[1];
+            if (wi.jhi() != kNoPos) {
+              stg[h0 + wi.hthi()] = hv4[0];
+              stg[v0 + wi.hvhi()] = hv4[2];
+              stg[v0 + wi.hvhi() + wi.ahi()] = hv4[3];
             }
           }
         }
@@ -673,19 +677,22 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
   #pragma unroll
           for (int q = 0; q < 8; ++q) jv[q] = 0.0;
         }
-        if (gmax > 1) group_sum(jv, wi.grp, gmax);
-        if (wi.grp > 0) {  // (entries of a removed branch without a twin are never stored)
-          if (wi.jlo >= 0) {
-            stg[sP + wi.jlo] = jv[0];
-            stg[sP + wi.jlo + wi.alo] = jv[1];
-            stg[sQ + wi.jlo] = jv[2];
-            stg[sQ + wi.jlo + wi.alo] = jv[3];
+        if (gmax > 1) group_sum(jv, wi.grp(), gmax);
+        if (wi.grp() > 0) {  // (entries of a removed branch without a twin are never stored)
+          const uint32_t jlo = wi.jlo(), jhi = wi.jhi();
+          if (jlo != kNoPos) {
+            const int alo = int(wi.alo());
+            stg[jlo] = jv[0];
+            stg[jlo + alo] = jv[1];
+            stg[T.nP + jlo] = jv[2];
+            stg[T.nP + jlo + alo] = jv[3];
           }
-          if (wi.jhi >= 0) {
-            stg[sP + wi.jhi] = jv[4];
-            stg[sP + wi.jhi + wi.ahi] = jv[5];
-            stg[sQ + wi.jhi] = jv[6];
-            stg[sQ + wi.jhi + wi.ahi] = jv[7];
+          if (jhi != kNoPos) {
+            const int ahi = int(wi.ahi());
+            stg[jhi] = jv[4];
+            stg[jhi + ahi] = jv[5];
+            stg[T.nP + jhi] = jv[6];
+            stg[T.nP + jhi + ahi] = jv[7];
           }
         }
       }
@@ -770,13 +777,14 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
           }
         }
         if constexpr (pH) {
-          if (gmax > 1) group_sum(hv4, wi.grp, gmax);
-          if (wi.grp > 0) {
-            if (wi.jlo >= 0) stg[sV + wi.hvlo] = hv4[1];
-            if (wi.jhi >= 0) {
-              stg[sT + wi.hthi] = hv4[0];
-              stg[sV + wi.hvhi] = hv4[2];
-              stg[sV + wi.hvhi + wi.ahi] = hv4[3];
+          if (gmax > 1) group_sum(hv4, wi.grp(), gmax);
+          if (wi.grp() > 0) {
+            const int v0 = h0 + T.nT;  // the H v rows follow the theta rows
+            if (wi.jlo() != kNoPos) stg[v0 + wi.hvlo()] = hv4[1];
+            if (wi.jhi() != kNoPos) {
+              stg[h0 + wi.hthi()] = hv4[0];
+              stg[v0 + wi.hvhi()] = hv4[2];
+              stg[v0 + wi.hvhi() + wi.ahi()] = hv4[3];
             }
           }
         }

@@ -31,13 +31,22 @@ extern "C" int tile_check(const acopf_net_desc* d, int tile_be, unsigned slacks)
   for (int ti = 0; ti < S.counts[0]; ++ti) {
     const Tile& tl = S.tiles[ti];
     for (int k = 0; k < tl.nw; ++k) {
-      const WorkItem& w = S.work[tl.w0 + k];
-      if (w.l < 0) continue;
+      const WorkItem& wi = S.work[tl.w0 + k];
+      if (wi.l < 0) continue;
+      // absolute base positions from the tile-relative encoding
+      struct {
+        int l, f, t, grp, alo, ahi, jlo, jhi, hvlo, hvhi, hthi;
+      } w{wi.l, wi.f, wi.t, wi.grp(), int(wi.alo()), int(wi.ahi()),
+          wi.jlo() == kNoPos ? -1 : tl.jP0 + int(wi.jlo()),
+          wi.jhi() == kNoPos ? -1 : tl.jP0 + int(wi.jhi()),
+          wi.jlo() == kNoPos ? -1 : tl.hV0 + int(wi.hvlo()),
+          wi.jhi() == kNoPos ? -1 : tl.hV0 + int(wi.hvhi()),
+          wi.jhi() == kNoPos ? -1 : tl.hT0 + int(wi.hthi())};
       if (w.grp > 1) {  // members follow, same lo/hi, same wave
         chk(k / 64 == (k + w.grp - 1) / 64, "group straddles a wave", ti, k);
         for (int m = 1; m < w.grp; ++m) {
           const WorkItem& o = S.work[tl.w0 + k + m];
-          chk(o.grp == 0 && std::min(o.f, o.t) == std::min(w.f, w.t) &&
+          chk(o.grp() == 0 && std::min(o.f, o.t) == std::min(w.f, w.t) &&
                   std::max(o.f, o.t) == std::max(w.f, w.t) && o.l > w.l,
               "group member", ti, k + m);
         }
