@@ -48,8 +48,10 @@ struct acopf_batch_s {
   int ntiles = 0;
   int grid = 0;  // 0: one workgroup per tile
   acopf::Tile* d_tiles_inst = nullptr;  // the same tiles, instance after instance
-  acopf::Tile* d_ptiles = nullptr;      // product tiles: instances of one base in pairs
-  int nptiles = 0;
+  // product tiles: instances of one base in groups of kProdInst ([0]) or
+  // of two ([1]), as prod_group() gives per product
+  acopf::Tile* d_ptiles[2] = {nullptr, nullptr};
+  int nptiles[2] = {0, 0};
   acopf::WorkItem* d_work = nullptr;    // work items of every distinct base, back to back
   std::vector<int32_t> inst_tile_off;   // count + 1
   int max_len = 0;                      // max n + m over instances
@@ -144,14 +146,15 @@ unsigned variant_of(unsigned what) {
 bool is_product(unsigned variant) { return (variant & (W_VJP | W_HVP | W_JVP)) != 0; }
 
 // The evaluation kernel, then (if f is wanted) the f reduction.  The
-// products walk their own tile list, whose bus tiles serve two instances of
-// one base network at a time.
+// products walk their own tile lists, whose bus tiles serve several
+// instances of one base network at a time.
 hipError_t enqueue(acopf_batch_s* b, unsigned variant, const Bufs& bufs, hipStream_t s) {
   InstOff none{};
   none.work = b->d_work;  // the tiles' w0 index this array
   const bool prod = is_product(variant);
-  const Tile* tiles = prod ? b->d_ptiles : b->d_tiles;
-  const int nt = prod ? b->nptiles : b->ntiles;
+  const int pl = prod_group(variant) == kProdInst ? 0 : 1;
+  const Tile* tiles = prod ? b->d_ptiles[pl] : b->d_tiles;
+  const int nt = prod ? b->nptiles[pl] : b->ntiles;
   const int grid = b->grid > 0 ? std::min(b->grid, nt) : 0;
   hipError_t e = launch_eval(variant, b->sched.tile_be, bufs, b->d_table, none, tiles, nt, grid, s);
   // a single-chunk instance has its f written by its generator tile
@@ -335,53 +338,59 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     };
     std::vector<Tile> tiles = interleave(queue);
     b->ntiles = int(tiles.size());
-    // product tiles: the instances of each base network in pairs (instance
-    // order), a pair's bus tiles once with both instances, each instance's
-    // generator tiles on their own; pairs spread over the XCD queues
-    // largest-first like the instances above
-    std::vector<Tile> ptiles;
-    {
-      std::map<const Base*, std::vector<int>> by_base;
-      std::vector<const Base*> base_order;
-      for (int k = 0; k < count; ++k) {
-        const Base* B = nets[k]->base.get();
-        if (!by_base.count(B)) base_order.push_back(B);
-        by_base[B].push_back(k);
-      }
-      std::vector<std::pair<int, int>> units;
+    // product tiles: the instances of each base network in groups of up to
+    // `group` (instance order), a group's bus tiles once with all of its
+    // instances, each instance's generator tiles on their own; groups spread
+    // over the XCD queues largest-first like the instances above
+    std::map<const Base*, std::vector<int>> by_base;
+    std::vector<const Base*> base_order;
+    for (int k = 0; k < count; ++k) {
+      const Base* B = nets[k]->base.get();
+      if (!by_base.count(B)) base_order.push_back(B);
+      by_base[B].push_back(k);
+    }
+    auto product_tiles = [&](int group) {
+      struct Unit {
+        int inst[kProdInst];
+        int n;
+      };
+      std::vector<Unit> units;
       for (const Base* B : base_order) {
         const std::vector<int>& ks = by_base[B];
-        for (size_t j = 0; j < ks.size(); j += 2)
-          units.emplace_back(ks[j], j + 1 < ks.size() ? ks[j + 1] : -1);
+        for (size_t j = 0; j < ks.size(); j += group) {
+          Unit u{};
+          u.n = int(std::min<size_t>(group, ks.size() - j));
+          for (int q = 0; q < kProdInst; ++q) u.inst[q] = q < u.n ? ks[j + q] : -1;
+          units.push_back(u);
+        }
       }
-      std::stable_sort(units.begin(), units.end(), [&](const std::pair<int, int>& a,
-                                                       const std::pair<int, int>& c) {
-        return ntile(a.first) > ntile(c.first);
+      std::stable_sort(units.begin(), units.end(), [&](const Unit& a, const Unit& c) {
+        return ntile(a.inst[0]) > ntile(c.inst[0]);
       });
       std::vector<std::vector<Tile>> pq(s.xcd_group ? kXcds : 1);
       std::vector<int64_t> pload(pq.size(), 0);
-      for (const auto& u : units) {
+      for (const Unit& u : units) {
         const size_t qi = std::min_element(pload.begin(), pload.end()) - pload.begin();
-        const PerBase& pb = per_base[nets[u.first]->base.get()];
+        const PerBase& pb = per_base[nets[u.inst[0]]->base.get()];
         for (Tile t : pb.sch.tiles) {
-          t.inst = u.first;
+          t.inst = u.inst[0];
           t.w0 += int32_t(pb.work_off);
           if ((t.kind_aux & 3) == TILE_BUS) {
-            t.inst2 = u.second;
+            for (int q = 1; q < kProdInst; ++q) t.more[q - 1] = u.inst[q];
             pq[qi].push_back(t);
           } else {
-            pq[qi].push_back(t);
-            if (u.second >= 0) {
-              t.inst = u.second;
+            for (int q = 0; q < u.n; ++q) {
+              t.inst = u.inst[q];
               pq[qi].push_back(t);
             }
           }
         }
-        pload[qi] += ntile(u.first);
+        pload[qi] += ntile(u.inst[0]);
       }
-      ptiles = interleave(pq);
-    }
-    b->nptiles = int(ptiles.size());
+      return interleave(pq);
+    };
+    const std::vector<Tile> ptiles[2] = {product_tiles(kProdInst), product_tiles(2)};
+    for (int q = 0; q < 2; ++q) b->nptiles[q] = int(ptiles[q].size());
     int cus = 256;
     int rc = cu_count(dev, &cus);
     if (rc) {
@@ -395,8 +404,10 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     const size_t s_tinst = align_up(tiles_inst.size() * sizeof(Tile));
     const size_t s_work = align_up(std::max<size_t>(work_total, 1) * sizeof(WorkItem));
     const size_t s_fpart = align_up(size_t(fpo[count]) * sizeof(double));
-    const size_t s_ptiles = align_up(ptiles.size() * sizeof(Tile));
-    e = hipMalloc(&b->mem, s_table + s_tiles + s_work + s_fpart + s_tinst + s_ptiles);
+    const size_t s_ptiles0 = align_up(ptiles[0].size() * sizeof(Tile));
+    const size_t s_ptiles1 = align_up(ptiles[1].size() * sizeof(Tile));
+    e = hipMalloc(&b->mem,
+                  s_table + s_tiles + s_work + s_fpart + s_tinst + s_ptiles0 + s_ptiles1);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       b->mem = nullptr;
@@ -410,7 +421,8 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     b->d_work = d_work;
     b->d_fpart = reinterpret_cast<double*>(base + s_table + s_tiles + s_work);
     b->d_tiles_inst = reinterpret_cast<Tile*>(base + s_table + s_tiles + s_work + s_fpart);
-    b->d_ptiles = reinterpret_cast<Tile*>(base + s_table + s_tiles + s_work + s_fpart + s_tinst);
+    b->d_ptiles[0] = reinterpret_cast<Tile*>(base + s_table + s_tiles + s_work + s_fpart + s_tinst);
+    b->d_ptiles[1] = reinterpret_cast<Tile*>(reinterpret_cast<char*>(b->d_ptiles[0]) + s_ptiles0);
     std::vector<InstOff> table(count);
     for (int k = 0; k < count; ++k) {
       InstOff I = net_inst(nets[k]);
@@ -435,9 +447,10 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     if (e == hipSuccess)
       e = hipMemcpy(b->d_tiles_inst, tiles_inst.data(), tiles_inst.size() * sizeof(Tile),
                     hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-      e = hipMemcpy(b->d_ptiles, ptiles.data(), ptiles.size() * sizeof(Tile),
-                    hipMemcpyHostToDevice);
+    for (int q = 0; q < 2; ++q)
+      if (e == hipSuccess)
+        e = hipMemcpy(b->d_ptiles[q], ptiles[q].data(), ptiles[q].size() * sizeof(Tile),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(b->d_fpart, 0, s_fpart);
     if (e != hipSuccess) {
       free_batch(b);

@@ -43,12 +43,13 @@ enum TileKind : int32_t { TILE_BUS = 1, TILE_GEN = 2 };
 // H v rows [hV0, hV0 + nV).  Gen tile: cost items [a0, a1) (item k >= ng is
 // slack variable k - ng);
 // kind_aux = (chunk << 2) | kind.
-// A product bus tile may serve a second instance of the same base network
-// (inst2; -1 for none).
+// A product bus tile may serve up to kProdInst - 1 further instances of the
+// same base network (more[]; -1 past the last).
+constexpr int kProdInst = 4;
 struct Tile {
   int32_t inst, kind_aux, a0, a1, e0, ne, w0, nw;
   int32_t gmax, nP, nT, nV, jP0, jQ0, hT0, hV0;
-  int32_t inst2 = -1;
+  int32_t more[kProdInst - 1] = {-1, -1, -1};
 };
 
 // One branch evaluated by a bus tile, in 32 bytes.  l < 0 pads the list so
@@ -165,6 +166,13 @@ enum : unsigned {
   W_F = 1u, W_GRADF = 2u, W_C = 4u, W_J = 8u, W_H = 16u, W_VJP = 32u, W_HVP = 64u, W_JVP = 128u,
   W_CART = 256u,  // power-balance-cartesian representation (x = [e; f; Pg; Qg])
 };
+
+// Instances of one base network per product bus tile: kProdInst for the VJP
+// and the HVP; two for the JVP, whose tiles of four need more registers than
+// four waves per SIMD leave (and measured slower than pairs).
+__host__ __device__ constexpr int prod_group(unsigned what) {
+  return (what & W_JVP) != 0 ? 2 : kProdInst;
+}
 
 // Tile capacities of one schedule class (the schedule's tile_be value):
 // workgroup size, branch ends per bus tile (LDS records), buses per bus tile

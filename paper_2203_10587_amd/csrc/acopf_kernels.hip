@@ -223,8 +223,8 @@ struct Rec {
 // stored).
 template <unsigned WHAT, int BE, int STAGE>
 struct Lds {
-  // a product tile may hold the records of two instances
-  static constexpr int kInst = (WHAT & (W_VJP | W_HVP | W_JVP)) != 0 ? 2 : 1;
+  // a product tile may hold the records of up to kProdInst instances
+  static constexpr int kInst = (WHAT & (W_VJP | W_HVP | W_JVP)) != 0 ? prod_group(WHAT) : 1;
   static constexpr int kRec = Rec<WHAT>::N * BE * kInst;
   static constexpr int kStage = (Rec<WHAT>::J || Rec<WHAT>::H) ? STAGE : 0;
   static constexpr int kGen = kGenChunk;
@@ -1041,18 +1041,18 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
 }
 
 // ---------------------------------------------------------------------------
-// product tile: a bus tile of the VJP, HVP or JVP for NI instances that share
-// one base network (an N-1 batch pairs its instances).  The work items, the
-// branch admittances and the bus data are loaded once for all of them; each
-// instance gathers its own x, multipliers and direction (all of them before
-// any arithmetic, so that their loads are in flight together) and keeps its
-// own records.  Per instance the arithmetic and its order are those of a
-// tile of one instance, so results do not depend on the pairing.
+// product tile: a bus tile of the VJP, HVP or JVP for ni <= NI instances
+// that share one base network (an N-1 batch groups its instances).  The work
+// items, the branch admittances and the bus data are loaded once for all of
+// them; each instance gathers its own x, multipliers and direction and keeps
+// its own records.  Per instance the arithmetic and its order are those of a
+// tile of one instance, so results do not depend on the grouping.
 template <unsigned WHAT, int WG, int BE, int NI>
-__device__ void prod_tile(const Bufs& B, const InstOff& I0, const InstOff& I1, const NetDev& N,
-                          const Tile& T, const WorkItem* __restrict__ work, double* smem) {
+__device__ void prod_tile(const Bufs& B, const InstOff* __restrict__ table, const InstOff& I0,
+                          const NetDev& N, const Tile& T, int ni,
+                          const WorkItem* __restrict__ work, double* smem) {
   using R = Rec<WHAT>;
-  static_assert(NI == 1 || NI == 2, "one or two instances per tile");
+  static_assert(NI >= 1 && NI <= kProdInst, "instances per product tile");
   static_assert(!R::C && !R::J && !R::H, "products only");
   constexpr bool CART = (WHAT & W_CART) != 0;
   constexpr bool MUL = R::V || R::HV;   // weights: w_c (VJP) or lambda (HVP)
@@ -1067,7 +1067,8 @@ __device__ void prod_tile(const Bufs& B, const InstOff& I0, const InstOff& I1, c
   int64_t xo[NI], co[NI];
 #pragma unroll
   for (int ii = 0; ii < NI; ++ii) {
-    const InstOff& I = ii ? I1 : I0;
+    if (ii >= ni) break;
+    const InstOff& I = ii ? table[T.more[ii - 1]] : I0;
     ol[ii] = I.out_l;
     nll[ii] = N.nl - (I.out_l >= 0 ? 1 : 0);
     xo[ii] = I.xo;
@@ -1126,6 +1127,7 @@ __device__ void prod_tile(const Bufs& B, const InstOff& I0, const InstOff& I1, c
     };
 #pragma unroll
     for (int ii = 0; ii < NI; ++ii) {
+      if (ii >= ni) break;
       gather(ii);
       double* rec = smem + ii * (R::N * BE);
       if (l >= 0 && !live[ii]) {  // removed branch: its ends keep their places and add zero
@@ -1290,82 +1292,96 @@ __device__ void prod_tile(const Bufs& B, const InstOff& I0, const InstOff& I1, c
     }
   }
 
-  // ---- lane per bus: its own terms, then (after the barrier) its ends'
-  // records summed in adjacency order
+  // ---- lane per bus: its own terms and its ends' records summed in
+  // adjacency order.  The own terms of the first E instances are loaded
+  // before the barrier (their loads overlap the wait), the others' after it,
+  // one instance at a time: a tile of four holds one set across the barrier,
+  // a pair both.
   const bool has_bus = tid < nbus;
   const int i = b0 + tid;
   int ea = 0, eb = 0;
-  double own0[NI], own1[NI], own2[NI];  // per product: the bus's own terms
+  double4 bd{};  // pd, qd, gs, bs
+  auto own_terms = [&](int ii, double& o0, double& o1, double& o2) {
+    o0 = o1 = o2 = 0.0;
+    const double* x = xs[ii];
+    const double vi = x[nb + i];  // v_i, or f_i in the cartesian representation
+    double lvm = 0.0;
+    (void)lvm;
+    double ei = 0.0;
+    (void)ei;
+    if constexpr (CART) {
+      ei = x[i];
+      if constexpr (MUL) lvm = mul[ii][2 * nb + 2 * nll[ii] + i];
+    }
+    if constexpr (R::V) {
+      const double* m = mul[ii];
+      if constexpr (CART) {
+        const double kap = 2.0 * (fma(m[i], bd.z, -(m[nb + i] * bd.w)) + lvm);
+        o0 = kap * ei;   // theta (e) column
+        o1 = kap * vi;   // v (f) column
+      } else {
+        o1 = 2.0 * vi * fma(m[i], bd.z, -(m[nb + i] * bd.w));
+      }
+    }
+    if constexpr (R::HV) {
+      const double* m = mul[ii];
+      const double* d = dir[ii];
+      if constexpr (CART) {
+        const double kap = 2.0 * (fma(m[i], bd.z, -(m[nb + i] * bd.w)) + lvm);
+        o0 = kap * d[i];
+        o1 = kap * d[nb + i];
+      } else {
+        o1 = 2.0 * fma(m[i], bd.z, -(m[nb + i] * bd.w)) * d[nb + i];
+      }
+    }
+    if constexpr (R::JV) {
+      const double* d = dir[ii];
+      double dpg = 0, dqg = 0;
+      for (int g = N.gen_ptr[i], g1 = N.gen_ptr[i + 1]; g < g1; ++g) {
+        const int kk = N.gen_ident ? g : N.gen_list[g];
+        dpg += d[2 * nb + kk];
+        dqg += d[2 * nb + N.ng + kk];
+      }
+      double jvP, jvQ;
+      if constexpr (CART) {  // d|V_i|^2 along the direction
+        const double jvm = 2.0 * fma(ei, d[i], vi * d[nb + i]);
+        o2 = jvm;
+        jvP = bd.z * jvm - dpg;
+        jvQ = -bd.w * jvm - dqg;
+      } else {
+        jvP = 2.0 * bd.z * vi * d[nb + i] - dpg;
+        jvQ = -2.0 * bd.w * vi * d[nb + i] - dqg;
+      }
+      for (int q = 0; q < N.sl.ns; ++q) {
+        const double tt = N.sl.coef[q] * d[2 * nb + 2 * N.ng + q * nb + i];
+        if (N.sl.row[q] == 0) jvP += tt; else jvQ += tt;
+      }
+      o0 = jvP;
+      o1 = jvQ;
+    }
+  };
+  constexpr int E = NI <= 2 ? NI : 1;
+  double f0[NI], f1[NI], f2[NI];  // own terms of the first E instances
 #pragma unroll
-  for (int ii = 0; ii < NI; ++ii) own0[ii] = own1[ii] = own2[ii] = 0.0;
+  for (int ii = 0; ii < NI; ++ii) f0[ii] = f1[ii] = f2[ii] = 0.0;
   if (has_bus) {
     ea = N.be_ptr[i] - e0;
     eb = N.be_ptr[i + 1] - e0;
-    const double4 bd = N.bus[i];  // pd, qd, gs, bs
+    bd = N.bus[i];
 #pragma unroll
-    for (int ii = 0; ii < NI; ++ii) {
-      const double* x = xs[ii];
-      const double vi = x[nb + i];  // v_i, or f_i in the cartesian representation
-      double lvm = 0.0;
-      (void)lvm;
-      double ei = 0.0;
-      (void)ei;
-      if constexpr (CART) {
-        ei = x[i];
-        if constexpr (MUL) lvm = mul[ii][2 * nb + 2 * nll[ii] + i];
-      }
-      if constexpr (R::V) {
-        const double* m = mul[ii];
-        if constexpr (CART) {
-          const double kap = 2.0 * (fma(m[i], bd.z, -(m[nb + i] * bd.w)) + lvm);
-          own0[ii] = kap * ei;   // theta (e) column
-          own1[ii] = kap * vi;   // v (f) column
-        } else {
-          own1[ii] = 2.0 * vi * fma(m[i], bd.z, -(m[nb + i] * bd.w));
-        }
-      }
-      if constexpr (R::HV) {
-        const double* m = mul[ii];
-        const double* d = dir[ii];
-        if constexpr (CART) {
-          const double kap = 2.0 * (fma(m[i], bd.z, -(m[nb + i] * bd.w)) + lvm);
-          own0[ii] = kap * d[i];
-          own1[ii] = kap * d[nb + i];
-        } else {
-          own1[ii] = 2.0 * fma(m[i], bd.z, -(m[nb + i] * bd.w)) * d[nb + i];
-        }
-      }
-      if constexpr (R::JV) {
-        const double* d = dir[ii];
-        double dpg = 0, dqg = 0;
-        for (int g = N.gen_ptr[i], g1 = N.gen_ptr[i + 1]; g < g1; ++g) {
-          const int kk = N.gen_ident ? g : N.gen_list[g];
-          dpg += d[2 * nb + kk];
-          dqg += d[2 * nb + N.ng + kk];
-        }
-        double jvP, jvQ;
-        if constexpr (CART) {  // d|V_i|^2 along the direction
-          const double jvm = 2.0 * fma(ei, d[i], vi * d[nb + i]);
-          own2[ii] = jvm;
-          jvP = bd.z * jvm - dpg;
-          jvQ = -bd.w * jvm - dqg;
-        } else {
-          jvP = 2.0 * bd.z * vi * d[nb + i] - dpg;
-          jvQ = -2.0 * bd.w * vi * d[nb + i] - dqg;
-        }
-        for (int q = 0; q < N.sl.ns; ++q) {
-          const double tt = N.sl.coef[q] * d[2 * nb + 2 * N.ng + q * nb + i];
-          if (N.sl.row[q] == 0) jvP += tt; else jvQ += tt;
-        }
-        own0[ii] = jvP;
-        own1[ii] = jvQ;
-      }
+    for (int ii = 0; ii < E; ++ii) {
+      if (ii >= ni) break;
+      own_terms(ii, f0[ii], f1[ii], f2[ii]);
     }
   }
   __syncthreads();
   if (has_bus) {
 #pragma unroll
     for (int ii = 0; ii < NI; ++ii) {
+      if (ii >= ni) break;
+      double own0 = f0[ii], own1 = f1[ii], own2 = f2[ii];
+      if (ii >= E) own_terms(ii, own0, own1, own2);
+      (void)own2;
       const double* rec = smem + ii * (R::N * BE);
       constexpr int o = R::V ? R::oV : (R::HV ? R::oHV : R::oJV);
       double s0 = 0.0, s1 = 0.0;
@@ -1375,13 +1391,13 @@ __device__ void prod_tile(const Bufs& B, const InstOff& I0, const InstOff& I1, c
       }
       if constexpr (R::V || R::HV) {
         double* out = (R::V ? B.u : B.out) + xo[ii];
-        put(&out[i], CART ? s0 + own0[ii] : s0);
-        put(&out[nb + i], s1 + own1[ii]);
+        put(&out[i], CART ? s0 + own0 : s0);
+        put(&out[nb + i], s1 + own1);
       } else {
         double* out = B.out + co[ii];
-        put(&out[i], s0 + own0[ii]);
-        put(&out[nb + i], s1 + own1[ii]);
-        if constexpr (CART) put(&out[2 * nb + 2 * nll[ii] + i], own2[ii]);
+        put(&out[i], s0 + own0);
+        put(&out[nb + i], s1 + own1);
+        if constexpr (CART) put(&out[2 * nb + 2 * nll[ii] + i], own2);
       }
     }
   }
@@ -1496,7 +1512,7 @@ __global__ __launch_bounds__(256) void k_fsum(const InstOff* __restrict__ table,
 
 // ---------------------------------------------------------------------------
 
-// The products' kernel: bus tiles of one or two instances (prod_tile) and
+// The products' kernel: bus tiles of up to kProdInst instances (prod_tile) and
 // generator tiles, at the waves per SIMD their registers allow without
 // spilling: three for the HVP, four otherwise.
 template <unsigned WHAT>
@@ -1514,10 +1530,14 @@ void k_prod(Bufs B, const InstOff* __restrict__ table, InstOff one, const Tile* 
     const InstOff I = table ? table[T.inst] : one;
     const NetDev& N = *I.net;
     if ((T.kind_aux & 3) == TILE_BUS) {
-      if (T.inst2 >= 0)
-        prod_tile<WHAT, WG, BE, 2>(B, I, table[T.inst2], N, T, one.work, smem);
-      else
-        prod_tile<WHAT, WG, BE, 1>(B, I, I, N, T, one.work, smem);
+      if (T.more[0] >= 0) {
+        constexpr int G = prod_group(WHAT);
+        int ni = 2;
+        while (ni < G && T.more[ni - 1] >= 0) ++ni;
+        prod_tile<WHAT, WG, BE, G>(B, table, I, N, T, ni, one.work, smem);
+      } else {
+        prod_tile<WHAT, WG, BE, 1>(B, table, I, N, T, 1, one.work, smem);
+      }
     } else {
       gen_tile<WHAT, WG>(B, I, N, T.a0, T.a1, T.kind_aux >> 2, smem);
     }

@@ -340,3 +340,47 @@ def test_batch_xdot_matches_exact_sums(gpu_lib):
         prod = a[seg] * v[seg]
         want = math.fsum(prod)
         assert abs(got[k] - want) <= 1e-12 * np.abs(prod).sum(), (k, got[k], want)
+
+
+@pytest.mark.parametrize("form", ["polar", "cartesian"])
+def test_product_groups_bitwise(gpu_lib, form):
+    """The batched VJP, HVP and JVP group the instances of one base network
+    into shared product tiles (four at a time, the remainder in a smaller
+    group, a lone instance on its own).  Bases with 7, 3, 2 and 1 outage
+    children, interleaved in the batch, give groups of every size; every
+    instance's products equal its one-instance launch bit for bit."""
+    torch = _t()
+    from paper_2203_10587_amd import acopf as A
+    sets = [S.n1_security_set(s, nb=300, nl=450, count=n) for s, n in ((1, 7), (2, 3), (3, 2), (4, 1))]
+    kind = A.ACOPF_CARTESIAN if form == "cartesian" else A.ACOPF_POLAR
+    bases = [A.acopf_net_create_form(o.base, kind) for o in sets]
+    kids = [[A.acopf_net_create_outage(bn, int(l)) for l in o.outages] for bn, o in zip(bases, sets)]
+    nets = []
+    for j in range(max(len(k) for k in kids)):  # interleave the bases
+        nets += [k[j] for k in kids if j < len(k)]
+    b = A.acopf_batch_create(nets)
+    rng = np.random.default_rng(21)
+    nx, nc = int(b.x_off[-1]), int(b.c_off[-1])
+    dev = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64), device="cuda")
+    nan = lambda n: torch.full((int(n),), np.nan, dtype=torch.float64, device="cuda")
+    x = rng.uniform(0.9, 1.1, nx)
+    lam, wc, d = rng.standard_normal(nc), rng.standard_normal(nc), rng.standard_normal(nx)
+    wf, sig = rng.standard_normal(b.count), rng.uniform(0.5, 2.0, b.count)
+    u, hd, jd = nan(nx), nan(nx), nan(nc)
+    log(f"[groups] {form}: {b.count} instances")
+    A.acopf_batch_vjp(b, dev(x), dev(wf), dev(wc), u)
+    A.acopf_batch_hvp(b, dev(x), dev(sig), dev(lam), dev(d), hd)
+    A.acopf_batch_jvp(b, dev(x), dev(d), jd)
+    torch.cuda.synchronize()
+    u, hd, jd = u.cpu().numpy(), hd.cpu().numpy(), jd.cpu().numpy()
+    for k, net in enumerate(nets):
+        xs, cs = slice(int(b.x_off[k]), int(b.x_off[k + 1])), slice(int(b.c_off[k]), int(b.c_off[k + 1]))
+        u1, h1, j1 = nan(net.n), nan(net.n), nan(net.m)
+        A.acopf_vjp(net, dev(x[xs]), float(wf[k]), dev(wc[cs]), u1)
+        A.acopf_hvp(net, dev(x[xs]), float(sig[k]), dev(lam[cs]), dev(d[xs]), h1)
+        A.acopf_jvp(net, dev(x[xs]), dev(d[xs]), j1)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(u[xs], u1.cpu().numpy(), err_msg=f"vjp {k}")
+        np.testing.assert_array_equal(hd[xs], h1.cpu().numpy(), err_msg=f"hvp {k}")
+        np.testing.assert_array_equal(jd[cs], j1.cpu().numpy(), err_msg=f"jvp {k}")
+    b.close()
