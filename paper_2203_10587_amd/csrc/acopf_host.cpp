@@ -122,6 +122,16 @@ int build_topology(const acopf_net_desc* d, const acopf_net_opts* o, Topology* T
     Y.btt = bs + 0.5 * b;
     T->ft[l] = make_int2(f, t);
   }
+  T->y6.resize(nl);
+  T->tf.resize(nl);
+  T->shifted.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    const BranchY& Y = T->y[l];
+    T->y6[l] = BranchY6{Y.gff, Y.bff, Y.gft, Y.bft, Y.gtt, Y.btt};
+    T->tf[l] = make_double2(Y.gtf, Y.btf);
+    T->shifted[l] = (std::memcmp(&Y.gtf, &Y.gft, sizeof(double)) != 0 ||
+                     std::memcmp(&Y.btf, &Y.bft, sizeof(double)) != 0) ? 1 : 0;
+  }
   T->bus.resize(nb);
   for (int i = 0; i < nb; ++i) {
     const double v[4] = {d->bus_pd[i], d->bus_qd[i], d->bus_gs[i], d->bus_bs[i]};
@@ -455,7 +465,7 @@ int make_tiles(const Topology& T, int tile_be, Schedule* S) {
         }
         w.j = jlo | (jhi << 16);
         w.hv = hvlo | (hvhi << 16);
-        w.th = hthi | (uint32_t((m == k) ? g : 0) << 16);
+        w.th = hthi | (uint32_t((m == k) ? g : 0) << 16) | (uint32_t(T.shifted[l]) << 24);
         w.a = uint32_t(T.acnt[lo].x) | (uint32_t(T.acnt[hi].x) << 16);
         S->work.push_back(w);
       }
@@ -591,7 +601,7 @@ int upload_base(Base* B) {
     size_t off;
   };
   std::vector<Part> parts = {
-      {T.y.data(), T.y.size() * sizeof(BranchY), 0},
+      {T.y6.data(), T.y6.size() * sizeof(BranchY6), 0},
       {T.bus.data(), T.bus.size() * sizeof(double4), 0},
       {T.be_ptr.data(), T.be_ptr.size() * sizeof(int32_t), 0},
       {T.gen_ptr.data(), T.gen_ptr.size() * sizeof(int32_t), 0},
@@ -604,6 +614,7 @@ int upload_base(Base* B) {
       {B->plain.work.data(), B->plain.work.size() * sizeof(WorkItem), 0},
       {T.rows.data(), T.rows.size() * sizeof(int4), 0},
       {T.acnt.data(), T.acnt.size() * sizeof(int2), 0},
+      {T.tf.data(), T.tf.size() * sizeof(double2), 0},
       {nullptr, sizeof(NetDev), 0},
   };
   size_t total = 0;
@@ -629,7 +640,8 @@ int upload_base(Base* B) {
   nd.nl = T.nl;
   nd.ng = T.ng;
   nd.nchunks = T.nchunks;
-  nd.br_y = static_cast<const BranchY*>(at(0));
+  nd.br_y = static_cast<const BranchY6*>(at(0));
+  nd.br_tf = static_cast<const double2*>(at(13));
   nd.bus = static_cast<const double4*>(at(1));
   nd.be_ptr = static_cast<const int32_t*>(at(2));
   nd.gen_ptr = static_cast<const int32_t*>(at(3));
@@ -650,8 +662,8 @@ int upload_base(Base* B) {
   nd.sl = T.sl;
   B->d_tiles = static_cast<Tile*>(at(9));
   B->d_work = static_cast<WorkItem*>(at(10));
-  B->d_net = static_cast<NetDev*>(at(13));
-  parts[13].src = &nd;
+  B->d_net = static_cast<NetDev*>(at(14));
+  parts[14].src = &nd;
   for (const Part& p : parts) {
     if (p.bytes == 0) continue;
     e = hipMemcpy(base + p.off, p.src, p.bytes, hipMemcpyHostToDevice);

@@ -20,6 +20,9 @@ struct Topology {
   double base = 100.0;
   std::vector<int2> ft;
   std::vector<BranchY> y;
+  std::vector<BranchY6> y6;        // y without (gtf, btf)
+  std::vector<double2> tf;         // (gtf, btf)
+  std::vector<uint8_t> shifted;    // 1 where (gtf, btf) is not (gft, bft) bit for bit
   std::vector<double4> bus;
   std::vector<double> rate;       // apparent-power limit per branch (<= 0: none)
   std::vector<int32_t> gen_bus;

@@ -67,14 +67,15 @@ struct Tile {
 // a_e = |{e} u N(e)|, the length of the theta part of bus e's rows.
 // grp: for the first branch of a group of parallel branches, the group size
 // (1 for a branch without a twin); 0 for the other members, which follow in
-// the next lanes.
+// the next lanes.  shifted: the branch shifts phase, so the to side's
+// off-diagonal admittances differ from the from side's (NetDev::br_tf).
 constexpr uint32_t kNoPos = 0xFFFFu;
 struct WorkItem {
   int32_t l, f, t;
   uint32_t slots;
   uint32_t j;    // jlo | jhi << 16
   uint32_t hv;   // hvlo | hvhi << 16
-  uint32_t th;   // hthi | grp << 16
+  uint32_t th;   // hthi | grp << 16 | shifted << 24
   uint32_t a;    // alo | ahi << 16
   __host__ __device__ uint32_t jlo() const { return j & 0xFFFFu; }
   __host__ __device__ uint32_t jhi() const { return j >> 16; }
@@ -82,6 +83,7 @@ struct WorkItem {
   __host__ __device__ uint32_t hvhi() const { return hv >> 16; }
   __host__ __device__ uint32_t hthi() const { return th & 0xFFFFu; }
   __host__ __device__ int grp() const { return int((th >> 16) & 0xFFu); }
+  __host__ __device__ bool shifted() const { return ((th >> 24) & 1u) != 0; }
   __host__ __device__ uint32_t alo() const { return a & 0xFFFFu; }
   __host__ __device__ uint32_t ahi() const { return a >> 16; }
 };
@@ -102,9 +104,17 @@ struct BranchY {
   double gff, bff, gft, bft, gtf, btf, gtt, btt;
 };
 
+// What the kernels load per branch: BranchY without (gtf, btf), which equal
+// (gft, bft) unless the branch shifts phase; a shifting branch's pair is
+// kept apart (NetDev::br_tf) and read only by the lanes that need it.
+struct alignas(16) BranchY6 {
+  double gff, bff, gft, bft, gtt, btt;
+};
+
 struct NetDev {
   int32_t nb, nl, ng, nchunks;
-  const BranchY* br_y;      // [nl]
+  const BranchY6* br_y;     // [nl]
+  const double2* br_tf;     // [nl] (g_tf, b_tf), read for phase-shifting branches only
   const double4* bus;       // [nb] (pd, qd, gs, bs)
   const int32_t* be_ptr;    // [nb + 1] branch ends of bus i: adjacency positions be_ptr[i] ..
   const int32_t* gen_ptr;   // [nb + 1] generators at bus i: gen_list[gen_ptr[i] .. gen_ptr[i+1])

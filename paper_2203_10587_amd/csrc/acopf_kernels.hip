@@ -80,6 +80,19 @@ __device__ __forceinline__ void put_row4(double* p, bool al16, double a, double 
   }
 }
 
+// A branch's admittances: the 48-byte record, and for a phase-shifting
+// branch its to side's off-diagonal pair.
+__device__ __forceinline__ BranchY load_branch(const NetDev& N, const WorkItem& wi) {
+  const BranchY6 a = N.br_y[wi.l];
+  BranchY y{a.gff, a.bff, a.gft, a.bft, a.gft, a.bft, a.gtt, a.btt};
+  if (wi.shifted()) {
+    const double2 p = N.br_tf[wi.l];
+    y.gtf = p.x;
+    y.btf = p.y;
+  }
+  return y;
+}
+
 // ---------------------------------------------------------------------------
 // one branch: both end flows; first derivatives with respect to
 // (theta_f, v_f, v_t) are formed where they are used (members below)
@@ -372,7 +385,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       BrC b;
       int lp = 0;
       if (live) {
-        const BranchY y = N.br_y[l];
+        const BranchY y = load_branch(N, wi);
         branch_eval_cart(x[f], x[nb + f], x[t], x[nb + t], y, b);
         lp = l - after_outage(l, ol);
         if constexpr (pC) {
@@ -591,7 +604,7 @@ __device__ void bus_tile(const Bufs& B, const InstOff& I, const NetDev& N, const
       Br b;
       int lp = 0;
       if (live) {
-        const BranchY y = N.br_y[l];
+        const BranchY y = load_branch(N, wi);
         branch_eval(x[f], x[t], x[nb + f], x[nb + t], y, b);
         lp = l - after_outage(l, ol);
         if constexpr (pC) {
@@ -1087,7 +1100,7 @@ __device__ void prod_tile(const Bufs& B, const InstOff* __restrict__ table, cons
     const int l = wi.l, f = wi.f, t = wi.t;
     const uint32_t sf = wi.slots & 0xFFFFu, st = wi.slots >> 16;
     BranchY y{};
-    if (l >= 0) y = N.br_y[l];
+    if (l >= 0) y = load_branch(N, wi);
     // each instance's inputs are gathered just before its arithmetic:
     // gathering both instances' first holds both sets in registers, which
     // costs a wave per SIMD and measured slower in every product

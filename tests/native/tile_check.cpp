@@ -42,6 +42,9 @@ extern "C" int tile_check(const acopf_net_desc* d, int tile_be, unsigned slacks)
           wi.jlo() == kNoPos ? -1 : tl.hV0 + int(wi.hvlo()),
           wi.jhi() == kNoPos ? -1 : tl.hV0 + int(wi.hvhi()),
           wi.jhi() == kNoPos ? -1 : tl.hT0 + int(wi.hthi())};
+      chk(wi.shifted() == (T.shifted[wi.l] != 0), "shifted flag", ti, k);
+      chk(T.shifted[wi.l] != 0 || (T.y[wi.l].gtf == T.y[wi.l].gft && T.y[wi.l].btf == T.y[wi.l].bft),
+          "unshifted pair", ti, k);
       if (w.grp > 1) {  // members follow, same lo/hi, same wave
         chk(k / 64 == (k + w.grp - 1) / 64, "group straddles a wave", ti, k);
         for (int m = 1; m < w.grp; ++m) {
