@@ -276,7 +276,11 @@ class Server:
 
     def step(self) -> int:
         now = self.clock()
-        return self._retire(now) + self._admit(now)
+        n = self._retire(now)
+        t1 = self.clock()
+        n += self._admit(now)
+        self.last_step_s = (t1 - now, self.clock() - t1)  # retire; admit and launch
+        return n
 
     def idle(self) -> bool:
         return (not any(self.queues.values()) and not any(self.inflight.values())
@@ -288,14 +292,16 @@ class Server:
         """arrivals: (t_offset_s, grid, seed) sorted by time; requests enter at
         their scheduled time and latency runs from that time (open loop).
         Records every gap of more than STALL_S between two passes of the loop
-        (a stall: nothing is admitted or retired meanwhile) and every pause of
-        Python's garbage collector; with gc_off the collector is disabled for
-        the trace."""
+        (a stall: nothing is admitted or retired meanwhile), with the part of
+        the pass that took most of it (retiring, admitting and launching, or
+        neither: the arrivals' bookkeeping or time off the CPU), and every
+        pause of Python's garbage collector; with gc_off the collector is
+        disabled for the trace."""
         import gc
         t0 = self.clock()
         i = 0
         last_report = t0
-        stalls = []      # (start, length) of gaps between loop passes, s
+        stalls = []      # (start, length, where) of gaps between loop passes, s
         gc_pauses = []   # (start, length) of garbage collections, s
         gc_t = [0.0]
 
@@ -313,10 +319,14 @@ class Server:
         gc.callbacks.append(on_gc)
         try:
             prev = t0
+            self.last_step_s = (0.0, 0.0)
             while i < len(arrivals) or not self.idle():
                 now = self.clock()
                 if now - prev > STALL_S:
-                    stalls.append((prev - t0, now - prev))
+                    gap = now - prev
+                    rs, ad = self.last_step_s
+                    where = "retire" if rs > gap / 2 else ("admit" if ad > gap / 2 else "other")
+                    stalls.append((prev - t0, gap, where))
                 prev = now
                 while i < len(arrivals) and t0 + arrivals[i][0] <= now:
                     t, g, s = arrivals[i]
@@ -335,10 +345,15 @@ class Server:
                 if was_enabled:
                     gc.enable()
         st = self.stats(self.clock() - t0)
-        in_gc = sum(any(gs < s0 + sl and s0 < gs + gl for gs, gl in gc_pauses) for s0, sl in stalls)
+        in_gc = sum(any(gs < s0 + sl and s0 < gs + gl for gs, gl in gc_pauses)
+                    for s0, sl, _ in stalls)
         st["stalls"] = {"threshold_ms": STALL_S * 1e3, "count": len(stalls),
-                        "max_ms": max((sl for _, sl in stalls), default=0.0) * 1e3,
-                        "total_ms": sum(sl for _, sl in stalls) * 1e3,
+                        "max_ms": max((sl for _, sl, _ in stalls), default=0.0) * 1e3,
+                        "total_ms": sum(sl for _, sl, _ in stalls) * 1e3,
+                        "where": {w: sum(1 for *_, x in stalls if x == w)
+                                  for w in ("retire", "admit", "other")},
+                        "longest": [[round(s0, 3), round(sl * 1e3, 3), w]
+                                    for s0, sl, w in sorted(stalls, key=lambda z: -z[1])[:5]],
                         "overlapping_gc": in_gc,
                         "gc_pauses": len(gc_pauses),
                         "gc_max_ms": max((gl for _, gl in gc_pauses), default=0.0) * 1e3,

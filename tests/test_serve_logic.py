@@ -329,3 +329,49 @@ def test_run_trace_reports_stalls():
     assert st["stalls"]["count"] >= 1 and st["stalls"]["max_ms"] >= 4.0
     assert st["stalls"]["gc_off"] is True and st["stalls"]["gc_pauses"] == 0
     assert SV.STALL_S * 1e3 == st["stalls"]["threshold_ms"]
+
+
+def test_stalls_name_the_part_of_the_pass():
+    """A stall inside the launch call is attributed to admitting; one in the
+    completion poll to retiring; one between passes to neither."""
+
+    class TickClock(Clock):
+        def __call__(self):
+            self.t += 1e-5
+            return self.t
+
+    for where in ("admit", "retire", "other"):
+        clk = TickClock()
+
+        class Slow(FakeExecutor):
+            slowed = False
+
+            def launch(self, g, first, seeds):
+                if where == "admit" and not Slow.slowed:
+                    Slow.slowed = True
+                    clk.t += 0.004
+                return super().launch(g, first, seeds)
+
+            def done(self, h):
+                if where == "retire" and not Slow.slowed and self.calls:
+                    Slow.slowed = True
+                    clk.t += 0.004
+                return super().done(h)
+
+        ex = Slow(clk)
+        s = Server(ex, clock=clk)
+        tr = [(0.002 * k, k % 2, k) for k in range(20)]
+        if where == "other":
+            orig = s.submit
+
+            def submit(*a, **k):
+                if not getattr(s, "_slowed", False):
+                    s._slowed = True
+                    clk.t += 0.004
+                return orig(*a, **k)
+            s.submit = submit
+        st = s.run_trace(tr)
+        assert st["done"] == 20
+        long = [x for x in st["stalls"]["longest"] if x[1] >= 4.0]
+        assert long and long[0][2] == where, (where, st["stalls"])
+        assert st["stalls"]["where"][where] >= 1
