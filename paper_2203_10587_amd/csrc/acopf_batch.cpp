@@ -49,7 +49,7 @@ struct acopf_batch_s {
   int grid = 0;  // 0: one workgroup per tile
   acopf::Tile* d_tiles_inst = nullptr;  // the same tiles, instance after instance
   // product tiles: instances of one base in groups of kProdInst ([0]) or
-  // of two ([1]), as prod_group() gives per product
+  // of the JVP's size ([1]), as prod_group() gives per product
   acopf::Tile* d_ptiles[2] = {nullptr, nullptr};
   int nptiles[2] = {0, 0};
   acopf::WorkItem* d_work = nullptr;    // work items of every distinct base, back to back
@@ -389,7 +389,7 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
       }
       return interleave(pq);
     };
-    const std::vector<Tile> ptiles[2] = {product_tiles(kProdInst), product_tiles(2)};
+    const std::vector<Tile> ptiles[2] = {product_tiles(kProdInst), product_tiles(prod_group(W_JVP))};
     for (int q = 0; q < 2; ++q) b->nptiles[q] = int(ptiles[q].size());
     int cus = 256;
     int rc = cu_count(dev, &cus);

@@ -178,10 +178,10 @@ enum : unsigned {
 };
 
 // Instances of one base network per product bus tile: kProdInst for the VJP
-// and the HVP; two for the JVP, whose tiles of four need more registers than
-// four waves per SIMD leave (and measured slower than pairs).
+// and the HVP; three for the JVP, whose tiles of four need more registers
+// than four waves per SIMD leave.
 __host__ __device__ constexpr int prod_group(unsigned what) {
-  return (what & W_JVP) != 0 ? 2 : kProdInst;
+  return (what & W_JVP) != 0 ? 3 : kProdInst;
 }
 
 // Tile capacities of one schedule class (the schedule's tile_be value):

@@ -1309,7 +1309,7 @@ __device__ void prod_tile(const Bufs& B, const InstOff* __restrict__ table, cons
   // adjacency order.  The own terms of the first E instances are loaded
   // before the barrier (their loads overlap the wait), the others' after it,
   // one instance at a time: a tile of four holds one set across the barrier,
-  // a pair both.
+  // smaller tiles all of theirs.
   const bool has_bus = tid < nbus;
   const int i = b0 + tid;
   int ea = 0, eb = 0;
@@ -1373,7 +1373,7 @@ __device__ void prod_tile(const Bufs& B, const InstOff* __restrict__ table, cons
       o1 = jvQ;
     }
   };
-  constexpr int E = NI <= 2 ? NI : 1;
+  constexpr int E = NI <= 3 ? NI : 1;
   double f0[NI], f1[NI], f2[NI];  // own terms of the first E instances
 #pragma unroll
   for (int ii = 0; ii < NI; ++ii) f0[ii] = f1[ii] = f2[ii] = 0.0;
