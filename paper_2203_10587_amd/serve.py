@@ -298,6 +298,13 @@ class Server:
         pause of Python's garbage collector; with gc_off the collector is
         disabled for the trace."""
         import gc
+        # the collector is set up before the trace's clock starts: a full
+        # collection here would otherwise hold up the first arrivals
+        was_enabled = gc.isenabled()
+        if gc_off:
+            gc.collect()
+            gc.freeze()  # what exists now is never traversed again
+            gc.disable()
         t0 = self.clock()
         i = 0
         last_report = t0
@@ -311,11 +318,6 @@ class Server:
             else:
                 gc_pauses.append((gc_t[0] - t0, time.perf_counter() - gc_t[0]))
 
-        was_enabled = gc.isenabled()
-        if gc_off:
-            gc.collect()
-            gc.freeze()  # what exists now is never traversed again
-            gc.disable()
         gc.callbacks.append(on_gc)
         try:
             prev = t0

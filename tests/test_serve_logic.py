@@ -375,3 +375,37 @@ def test_stalls_name_the_part_of_the_pass():
         long = [x for x in st["stalls"]["longest"] if x[1] >= 4.0]
         assert long and long[0][2] == where, (where, st["stalls"])
         assert st["stalls"]["where"][where] >= 1
+
+
+def test_collector_setup_precedes_the_trace_clock(monkeypatch):
+    """With gc_off the full collection runs before the trace's clock starts,
+    so it is neither a stall nor part of any request's latency."""
+    import gc
+
+    class TickClock(Clock):
+        def __call__(self):
+            self.t += 1e-5
+            return self.t
+
+    real = gc.collect
+
+    def run(collect_s):
+        clk = TickClock()
+
+        def slow_collect(*a, **k):
+            clk.t += collect_s  # the collection's time on the trace's clock
+            return real(*a, **k)
+
+        monkeypatch.setattr(gc, "collect", slow_collect)
+        s = Server(FakeExecutor(clk), clock=clk)
+        st = s.run_trace([(0.0005 * k, k % 2, k) for k in range(20)], gc_off=True)
+        monkeypatch.setattr(gc, "collect", real)
+        assert st["done"] == 20
+        return st, [r.latency for r in s.requests]
+
+    st, slow = run(0.07)
+    assert st["stalls"]["count"] == 0, st["stalls"]
+    _, fast = run(0.0)
+    # (the same up to a clock tick or two; a collection on the trace clock
+    # would add its 70 ms to the first requests)
+    assert len(slow) == len(fast) and all(abs(a - b) <= 1e-3 for a, b in zip(slow, fast))
