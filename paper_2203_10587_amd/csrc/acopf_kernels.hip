@@ -1102,8 +1102,8 @@ __device__ void prod_tile(const Bufs& B, const InstOff* __restrict__ table, cons
     BranchY y{};
     if (l >= 0) y = load_branch(N, wi);
     // each instance's inputs are gathered just before its arithmetic:
-    // gathering both instances' first holds both sets in registers, which
-    // costs a wave per SIMD and measured slower in every product
+    // gathering every instance's first holds all the sets in registers,
+    // which costs a wave per SIMD and measured slower in every product
     bool live[NI];
     int lp[NI];
     double gx[NI][4], gm[NI][6], gd[NI][4];

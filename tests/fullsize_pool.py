@@ -38,6 +38,11 @@ def draw(model, k, g, it):
     return np.concatenate([it.x, rng.uniform(0.0, 0.05, 6 * g.nbus)]), it.lam, it.sigma
 
 
+def direction(k, n):
+    """The direction of the HVP and JVP of instance k (length n)."""
+    return np.random.default_rng([2204, k]).standard_normal(n)
+
+
 def _init(kind, model):
     from threadpoolctl import threadpool_limits
     from paper_2203_10587_amd import synth as S
@@ -55,8 +60,12 @@ def instance(kind, k, os_=None):
     return g, it
 
 
-def reference(model, g, x, lam, sigma, w=None):
-    """Oracle outputs, scales and patterns of one instance in a model."""
+def reference(model, g, x, lam, sigma, w=None, d=None):
+    """Oracle outputs, scales and patterns of one instance in a model; with
+    a direction d (polar), also H d and J d from the oracle's matrices, with
+    the scales of the product tests (J: the row scale times |d| summed over
+    the row's columns; H: the row's largest |entry| times the sum of |d| over
+    its columns)."""
     import oracle as O
     from oracle import cartesian as OC
     from oracle import slacks as OS
@@ -80,20 +89,32 @@ def reference(model, g, x, lam, sigma, w=None):
     ref = {"out": out, "scale": sc}
     if w is not None:
         ref["u"], ref["u_scale"] = vjp(*w)
+    if d is not None:
+        assert model == "polar"
+        J = O.jacobian_matrix(mdl, x)
+        H = O.hessian_matrix(mdl, x, sigma, lam)
+        sj = O.jacobian_row_scales(mdl, x, out["jac_val"])
+        rows = np.repeat(np.arange(mdl.m), np.diff(mdl.jac_rowptr))
+        ref["jd"] = J @ d
+        ref["jd_scale"] = np.bincount(rows, weights=sj * np.abs(d[mdl.jac_col]), minlength=mdl.m)
+        Habs = abs(H).tocsr()
+        ref["hd"] = H @ d
+        ref["hd_scale"] = Habs.max(axis=1).toarray().ravel() * ((Habs > 0).astype(float) @ np.abs(d))
     return ref, pat
 
 
 def check(item):
     """item = (k, gpu outputs dict, library CSR patterns or None, (w_f, w_c)
-    or None).  Returns (k, nbus, worst error/bound per output) or (k, nbus,
-    message) on a mismatch."""
+    or None, whether the outputs hold H d and J d along direction(k, n)).
+    Returns (k, nbus, worst error/bound per output) or (k, nbus, message) on
+    a mismatch."""
     from tests.parity import compare_outputs
-    k, got, pat, w = item
+    k, got, pat, w, prod = item
     kind, model = _W["kind"], _W["model"]
     g, it = instance(kind, k, _W.get("os"))
     x, lam, sigma = draw(model, k, g, it)
     try:
-        ref, opat = reference(model, g, x, lam, sigma, w)
+        ref, opat = reference(model, g, x, lam, sigma, w, direction(k, len(x)) if prod else None)
         if pat is not None:
             for name, a, b in zip(("jac_rowptr", "jac_col", "hess_rowptr", "hess_col"), pat, opat):
                 if not np.array_equal(np.asarray(a), np.asarray(b)):

@@ -52,4 +52,7 @@ def compare_outputs(tag, gpu, ref, tol=TOL):
             r[k] = assert_close(f"{tag}.{k}", gpu[k], out[k], sc[k], tol)
     if "u" in gpu:
         r["u"] = assert_close(tag + ".u", gpu["u"], ref["u"], ref["u_scale"], tol)
+    for k in ("hd", "jd"):  # H d and J d along a direction
+        if k in gpu:
+            r[k] = assert_close(f"{tag}.{k}", gpu[k], ref[k], ref[k + "_scale"], tol)
     return r

@@ -3,8 +3,9 @@
   * 1,000 N-1 outages of the 2,000-bus grid (paper: SCOPFLOW section, the
     single-period security-constrained problem), evaluated in one launch of
     the schedule the benchmark times: f, grad f, c, J, H and the VJP of every
-    instance, CSR patterns bit for bit; the same workload in the cartesian
-    formulation and with both slack blocks;
+    instance, CSR patterns bit for bit, and (polar) the batched HVP and JVP
+    of every instance along its own seeded direction; the same workload in
+    the cartesian formulation and with both slack blocks;
   * the 512 uneven scenario grids of 200..25,000 buses (paper: SOPFLOW
     section, one period): every instance's outputs and VJP, and directional
     central differences through AcopfBatchEval over the whole batch;
@@ -27,10 +28,11 @@ def _torch():
     return torch
 
 
-def _evaluate(A, nets, points, w=None):
+def _evaluate(A, nets, points, w=None, products=False):
     """Pack points [(x, lam, sigma)], evaluate every output of every instance
     in one launch of the tuned schedule (and the batched VJP with weights
-    w = (w_f, [w_c]) if given); host copies and the batch."""
+    w = (w_f, [w_c]) if given; with products, the batched HVP and JVP along
+    each instance's seeded direction); host copies and the batch."""
     from paper_2203_10587_amd import tune
     torch = _torch()
     sched = tune.lookup_or_default(nets)
@@ -55,6 +57,12 @@ def _evaluate(A, nets, points, w=None):
         u = nan(b.x_off[-1])
         A.acopf_batch_vjp(b, xt, d(w[0]), d(wc), u)
         host["u"] = u
+    if products:
+        dv = np.concatenate([FP.direction(k, int(b.x_off[k + 1] - b.x_off[k])) for k in range(K)])
+        hd, jd = nan(b.x_off[-1]), nan(b.c_off[-1])
+        A.acopf_batch_hvp(b, xt, st, lt, d(dv), hd)
+        A.acopf_batch_jvp(b, xt, d(dv), jd)
+        host["hd"], host["jd"] = hd, jd
     torch.cuda.synchronize()
     host = {k: v.cpu().numpy() for k, v in host.items()}
     for k, v in host.items():
@@ -64,14 +72,14 @@ def _evaluate(A, nets, points, w=None):
 
 def _items(b, host, nets, A, w=None, with_patterns=True):
     offs = {"grad_f": b.x_off, "c": b.c_off, "jac_val": b.j_off, "hess_val": b.h_off,
-            "u": b.x_off}
+            "u": b.x_off, "hd": b.x_off, "jd": b.c_off}
     for k in range(b.count):
         got = {"f": float(host["f"][k])}
         for key, o in offs.items():
             if key in host:
                 got[key] = host[key][int(o[k]):int(o[k + 1])]
         pat = A.acopf_pattern(nets[k]) if with_patterns else None
-        yield k, got, pat, (None if w is None else (float(w[0][k]), w[1][k]))
+        yield k, got, pat, (None if w is None else (float(w[0][k]), w[1][k])), "hd" in host
 
 
 def _report(tag, res, bad, count):
@@ -99,7 +107,7 @@ def test_n1_every_instance_polar(gpu_lib):
     rng = np.random.default_rng(21)
     w = (rng.standard_normal(len(nets)), [rng.standard_normal(it.lam.shape) for it in os_.iterates])
     pts = [(it.x, it.lam, it.sigma) for it in os_.iterates]
-    host, b = _evaluate(A, nets, pts, w)
+    host, b = _evaluate(A, nets, pts, w, products=True)
     res, bad = FP.check_all("n1", "polar", _items(b, host, nets, A, w))
     _report("n1 polar", res, bad, len(nets))
 
