@@ -298,18 +298,30 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
     std::iota(order.begin(), order.end(), 0);
     auto ntile = [&](int k) { return int(per_base[nets[k]->base.get()].sch.tiles.size()); };
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return ntile(a) > ntile(c); });
-    std::vector<std::vector<Tile>> queue(s.xcd_group ? kXcds : 1);
+    // A queue ends with its instances' generator chunks (a pure generator
+    // chunk is short work), so that the launch's last workgroups are short
+    // ones; slack chunks, which are not, stay with their instance.
+    auto short_tail = [](const Tile& t, int ng) {
+      return (t.kind_aux & 3) == TILE_GEN && t.a1 <= ng;
+    };
+    auto close_queues = [](std::vector<std::vector<Tile>>& qs, std::vector<std::vector<Tile>>& tails) {
+      for (size_t qi = 0; qi < qs.size(); ++qi)
+        qs[qi].insert(qs[qi].end(), tails[qi].begin(), tails[qi].end());
+    };
+    std::vector<std::vector<Tile>> queue(s.xcd_group ? kXcds : 1), qtail(queue.size());
     std::vector<int64_t> load(queue.size(), 0);
     for (int k : order) {
       const size_t qi = std::min_element(load.begin(), load.end()) - load.begin();
       const PerBase& pb = per_base[nets[k]->base.get()];
+      const int ng = nets[k]->base->topo.ng;
       for (Tile t : pb.sch.tiles) {
         t.inst = k;
         t.w0 += int32_t(pb.work_off);
-        queue[qi].push_back(t);
+        (short_tail(t, ng) ? qtail : queue)[qi].push_back(t);
       }
       load[qi] += ntile(k);
     }
+    close_queues(queue, qtail);
     std::vector<Tile> tiles_inst;
     b->inst_tile_off.assign(count + 1, 0);
     for (int k = 0; k < count; ++k) {
@@ -367,11 +379,12 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
       std::stable_sort(units.begin(), units.end(), [&](const Unit& a, const Unit& c) {
         return ntile(a.inst[0]) > ntile(c.inst[0]);
       });
-      std::vector<std::vector<Tile>> pq(s.xcd_group ? kXcds : 1);
+      std::vector<std::vector<Tile>> pq(s.xcd_group ? kXcds : 1), ptail(pq.size());
       std::vector<int64_t> pload(pq.size(), 0);
       for (const Unit& u : units) {
         const size_t qi = std::min_element(pload.begin(), pload.end()) - pload.begin();
         const PerBase& pb = per_base[nets[u.inst[0]]->base.get()];
+        const int ng = nets[u.inst[0]]->base->topo.ng;
         for (Tile t : pb.sch.tiles) {
           t.inst = u.inst[0];
           t.w0 += int32_t(pb.work_off);
@@ -381,12 +394,13 @@ int acopf_batch_create(const acopf_net* nets, int32_t count, const acopf_sched* 
           } else {
             for (int q = 0; q < u.n; ++q) {
               t.inst = u.inst[q];
-              pq[qi].push_back(t);
+              (short_tail(t, ng) ? ptail : pq)[qi].push_back(t);
             }
           }
         }
         pload[qi] += ntile(u.inst[0]);
       }
+      close_queues(pq, ptail);
       return interleave(pq);
     };
     const std::vector<Tile> ptiles[2] = {product_tiles(kProdInst), product_tiles(prod_group(W_JVP))};
