@@ -115,18 +115,29 @@ def test_batch_equals_plain_and_oracle(gpu_lib, small_n1):
 
 
 def test_schedules_bitwise_identical(gpu_lib, small_n1):
+    """Every schedule (tile class, persistent grid, XCD grouping, graph or
+    direct launch) gives the same bits, for the evaluation and for the
+    batched VJP, HVP and JVP."""
     from paper_2203_10587_amd import acopf as A
     from paper_2203_10587_amd import tune
-    os_, _, _ = small_n1
+    torch = _t()
+    os_, w_f, w_c = small_n1
     base, nets = _nets(A, os_)
     ref = None
     for cand in tune.CANDIDATES + [dict(tune.DEFAULT, no_graph=1)]:
         log(f"[schedule] {cand}")
         b = A.acopf_batch_create(nets, **cand)
-        P = Packed(A, b, os_.iterates)
+        P = Packed(A, b, os_.iterates, w_f, w_c)
         P.eval()
-        _t().cuda.synchronize()
-        outs = [P.instance(k) for k in (0, 17, 39)]
+        P.vjp()
+        nx, nc = int(b.x_off[-1]), int(b.c_off[-1])
+        d = torch.as_tensor(np.random.default_rng(3).standard_normal(nx), device="cuda")
+        hd = torch.full((nx,), np.nan, dtype=torch.float64, device="cuda")
+        jd = torch.full((nc,), np.nan, dtype=torch.float64, device="cuda")
+        A.acopf_batch_hvp(b, P.x, P.sigma, P.lam, d, hd)
+        A.acopf_batch_jvp(b, P.x, d, jd)
+        torch.cuda.synchronize()
+        outs = [P.instance(k) for k in (0, 17, 39)] + [{"hd": hd.cpu().numpy(), "jd": jd.cpu().numpy()}]
         if ref is None:
             ref = outs
         else:
