@@ -395,3 +395,42 @@ def test_product_groups_bitwise(gpu_lib, form):
         np.testing.assert_array_equal(hd[xs], h1.cpu().numpy(), err_msg=f"hvp {k}")
         np.testing.assert_array_equal(jd[cs], j1.cpu().numpy(), err_msg=f"jvp {k}")
     b.close()
+
+
+def test_product_graph_replays_match_eager(gpu_lib, small_n1):
+    """The batched VJP, HVP and JVP replayed from their captured graphs four
+    times, with eager launches and synchronisations in between: every replay
+    equals the direct launch bit for bit."""
+    from paper_2203_10587_amd import acopf as A
+    torch = _t()
+    os_, w_f, w_c = small_n1
+    base, nets = _nets(A, os_)
+
+    def run(b, P, d, out):
+        u, hd, jd = out
+        A.acopf_batch_vjp(b, P.x, P.wf, P.wc, u)
+        A.acopf_batch_hvp(b, P.x, P.sigma, P.lam, d, hd)
+        A.acopf_batch_jvp(b, P.x, d, jd)
+
+    eb = A.acopf_batch_create(nets, no_graph=1)
+    E = Packed(A, eb, os_.iterates, w_f, w_c)
+    nx, nc = int(eb.x_off[-1]), int(eb.c_off[-1])
+    d = torch.as_tensor(np.random.default_rng(9).standard_normal(nx), device="cuda")
+    nan = lambda n: torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+    eout = (nan(nx), nan(nx), nan(nc))
+    run(eb, E, d, eout)
+    torch.cuda.synchronize()
+    ref = [t.cpu().numpy() for t in eout]
+    gb = A.acopf_batch_create(nets)  # graph replay
+    G = Packed(A, gb, os_.iterates, w_f, w_c)
+    gout = (nan(nx), nan(nx), nan(nc))
+    for rep in range(4):
+        for t in gout:
+            t.fill_(np.nan)
+        run(gb, G, d, gout)
+        junk = torch.randn(1 << 20, dtype=torch.float64, device="cuda")
+        _ = (junk * 2.0).sum().item()
+        run(eb, E, d, eout)  # direct launches between the replays
+        torch.cuda.synchronize()
+        for name, got, want in zip(("vjp", "hvp", "jvp"), gout, ref):
+            np.testing.assert_array_equal(got.cpu().numpy(), want, err_msg=f"replay{rep}:{name}")
