@@ -434,3 +434,22 @@ def test_product_graph_replays_match_eager(gpu_lib, small_n1):
         torch.cuda.synchronize()
         for name, got, want in zip(("vjp", "hvp", "jvp"), gout, ref):
             np.testing.assert_array_equal(got.cpu().numpy(), want, err_msg=f"replay{rep}:{name}")
+
+
+def test_autotune_picks_one_of_its_candidates(gpu_lib, small_n1, tmp_path, monkeypatch):
+    """The autotuner (device warm-up, then every candidate timed) returns one
+    of its candidates and, with save=False, leaves the cache alone."""
+    from paper_2203_10587_amd import acopf as A
+    from paper_2203_10587_amd import tune
+    monkeypatch.setenv("ACOPF_TUNE_CACHE", str(tmp_path / "cache.json"))
+    monkeypatch.setattr(tune, "WARM_MS", 20.0)
+    os_, _, _ = small_n1
+    base, nets = _nets(A, os_)
+    b = A.acopf_batch_create(nets, no_graph=1)
+    P = Packed(A, b, os_.iterates)
+    cands = [dict(tune.DEFAULT, no_graph=1), dict(tune.DEFAULT, tile_be=128, no_graph=1)]
+    best = tune.autotune(nets, P.x, P.sigma, P.lam, [P.f, P.gf, P.c, P.jv, P.hv], reps=2,
+                         candidates=cands, save=False)
+    assert best in cands
+    assert not (tmp_path / "cache.json").exists()
+    b.close()
